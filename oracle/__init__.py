@@ -1,0 +1,130 @@
+"""Oracle for bitslice custom-precision floating point.
+
+TEST INFRASTRUCTURE ONLY: this package is used by ``tests/``, by the smoke
+check in ``__graft_entry__`` and by the CPU-baseline leg of ``bench.py``.  The
+GPU library and its Python binding never import it.
+
+The arithmetic lives in ``bfp_oracle.c`` (plain C, exact integers): decode to
+(sign, integer significand, exponent), compute the exact sum or product, round
+once to nearest-even or toward zero (Section 4 of the paper fixes the two
+modes; Table 1 the operations).  This module only marshals numpy arrays.
+"""
+from __future__ import annotations
+
+import ctypes
+import os
+import subprocess
+
+import numpy as np
+
+_HERE = os.path.dirname(os.path.abspath(__file__))
+_SRC = os.path.join(_HERE, "bfp_oracle.c")
+_LIB = os.path.join(_HERE, "liboracle.so")
+
+ADD, SUB, MUL = 0, 1, 2
+RNE, RZ = 0, 1
+OPS = {"add": ADD, "sub": SUB, "mul": MUL}
+
+
+def build(force: bool = False) -> str:
+    """Compile the oracle with gcc (-O2, no fast-math)."""
+    if force or not os.path.exists(_LIB) or os.path.getmtime(_LIB) < os.path.getmtime(_SRC):
+        tmp = _LIB + ".tmp%d" % os.getpid()
+        subprocess.check_call(
+            ["gcc", "-O2", "-std=c11", "-Wall", "-Wextra", "-fPIC", "-shared", "-pthread",
+             _SRC, "-o", tmp])
+        os.replace(tmp, _LIB)
+    return _LIB
+
+
+_lib = None
+
+
+def lib():
+    global _lib
+    if _lib is None:
+        build()
+        L = ctypes.CDLL(_LIB)
+        u32, i32, u64 = ctypes.c_uint32, ctypes.c_int, ctypes.c_uint64
+        vp = ctypes.c_void_p
+        L.oracle_op1.restype = u32
+        L.oracle_op1.argtypes = [i32, i32, i32, i32, u32, u32]
+        L.oracle_from_double.restype = u32
+        L.oracle_from_double.argtypes = [i32, i32, i32, ctypes.c_double]
+        L.oracle_binop.restype = i32
+        L.oracle_binop.argtypes = [i32, i32, i32, i32, vp, vp, vp, u64, i32]
+        L.oracle_pack.restype = i32
+        L.oracle_pack.argtypes = [i32, i32, vp, vp, u64, u64]
+        L.oracle_unpack.restype = i32
+        L.oracle_unpack.argtypes = [i32, i32, vp, vp, u64, u64]
+        _lib = L
+    return _lib
+
+
+def _op(op) -> int:
+    return OPS[op] if isinstance(op, str) else int(op)
+
+
+def op1(op, e: int, m: int, mode: int, a: int, b: int) -> int:
+    """One element: pattern of a op b."""
+    r = lib().oracle_op1(_op(op), e, m, mode, a, b)
+    if r == 0xFFFFFFFF:
+        raise ValueError("invalid oracle arguments")
+    return int(r)
+
+
+def binop(op, e: int, m: int, mode: int, a, b, nthreads: int = 1) -> np.ndarray:
+    """Elementwise a op b over arrays of patterns (any unsigned container)."""
+    a32 = np.ascontiguousarray(np.asarray(a).astype(np.uint32))
+    b32 = np.ascontiguousarray(np.asarray(b).astype(np.uint32))
+    if a32.shape != b32.shape:
+        raise ValueError("shape mismatch")
+    c = np.empty_like(a32)
+    rc = lib().oracle_binop(_op(op), e, m, mode, a32.ctypes.data, b32.ctypes.data,
+                            c.ctypes.data, a32.size, nthreads)
+    if rc != 0:
+        raise ValueError("invalid oracle arguments")
+    return c
+
+
+def from_double(e: int, m: int, mode: int, v: float) -> int:
+    return int(lib().oracle_from_double(e, m, mode, float(v)))
+
+
+def container_bytes(e: int, m: int) -> int:
+    B = 1 + e + m
+    return 1 if B <= 8 else (2 if B <= 16 else 4)
+
+
+def plane_stride_words(n: int) -> int:
+    """32-bit words per plane: ceil(n/32) rounded up to a multiple of 64."""
+    g = (n + 31) // 32
+    return (g + 63) // 64 * 64
+
+
+def pack(e: int, m: int, x, gpad: int | None = None) -> np.ndarray:
+    """Standard containers -> bitslice planes, shape (B, gpad) uint32."""
+    B = 1 + e + m
+    c = container_bytes(e, m)
+    dt = {1: np.uint8, 2: np.uint16, 4: np.uint32}[c]
+    xs = np.ascontiguousarray(np.asarray(x).astype(dt))
+    n = xs.size
+    gpad = plane_stride_words(n) if gpad is None else gpad
+    planes = np.empty((B, gpad), dtype=np.uint32)
+    if lib().oracle_pack(B, c, xs.ctypes.data, planes.ctypes.data, n, gpad) != 0:
+        raise ValueError("invalid pack arguments")
+    return planes
+
+
+def unpack(e: int, m: int, planes, n: int) -> np.ndarray:
+    """Bitslice planes (B, gpad) -> standard containers (uint8/16/32)."""
+    B = 1 + e + m
+    c = container_bytes(e, m)
+    dt = {1: np.uint8, 2: np.uint16, 4: np.uint32}[c]
+    p = np.ascontiguousarray(np.asarray(planes, dtype=np.uint32))
+    if p.shape[0] != B:
+        raise ValueError("plane count mismatch")
+    out = np.empty(n, dtype=dt)
+    if lib().oracle_unpack(B, c, p.ctypes.data, out.ctypes.data, n, p.shape[1]) != 0:
+        raise ValueError("invalid unpack arguments")
+    return out

@@ -1,0 +1,385 @@
+/*
+ * bfp_oracle.c -- reference arithmetic for custom-precision floating point
+ * (1 sign bit, e exponent bits, m mantissa bits) and for the standard <->
+ * bitslice layout transforms.
+ *
+ * TEST INFRASTRUCTURE ONLY. This file is the oracle: the tests, the smoke
+ * check and the CPU-baseline leg of the benchmark call it; the GPU library
+ * never does, and it shares no code with the GPU library.
+ *
+ * Method (plain definition, no circuit): decode each operand to an exact
+ * (sign, integer significand, power-of-two exponent), form the exact sum or
+ * product with wide unsigned integers, and round once.  The paper fixes the
+ * two rounding modes (Section 4: round toward zero, and round to nearest with
+ * ties to even) and the three arithmetic operations (Section 4, Table 1:
+ * add/sub, mul; div is not built here).  Everything the paper leaves open
+ * (bias, subnormals, infinities and NaN, overflow, the sign of an exact zero,
+ * NaN output bits) follows IEEE 754-2008 binary interchange semantics
+ * generalised to (e, m); each such reading is listed in the design notes.
+ *
+ * Wide integers: exact sums need at most 2^e - 3 + m + 2 <= 278 bits for
+ * e <= 8, m <= 23, so a fixed 384-bit unsigned integer (six 64-bit limbs,
+ * least significant first) is enough; products need at most 48 bits.
+ */
+#include <stdint.h>
+#include <stdlib.h>
+#include <string.h>
+#include <pthread.h>
+
+#define ORACLE_RNE 0
+#define ORACLE_RZ 1
+#define ORACLE_ADD 0
+#define ORACLE_SUB 1
+#define ORACLE_MUL 2
+
+/* ------------------------------------------------------------------------ */
+/* 384-bit unsigned integers                                                 */
+/* ------------------------------------------------------------------------ */
+#define NLIMB 6
+typedef struct { uint64_t w[NLIMB]; } big;
+
+static big big_from_u64(uint64_t v) {
+    big r;
+    memset(&r, 0, sizeof r);
+    r.w[0] = v;
+    return r;
+}
+
+static int big_cmp(const big *a, const big *b) {
+    for (int i = NLIMB - 1; i >= 0; i--) {
+        if (a->w[i] > b->w[i]) return 1;
+        if (a->w[i] < b->w[i]) return -1;
+    }
+    return 0;
+}
+
+/* a << s, s < 384; the operands used here never overflow 384 bits. */
+static big big_shl(const big *a, int s) {
+    big r;
+    memset(&r, 0, sizeof r);
+    int limb = s / 64, bit = s % 64;
+    for (int i = NLIMB - 1; i >= 0; i--) {
+        int src = i - limb;
+        if (src < 0) continue;
+        uint64_t v = a->w[src] << bit;
+        if (bit && src - 1 >= 0) v |= a->w[src - 1] >> (64 - bit);
+        r.w[i] = v;
+    }
+    return r;
+}
+
+/* a >> s */
+static big big_shr(const big *a, int s) {
+    big r;
+    memset(&r, 0, sizeof r);
+    int limb = s / 64, bit = s % 64;
+    for (int i = 0; i < NLIMB; i++) {
+        int src = i + limb;
+        if (src >= NLIMB) continue;
+        uint64_t v = a->w[src] >> bit;
+        if (bit && src + 1 < NLIMB) v |= a->w[src + 1] << (64 - bit);
+        r.w[i] = v;
+    }
+    return r;
+}
+
+static big big_add(const big *a, const big *b) {
+    big r;
+    uint64_t carry = 0;
+    for (int i = 0; i < NLIMB; i++) {
+        uint64_t s = a->w[i] + b->w[i];
+        uint64_t c1 = s < a->w[i];
+        uint64_t t = s + carry;
+        uint64_t c2 = t < s;
+        r.w[i] = t;
+        carry = c1 | c2;
+    }
+    return r;
+}
+
+/* a - b, requires a >= b */
+static big big_sub(const big *a, const big *b) {
+    big r;
+    uint64_t borrow = 0;
+    for (int i = 0; i < NLIMB; i++) {
+        uint64_t d = a->w[i] - b->w[i];
+        uint64_t b1 = a->w[i] < b->w[i];
+        uint64_t t = d - borrow;
+        uint64_t b2 = d < borrow;
+        r.w[i] = t;
+        borrow = b1 | b2;
+    }
+    return r;
+}
+
+/* number of significant bits; 0 for zero */
+static int big_bitlen(const big *a) {
+    for (int i = NLIMB - 1; i >= 0; i--) {
+        if (a->w[i]) {
+            int n = 64;
+            while (!((a->w[i] >> (n - 1)) & 1)) n--;
+            return i * 64 + n;
+        }
+    }
+    return 0;
+}
+
+/* ------------------------------------------------------------------------ */
+/* Number model                                                              */
+/* ------------------------------------------------------------------------ */
+enum { CLS_ZERO, CLS_FINITE, CLS_INF, CLS_NAN };
+
+typedef struct {
+    int s;         /* sign bit */
+    uint64_t sig;  /* integer significand */
+    int q;         /* value = (-1)^s * sig * 2^q */
+    int cls;
+} decoded;
+
+static int bias_of(int e) { return (1 << (e - 1)) - 1; }
+
+/* Field layout of a pattern x (low 1+e+m bits): mantissa in bits [0,m),
+ * exponent in bits [m,m+e), sign in bit m+e. */
+static decoded decode(uint32_t x, int e, int m) {
+    decoded d;
+    uint32_t M = x & ((1u << m) - 1u);
+    uint32_t E = (x >> m) & ((1u << e) - 1u);
+    d.s = (int)((x >> (e + m)) & 1u);
+    d.sig = 0;
+    d.q = 0;
+    if (E == (1u << e) - 1u) {
+        d.cls = M ? CLS_NAN : CLS_INF;
+    } else if (E == 0) {
+        d.sig = M;
+        d.q = 1 - bias_of(e) - m;
+        d.cls = M ? CLS_FINITE : CLS_ZERO;
+    } else {
+        d.sig = (1ull << m) + M;
+        d.q = (int)E - bias_of(e) - m;
+        d.cls = CLS_FINITE;
+    }
+    return d;
+}
+
+static uint32_t encode(int s, uint32_t E, uint32_t M, int e, int m) {
+    return ((uint32_t)s << (e + m)) | (E << m) | M;
+}
+
+static uint32_t canonical_nan(int e, int m) {
+    return encode(0, (1u << e) - 1u, 1u << (m - 1), e, m);
+}
+
+static uint32_t infinity(int s, int e, int m) {
+    return encode(s, (1u << e) - 1u, 0, e, m);
+}
+
+/* Round (-1)^s * S * 2^q0 (S > 0) once to the format. */
+static uint32_t round_exact(int s, const big *S, int q0, int e, int m, int mode) {
+    int bias = bias_of(e);
+    int L = big_bitlen(S);
+    /* ulp exponent of the result: normal ulp, clamped at the subnormal ulp */
+    int top = q0 + L - 1;
+    int qt = (top > 1 - bias ? top : 1 - bias) - m;
+    uint64_t sig;
+    if (qt <= q0) {
+        big t = big_shl(S, q0 - qt); /* exact, fits in m+1 bits */
+        sig = t.w[0];
+    } else {
+        int sh = qt - q0;
+        big t = big_shr(S, sh);
+        sig = t.w[0];
+        big back = big_shl(&t, sh);
+        big rem = big_sub(S, &back);
+        big one = big_from_u64(1);
+        big half = big_shl(&one, sh - 1);
+        if (mode == ORACLE_RNE) {
+            int c = big_cmp(&rem, &half);
+            if (c > 0 || (c == 0 && (sig & 1u))) sig += 1;
+        }
+    }
+    if (sig == (1ull << (m + 1))) { /* rounding carried into a new bit */
+        sig >>= 1;
+        qt += 1;
+    }
+    uint32_t E, M;
+    if (sig < (1ull << m)) { /* subnormal (or zero), qt is the subnormal ulp */
+        E = 0;
+        M = (uint32_t)sig;
+    } else {
+        long Ev = (long)qt + m + bias;
+        if (Ev >= (1L << e) - 1) { /* overflow */
+            if (mode == ORACLE_RNE) return infinity(s, e, m);
+            return encode(s, (1u << e) - 2u, (1u << m) - 1u, e, m);
+        }
+        E = (uint32_t)Ev;
+        M = (uint32_t)(sig - (1ull << m));
+    }
+    return encode(s, E, M, e, m);
+}
+
+/* ------------------------------------------------------------------------ */
+/* Operations                                                                */
+/* ------------------------------------------------------------------------ */
+static uint32_t op_add(uint32_t a, uint32_t b, int e, int m, int mode) {
+    decoded x = decode(a, e, m), y = decode(b, e, m);
+    if (x.cls == CLS_NAN || y.cls == CLS_NAN) return canonical_nan(e, m);
+    if (x.cls == CLS_INF && y.cls == CLS_INF)
+        return x.s == y.s ? infinity(x.s, e, m) : canonical_nan(e, m);
+    if (x.cls == CLS_INF) return infinity(x.s, e, m);
+    if (y.cls == CLS_INF) return infinity(y.s, e, m);
+    if (x.cls == CLS_ZERO && y.cls == CLS_ZERO)
+        return encode(x.s == y.s ? x.s : 0, 0, 0, e, m);
+    int q0 = x.q < y.q ? x.q : y.q;
+    big A0 = big_from_u64(x.sig), B0 = big_from_u64(y.sig);
+    big A = big_shl(&A0, x.q - q0);
+    big B = big_shl(&B0, y.q - q0);
+    big S;
+    int s;
+    if (x.s == y.s) {
+        S = big_add(&A, &B);
+        s = x.s;
+    } else {
+        int c = big_cmp(&A, &B);
+        if (c == 0) return encode(0, 0, 0, e, m); /* exact cancellation: +0 */
+        if (c > 0) {
+            S = big_sub(&A, &B);
+            s = x.s;
+        } else {
+            S = big_sub(&B, &A);
+            s = y.s;
+        }
+    }
+    return round_exact(s, &S, q0, e, m, mode);
+}
+
+static uint32_t op_mul(uint32_t a, uint32_t b, int e, int m, int mode) {
+    decoded x = decode(a, e, m), y = decode(b, e, m);
+    int s = x.s ^ y.s;
+    if (x.cls == CLS_NAN || y.cls == CLS_NAN) return canonical_nan(e, m);
+    if (x.cls == CLS_INF || y.cls == CLS_INF) {
+        if (x.cls == CLS_ZERO || y.cls == CLS_ZERO) return canonical_nan(e, m);
+        return infinity(s, e, m);
+    }
+    if (x.cls == CLS_ZERO || y.cls == CLS_ZERO) return encode(s, 0, 0, e, m);
+    big S = big_from_u64(x.sig * y.sig); /* < 2^48 */
+    return round_exact(s, &S, x.q + y.q, e, m, mode);
+}
+
+static int format_ok(int e, int m) { return e >= 2 && e <= 8 && m >= 1 && m <= 23; }
+
+/* One element.  op: 0 add, 1 sub, 2 mul.  mode: 0 RNE, 1 RZ.
+ * Returns the result pattern, or 0xFFFFFFFF for an invalid argument. */
+uint32_t oracle_op1(int op, int e, int m, int mode, uint32_t a, uint32_t b) {
+    if (!format_ok(e, m) || (mode != ORACLE_RNE && mode != ORACLE_RZ)) return 0xFFFFFFFFu;
+    uint32_t mask = (uint32_t)((1ull << (1 + e + m)) - 1u);
+    a &= mask;
+    b &= mask;
+    switch (op) {
+    case ORACLE_ADD: return op_add(a, b, e, m, mode);
+    case ORACLE_SUB: return op_add(a, b ^ (1u << (e + m)), e, m, mode); /* a + (-b) */
+    case ORACLE_MUL: return op_mul(a, b, e, m, mode);
+    default: return 0xFFFFFFFFu;
+    }
+}
+
+/* Round a binary64 value once to the format (used to build expected values
+ * for pins, never by the GPU path). */
+uint32_t oracle_from_double(int e, int m, int mode, double v) {
+    if (!format_ok(e, m)) return 0xFFFFFFFFu;
+    uint64_t bits;
+    memcpy(&bits, &v, sizeof bits);
+    int s = (int)(bits >> 63);
+    int E = (int)((bits >> 52) & 0x7FF);
+    uint64_t F = bits & ((1ull << 52) - 1);
+    if (E == 0x7FF) return F ? canonical_nan(e, m) : infinity(s, e, m);
+    if (E == 0 && F == 0) return encode(s, 0, 0, e, m);
+    uint64_t sig = E ? (F | (1ull << 52)) : F;
+    int q = (E ? E : 1) - 1023 - 52;
+    big S = big_from_u64(sig);
+    return round_exact(s, &S, q, e, m, mode);
+}
+
+/* ------------------------------------------------------------------------ */
+/* Vector driver with optional threads                                       */
+/* ------------------------------------------------------------------------ */
+typedef struct {
+    int op, e, m, mode;
+    const uint32_t *a, *b;
+    uint32_t *c;
+    uint64_t lo, hi;
+} job;
+
+static void *run_job(void *p) {
+    job *j = (job *)p;
+    for (uint64_t i = j->lo; i < j->hi; i++)
+        j->c[i] = oracle_op1(j->op, j->e, j->m, j->mode, j->a[i], j->b[i]);
+    return NULL;
+}
+
+/* Elementwise c[i] = a[i] op b[i] on patterns held in uint32 words.
+ * Returns 0, or -1 for an invalid argument. */
+int oracle_binop(int op, int e, int m, int mode, const uint32_t *a, const uint32_t *b,
+                 uint32_t *c, uint64_t n, int nthreads) {
+    if (!format_ok(e, m) || op < 0 || op > 2 || (mode != 0 && mode != 1)) return -1;
+    if (nthreads < 1) nthreads = 1;
+    if (nthreads > 256) nthreads = 256;
+    if ((uint64_t)nthreads > n) nthreads = n ? (int)n : 1;
+    job jobs[256];
+    pthread_t tids[256];
+    uint64_t chunk = (n + nthreads - 1) / nthreads;
+    for (int t = 0; t < nthreads; t++) {
+        uint64_t lo = chunk * t, hi = lo + chunk;
+        if (lo > n) lo = n;
+        if (hi > n) hi = n;
+        jobs[t] = (job){op, e, m, mode, a, b, c, lo, hi};
+    }
+    if (nthreads == 1) {
+        run_job(&jobs[0]);
+        return 0;
+    }
+    for (int t = 0; t < nthreads; t++) pthread_create(&tids[t], NULL, run_job, &jobs[t]);
+    for (int t = 0; t < nthreads; t++) pthread_join(tids[t], NULL);
+    return 0;
+}
+
+/* ------------------------------------------------------------------------ */
+/* Layout transforms (Section 2, Figure 1; Section 4 helper transforms)       */
+/* ------------------------------------------------------------------------ */
+/* Bitslice layout: plane k (0 <= k < B) holds bit k of every element's
+ * standard pattern; element i sits in word i / 32 of the plane at bit
+ * i % 32.  Planes are gpad 32-bit words apart. */
+static uint32_t load_container(const void *x, int cbytes, uint64_t i) {
+    if (cbytes == 1) return ((const uint8_t *)x)[i];
+    if (cbytes == 2) return ((const uint16_t *)x)[i];
+    return ((const uint32_t *)x)[i];
+}
+
+static void store_container(void *x, int cbytes, uint64_t i, uint32_t v) {
+    if (cbytes == 1) ((uint8_t *)x)[i] = (uint8_t)v;
+    else if (cbytes == 2) ((uint16_t *)x)[i] = (uint16_t)v;
+    else ((uint32_t *)x)[i] = v;
+}
+
+int oracle_pack(int B, int cbytes, const void *x, uint32_t *planes, uint64_t n, uint64_t gpad) {
+    if (B < 1 || B > 32 || B > 8 * cbytes || (cbytes != 1 && cbytes != 2 && cbytes != 4)) return -1;
+    if (gpad * 32 < n) return -1;
+    memset(planes, 0, (size_t)B * gpad * sizeof(uint32_t));
+    for (uint64_t i = 0; i < n; i++) {
+        uint32_t v = load_container(x, cbytes, i);
+        for (int k = 0; k < B; k++)
+            if ((v >> k) & 1u) planes[(uint64_t)k * gpad + i / 32] |= 1u << (i % 32);
+    }
+    return 0;
+}
+
+int oracle_unpack(int B, int cbytes, const uint32_t *planes, void *x, uint64_t n, uint64_t gpad) {
+    if (B < 1 || B > 32 || B > 8 * cbytes || (cbytes != 1 && cbytes != 2 && cbytes != 4)) return -1;
+    if (gpad * 32 < n) return -1;
+    for (uint64_t i = 0; i < n; i++) {
+        uint32_t v = 0;
+        for (int k = 0; k < B; k++)
+            if ((planes[(uint64_t)k * gpad + i / 32] >> (i % 32)) & 1u) v |= 1u << k;
+        store_container(x, cbytes, i, v);
+    }
+    return 0;
+}

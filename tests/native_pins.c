@@ -1,0 +1,62 @@
+/* Native IEEE arithmetic on the host CPU, used to pin the oracle at the
+ * formats that hardware implements: (8,23) = binary32 and (5,10) = binary16.
+ * Test helper only.  Built with gcc -frounding-math, no fast-math, and with
+ * the SSE flush-to-zero / denormals-are-zero bits cleared while it runs. */
+#include <fenv.h>
+#include <stdint.h>
+#include <string.h>
+#include <stddef.h>
+#include <immintrin.h>
+
+#pragma STDC FENV_ACCESS ON
+
+static unsigned clear_ftz_daz(void) {
+    unsigned old = _mm_getcsr();
+    _mm_setcsr(old & ~((1u << 15) | (1u << 6)));
+    return old;
+}
+
+/* op: 0 add, 1 sub, 2 mul; mode: 0 nearest-even, 1 toward zero */
+void f32_binop(int op, int mode, const uint32_t *a, const uint32_t *b, uint32_t *c, size_t n) {
+    unsigned csr = clear_ftz_daz();
+    int old = fegetround();
+    fesetround(mode == 0 ? FE_TONEAREST : FE_TOWARDZERO);
+    for (size_t i = 0; i < n; i++) {
+        volatile float x, y, r;
+        float tx, ty;
+        memcpy(&tx, &a[i], 4);
+        memcpy(&ty, &b[i], 4);
+        x = tx;
+        y = ty;
+        if (op == 0) r = x + y;
+        else if (op == 1) r = x - y;
+        else r = x * y;
+        float tr = r;
+        memcpy(&c[i], &tr, 4);
+    }
+    fesetround(old);
+    _mm_setcsr(csr);
+}
+
+/* binary16 toward zero: binary16 operands are exact in double, and a sum or
+ * product of two of them is exact in double (at most 40 significant bits);
+ * double -> float under FE_TOWARDZERO and float -> half with the F16C
+ * truncating conversion round toward zero twice on nested grids, which equals
+ * one rounding toward zero. */
+void f16_binop_rz(int op, const uint16_t *a, const uint16_t *b, uint16_t *c, size_t n) {
+    unsigned csr = clear_ftz_daz();
+    int old = fegetround();
+    for (size_t i = 0; i < n; i++) {
+        float fa = _cvtsh_ss(a[i]);
+        float fb = _cvtsh_ss(b[i]);
+        volatile double x = fa, y = fb, r;
+        if (op == 0) r = x + y;
+        else if (op == 1) r = x - y;
+        else r = x * y;
+        fesetround(FE_TOWARDZERO);
+        volatile float rf = (float)r;
+        fesetround(old);
+        c[i] = _cvtss_sh(rf, _MM_FROUND_TO_ZERO | _MM_FROUND_NO_EXC);
+    }
+    _mm_setcsr(csr);
+}

@@ -1,0 +1,98 @@
+"""The pins must catch plausible mistakes in the oracle.
+
+Each mutant is a copy of ``oracle/bfp_oracle.c`` with one planted mistake
+(a dropped term, a wrong sign, an off-by-one, a wrong tie rule ...), built in
+a temporary directory.  The planted copy must disagree with the exact model
+(exhaustive on small formats) or with the hand-derived golden cases.  The
+committed oracle itself is never modified."""
+import ctypes
+import os
+import subprocess
+
+import numpy as np
+import pytest
+
+from tests.exact_model import Fmt, check_correctly_rounded, table_round, tables
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+SRC = os.path.join(ROOT, "oracle", "bfp_oracle.c")
+
+MUTANTS = [
+    ("tie ignores evenness", "(c == 0 && (sig & 1u))", "(c == 0)"),
+    ("rounds up on any remainder", "if (c > 0 || (c == 0 && (sig & 1u))) sig += 1;",
+     "if (c >= 0 || (c == 0 && (sig & 1u))) sig += 1;"),
+    ("cancellation keeps sign", "return encode(0, 0, 0, e, m); /* exact", "return encode(x.s, 0, 0, e, m); /* exact"),
+    ("overflow threshold off by one", "if (Ev >= (1L << e) - 1)", "if (Ev > (1L << e) - 1)"),
+    ("no subnormal clamp", "int qt = (top > 1 - bias ? top : 1 - bias) - m;", "int qt = top - m;"),
+    ("subnormal exponent off by one", "d.q = 1 - bias_of(e) - m;", "d.q = 0 - bias_of(e) - m;"),
+    ("RZ overflow gives Inf", "if (mode == ORACLE_RNE) return infinity(s, e, m);", "return infinity(s, e, m);"),
+    ("carry renormalisation dropped", "sig >>= 1;\n        qt += 1;", "qt += 0;"),
+    ("mul sign not xor", "int s = x.s ^ y.s;", "int s = x.s;"),
+    ("sub does not negate", "return op_add(a, b ^ (1u << (e + m)), e, m, mode);", "return op_add(a, b, e, m, mode);"),
+    ("inf*0 not NaN", "if (x.cls == CLS_ZERO || y.cls == CLS_ZERO) return canonical_nan(e, m);", ""),
+    ("wrong bias", "static int bias_of(int e) { return (1 << (e - 1)) - 1; }",
+     "static int bias_of(int e) { return (1 << (e - 1)); }"),
+    ("borrow dropped in sub", "borrow = b1 | b2;", "borrow = b1;"),
+    ("min exponent alignment", "int q0 = x.q < y.q ? x.q : y.q;", "int q0 = x.q > y.q ? y.q : y.q + 1;"),
+]
+
+
+def _build(tmp_path, src_text, name):
+    c = tmp_path / (name + ".c")
+    c.write_text(src_text)
+    so = tmp_path / (name + ".so")
+    subprocess.check_call(["gcc", "-O1", "-fPIC", "-shared", "-pthread", "-w", str(c), "-o", str(so)])
+    L = ctypes.CDLL(str(so))
+    L.oracle_binop.restype = ctypes.c_int
+    L.oracle_binop.argtypes = [ctypes.c_int] * 4 + [ctypes.c_void_p] * 3 + [ctypes.c_uint64, ctypes.c_int]
+    return L
+
+
+def _wide_gap_pairs():
+    """(8,23) pairs whose exact sums span several 64-bit limbs: a power of two
+    (or a value just above one) minus a value 60..200 binades smaller."""
+    rng = np.random.default_rng(3)
+    ea = rng.integers(200, 254, 64)
+    gap = rng.integers(60, 200, 64)
+    a = (ea << 23) | rng.integers(0, 2, 64)
+    b = (1 << 31) | ((ea - gap) << 23) | rng.integers(1, 1 << 23, 64)
+    return a.astype(np.uint32), b.astype(np.uint32)
+
+
+def _disagrees(L):
+    f = Fmt(8, 23)
+    a, b = _wide_gap_pairs()
+    c = np.empty_like(a)
+    for mode in (0, 1):
+        L.oracle_binop(0, 8, 23, mode, a.ctypes.data, b.ctypes.data, c.ctypes.data, a.size, 1)
+        for i in range(a.size):
+            if check_correctly_rounded(f, "add", mode, int(a[i]), int(b[i]), int(c[i])) is not None:
+                return True
+    for (e, m) in [(5, 2), (4, 3), (3, 1)]:
+        f = Fmt(e, m)
+        ta, tm = tables(f)
+        n = 1 << f.B
+        a = np.repeat(np.arange(n, dtype=np.uint32), n)
+        b = np.tile(np.arange(n, dtype=np.uint32), n)
+        c = np.empty_like(a)
+        for opi, op in enumerate(("add", "sub", "mul")):
+            for mode in (0, 1):
+                L.oracle_binop(opi, e, m, mode, a.ctypes.data, b.ctypes.data, c.ctypes.data, a.size, 1)
+                for i in range(0, a.size, 5):
+                    if int(c[i]) != table_round(f, ta, tm, op, mode, int(a[i]), int(b[i])):
+                        return True
+    return False
+
+
+@pytest.mark.parametrize("name,old,new", MUTANTS, ids=[m[0] for m in MUTANTS])
+def test_mutant_is_caught(tmp_path, name, old, new):
+    text = open(SRC).read()
+    assert text.count(old) == 1, "mutation site not found: " + name
+    L = _build(tmp_path, text.replace(old, new), "mutant")
+    assert _disagrees(L), "planted mistake survived the pins: " + name
+
+
+def test_unmutated_copy_agrees(tmp_path):
+    """The same harness finds no disagreement for the committed oracle."""
+    L = _build(tmp_path, open(SRC).read(), "clean")
+    assert not _disagrees(L)

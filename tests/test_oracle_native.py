@@ -1,0 +1,155 @@
+"""Pin the oracle against native IEEE arithmetic on the host (no GPU).
+
+(8,23) is binary32, (5,10) binary16 and (8,7) bfloat16 under the IEEE-style
+reading of the format.  NaN results are compared for NaN-ness only (x86 and
+numpy propagate payloads and signs; the oracle returns its canonical NaN).
+"""
+import ctypes
+import os
+import subprocess
+
+import numpy as np
+import pytest
+
+HERE = os.path.dirname(os.path.abspath(__file__))
+
+
+@pytest.fixture(scope="module")
+def native():
+    flags = open("/proc/cpuinfo").read()
+    if " f16c" not in flags:
+        pytest.skip("host CPU lacks F16C")
+    so = os.path.join(HERE, "_native_pins.so")
+    src = os.path.join(HERE, "native_pins.c")
+    if not os.path.exists(so) or os.path.getmtime(so) < os.path.getmtime(src):
+        subprocess.check_call(["gcc", "-O1", "-frounding-math", "-fno-fast-math", "-mf16c",
+                               "-msse4.1", "-fPIC", "-shared", src, "-o", so + ".tmp"])
+        os.replace(so + ".tmp", so)
+    L = ctypes.CDLL(so)
+    vp, i32, sz = ctypes.c_void_p, ctypes.c_int, ctypes.c_size_t
+    L.f32_binop.argtypes = [i32, i32, vp, vp, vp, sz]
+    L.f16_binop_rz.argtypes = [i32, vp, vp, vp, sz]
+    return L
+
+
+def _nan_mask(x, e, m):
+    x = x.astype(np.uint64)
+    E = (x >> m) & ((1 << e) - 1)
+    M = x & ((1 << m) - 1)
+    return (E == (1 << e) - 1) & (M != 0)
+
+
+def _compare(e, m, got, want, a, b, what):
+    gn, wn = _nan_mask(got, e, m), _nan_mask(want, e, m)
+    assert np.array_equal(gn, wn), (what, np.flatnonzero(gn != wn)[:5])
+    canon = ((1 << e) - 1) << m | (1 << (m - 1))
+    assert np.all(got[gn] == canon)
+    ok = (got == want) | wn
+    bad = np.flatnonzero(~ok)
+    assert bad.size == 0, [(what, hex(a[i]), hex(b[i]), hex(got[i]), hex(want[i])) for i in bad[:5]]
+
+
+def _operands(rng, e, m, n):
+    """Uniform patterns, near-cancellation pairs, subnormal-heavy pairs, small exponent gaps."""
+    B = 1 + e + m
+    top = 1 << B
+    a = rng.integers(0, top, n, dtype=np.uint64)
+    b = rng.integers(0, top, n, dtype=np.uint64)
+    q = n // 4
+    # near cancellation: b = -(a +- small)
+    b[:q] = ((a[:q] + rng.integers(0, 5, q).astype(np.uint64)) % top) ^ (1 << (e + m))
+    # subnormal / tiny exponents
+    mmask = (1 << m) - 1
+    a[q:2 * q] = (rng.integers(0, 3, q).astype(np.uint64) << m) | (a[q:2 * q] & mmask) | \
+        (a[q:2 * q] & (1 << (e + m)))
+    # exponent gap 0 .. m+4
+    gap = rng.integers(0, m + 5, q).astype(np.int64)
+    ea = ((a[2 * q:3 * q] >> m) & ((1 << e) - 1)).astype(np.int64)
+    eb = np.clip(ea - gap, 0, (1 << e) - 2).astype(np.uint64)
+    b[2 * q:3 * q] = (b[2 * q:3 * q] & ~np.uint64(((1 << e) - 1) << m)) | (eb << m)
+    return a.astype(np.uint32), b.astype(np.uint32)
+
+
+def _edges(e, m):
+    from tests.exact_model import Fmt, edge_patterns
+    f = Fmt(e, m)
+    pos = edge_patterns(f)
+    pats = pos + [p | f.sign_bit for p in pos]
+    a = np.array([x for x in pats for _ in pats], dtype=np.uint32)
+    b = np.array([y for _ in pats for y in pats], dtype=np.uint32)
+    return a, b
+
+
+@pytest.mark.parametrize("mode", [0, 1])
+@pytest.mark.parametrize("op", [0, 1, 2])
+def test_binary32(oracle_lib, native, op, mode):
+    rng = np.random.default_rng(23 + 3 * op + mode)
+    a, b = _operands(rng, 8, 23, 200000)
+    ea, eb = _edges(8, 23)
+    a, b = np.concatenate([a, ea]), np.concatenate([b, eb])
+    want = np.empty_like(a)
+    native.f32_binop(op, mode, a.ctypes.data, b.ctypes.data, want.ctypes.data, a.size)
+    got = oracle_lib.binop(op, 8, 23, mode, a, b, nthreads=4)
+    _compare(8, 23, got, want, a, b, ("f32", op, mode))
+
+
+@pytest.mark.parametrize("op", ["add", "sub", "mul"])
+def test_binary16_rne_numpy(oracle_lib, op):
+    rng = np.random.default_rng(16)
+    a, b = _operands(rng, 5, 10, 400000)
+    ea, eb = _edges(5, 10)
+    a, b = np.concatenate([a, ea]), np.concatenate([b, eb])
+    ha, hb = a.astype(np.uint16).view(np.float16), b.astype(np.uint16).view(np.float16)
+    with np.errstate(all="ignore"):
+        r = {"add": ha + hb, "sub": ha - hb, "mul": ha * hb}[op]
+    want = r.view(np.uint16).astype(np.uint32)
+    got = oracle_lib.binop(op, 5, 10, 0, a, b, nthreads=4)
+    _compare(5, 10, got, want, a, b, ("f16 rne", op))
+
+
+@pytest.mark.parametrize("op", [0, 1, 2])
+def test_binary16_rz_f16c(oracle_lib, native, op):
+    rng = np.random.default_rng(160 + op)
+    a, b = _operands(rng, 5, 10, 400000)
+    ea, eb = _edges(5, 10)
+    a, b = np.concatenate([a, ea]), np.concatenate([b, eb])
+    a16, b16 = a.astype(np.uint16), b.astype(np.uint16)
+    w16 = np.empty_like(a16)
+    native.f16_binop_rz(op, a16.ctypes.data, b16.ctypes.data, w16.ctypes.data, a16.size)
+    got = oracle_lib.binop(op, 5, 10, 1, a, b, nthreads=4)
+    _compare(5, 10, got, w16.astype(np.uint32), a, b, ("f16 rz", op))
+
+
+def test_binary16_exhaustive_slice(oracle_lib):
+    """All b against a fixed set of a's (65,536 x 64 pairs), binary16 RNE."""
+    bs = np.arange(65536, dtype=np.uint32)
+    rng = np.random.default_rng(99)
+    for av in rng.integers(0, 65536, 64):
+        a = np.full(65536, av, dtype=np.uint32)
+        ha, hb = a.astype(np.uint16).view(np.float16), bs.astype(np.uint16).view(np.float16)
+        for op in ("add", "mul"):
+            with np.errstate(all="ignore"):
+                r = ha + hb if op == "add" else ha * hb
+            got = oracle_lib.binop(op, 5, 10, 0, a, bs)
+            _compare(5, 10, got, r.view(np.uint16).astype(np.uint32), a, bs, ("f16 slice", op))
+
+
+@pytest.mark.parametrize("op", ["add", "sub", "mul"])
+def test_bfloat16_rne_torch(oracle_lib, op):
+    torch = pytest.importorskip("torch")
+    torch.set_flush_denormal(False)
+    # torch computes bf16 arithmetic in float32 and rounds once to nearest-even;
+    # check that on a tie first: 1 + 2^-8 lies halfway between 1 and 1 + 2^-7.
+    one = torch.tensor([0x3F80], dtype=torch.int16).view(torch.bfloat16)
+    tiny = torch.tensor([0x3B80], dtype=torch.int16).view(torch.bfloat16)
+    assert int((one + tiny).view(torch.int16)) == 0x3F80
+    rng = np.random.default_rng(87)
+    a, b = _operands(rng, 8, 7, 400000)
+    ea, eb = _edges(8, 7)
+    a, b = np.concatenate([a, ea]), np.concatenate([b, eb])
+    ta = torch.from_numpy(a.astype(np.uint16).view(np.int16)).view(torch.bfloat16)
+    tb = torch.from_numpy(b.astype(np.uint16).view(np.int16)).view(torch.bfloat16)
+    r = {"add": ta + tb, "sub": ta - tb, "mul": ta * tb}[op]
+    want = r.view(torch.int16).numpy().view(np.uint16).astype(np.uint32)
+    got = oracle_lib.binop(op, 8, 7, 0, a, b, nthreads=4)
+    _compare(8, 7, got, want, a, b, ("bf16", op))
