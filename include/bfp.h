@@ -1,0 +1,178 @@
+/*
+ * bfp.h -- C ABI of libbfp: bitslice custom-precision floating point on
+ * AMD MI355X (gfx950).
+ *
+ * A custom format has 1 sign bit, e exponent bits and m mantissa bits
+ * (B = 1 + e + m).  The paper offers its operations as intrinsic-style C
+ * functions generated for one (exponent bits, mantissa bits, rounding mode)
+ * configuration (Section 1 contributions; Section 5.1); here the same three
+ * numbers are a runtime argument, `bfp_format`, and the library carries the
+ * compiled circuits of every format e in {3,4,5,6,8} x m in
+ * {1,2,3,5,7,10,15,23}.
+ *
+ * Layouts (Section 2, Figure 1; Section 4, Figure 3):
+ *   standard  one element per unsigned container of 1, 2 or 4 bytes
+ *             (B <= 8, <= 16, <= 32), value in the low B bits: mantissa in
+ *             bits [0,m), exponent in [m,m+e), sign in bit m+e.  Bits above B
+ *             are ignored on input and written as zero on output.
+ *   bitslice  B planes of G_pad 32-bit words each, plane k first
+ *             (plane-major).  Plane k holds bit k of every element; element
+ *             i sits in word i/32 of its plane at bit i%32.
+ *             G_pad = bfp_plane_stride_words(n) = ceil(n/32) rounded up to a
+ *             multiple of 64, so every plane starts 256-byte aligned.  The
+ *             layout is the same for any word width a kernel uses (32 or 64
+ *             elements per lane word).  Padding bits past element n are zero
+ *             after bfp_pack and stay zero through every operation
+ *             (0 op 0 = +0, whose bits are all zero).
+ *
+ * Semantics: each result is the exact sum, difference or product rounded
+ * once, to nearest with ties to even (BFP_RNE) or toward zero (BFP_RZ) -- the
+ * two modes of Section 4.  Exponent bias 2^(e-1)-1; exponent field 0 holds
+ * zero and subnormals; all ones holds Inf (mantissa 0) and NaN.  Overflow
+ * gives Inf (RNE) or the largest finite value (RZ).  An exact zero sum of
+ * opposite-signed operands is +0.  NaN results are the canonical quiet NaN
+ * (sign 0, exponent all ones, mantissa 2^(m-1)); payloads do not propagate.
+ * sub(a, b) = add(a, b with its sign flipped).
+ *
+ * Conventions common to every call:
+ *   - Pointers named as device pointers are device memory (hipMalloc or a
+ *     torch CUDA tensor's data pointer), 16-byte aligned, owned by the
+ *     caller; calls never take ownership and op calls never allocate.
+ *   - `stream` is a hipStream_t passed as void*; NULL is the null stream.
+ *     Calls are asynchronous with respect to the host: they enqueue work and
+ *     return.  A fault inside a kernel surfaces at the caller's next
+ *     synchronisation of that stream.
+ *   - n == 0 is a no-op that returns BFP_OK.
+ *   - Errors are returned as negative bfp_status codes; nothing aborts and no
+ *     C++ exception crosses this interface.
+ *   - The library is thread-safe; the launch-configuration table is guarded
+ *     by a lock.
+ */
+#ifndef BFP_H
+#define BFP_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef int bfp_status;
+
+#define BFP_OK 0
+#define BFP_E_FORMAT (-1)   /* (e, m) not compiled, or round not RNE/RZ */
+#define BFP_E_NULL (-2)     /* null pointer with n > 0 */
+#define BFP_E_ALIGN (-3)    /* pointer not 16-byte aligned */
+#define BFP_E_OP (-4)       /* op not BFP_ADD/BFP_SUB/BFP_MUL */
+#define BFP_E_HIP (-5)      /* HIP runtime error on launch */
+#define BFP_E_ARG (-6)      /* other invalid argument (size, count, handle) */
+#define BFP_E_ALIAS (-7)    /* forbidden overlap of input and output */
+#define BFP_E_BUDGET (-8)   /* serving: memory budget exceeded */
+#define BFP_E_NOMEM (-9)    /* host or device allocation failed */
+#define BFP_E_NODEV (-10)   /* no usable gfx950 device */
+
+#define BFP_RNE 0 /* round to nearest, ties to even (Section 4) */
+#define BFP_RZ 1  /* round toward zero (Section 4) */
+
+/* Operation codes (Section 4, Table 1: Add/Sub, Mul). */
+#define BFP_ADD 0
+#define BFP_SUB 1
+#define BFP_MUL 2
+
+/* A custom format: e exponent bits, m mantissa bits, rounding mode. */
+typedef struct {
+  uint8_t e;
+  uint8_t m;
+  uint8_t round; /* BFP_RNE or BFP_RZ */
+  uint8_t pad;   /* must be 0 */
+} bfp_format;
+
+/* Text of a status code (static storage). */
+const char* bfp_status_string(bfp_status s);
+
+/* Library version, e.g. "0.1.0". */
+const char* bfp_version(void);
+
+/* 1 if (e, m, round) is compiled into this library, else 0. */
+int bfp_format_supported(bfp_format f);
+
+/* ---- sizing -------------------------------------------------------------- */
+
+/* Bytes of one standard container: 1, 2 or 4; 0 for an invalid format. */
+size_t bfp_container_bytes(bfp_format f);
+
+/* G_pad: 32-bit words per plane for n elements (ceil(n/32) rounded up to a
+ * multiple of 64). */
+uint64_t bfp_plane_stride_words(uint64_t n);
+
+/* Bytes of one bitslice vector: B * G_pad * 4; 0 for an invalid format. */
+size_t bfp_bitslice_bytes(bfp_format f, uint64_t n);
+
+/* ---- layout transforms (Section 4 helper transforms; Figure 1) ------------ */
+
+/* Standard -> bitslice.  std_in: device, n containers.  bs_out: device,
+ * bfp_bitslice_bytes(f, n) bytes, fully written (padding words zero).  The
+ * two buffers must not overlap (BFP_E_ALIAS). */
+bfp_status bfp_pack(bfp_format f, const void* std_in, void* bs_out, uint64_t n, void* stream);
+
+/* Bitslice -> standard.  bs_in: device, bitslice vector of n elements.
+ * std_out: device, n containers written (upper bits zero); no byte past
+ * container n-1 is written.  No overlap allowed. */
+bfp_status bfp_unpack(bfp_format f, const void* bs_in, void* std_out, uint64_t n, void* stream);
+
+/* ---- arithmetic on resident bitslice vectors (Section 4, Table 1) --------- */
+
+/* c = a op b elementwise, op in {BFP_ADD, BFP_SUB, BFP_MUL}.  a, b, c:
+ * device bitslice vectors of n elements in format f (same G_pad); all
+ * G_pad words of every plane of c are written.  c may be the same buffer as
+ * a or b (each lane reads all of its words before writing); partial
+ * overlaps are not allowed. */
+bfp_status bfp_binop(int op, bfp_format f, const void* a, const void* b, void* c, uint64_t n,
+                     void* stream);
+bfp_status bfp_add(bfp_format f, const void* a, const void* b, void* c, uint64_t n, void* stream);
+bfp_status bfp_sub(bfp_format f, const void* a, const void* b, void* c, uint64_t n, void* stream);
+bfp_status bfp_mul(bfp_format f, const void* a, const void* b, void* c, uint64_t n, void* stream);
+
+/* Fused standard-in / standard-out op: pack both operands in registers, run
+ * the circuit, unpack, in one kernel with no bitslice round trip to memory.
+ * a, b, c: device, n containers each (bfp_container_bytes).  c may equal a
+ * or b; partial overlaps are not allowed. */
+bfp_status bfp_binop_std(int op, bfp_format f, const void* a, const void* b, void* c, uint64_t n,
+                         void* stream);
+
+/* ---- launch configuration (autotuning) ------------------------------------ */
+
+/* One kernel variant: words per lane per plane (1: W = 32 elements,
+ * 2: W = 64), threads per block, and blocks per compute unit for the
+ * grid-stride grid (0: one thread per work item, no stride loop). */
+typedef struct {
+  int32_t words_per_lane; /* 1 or 2 */
+  int32_t block;          /* 64, 128, 256 or 512 */
+  int32_t blocks_per_cu;  /* 0 or 1..64 */
+  int32_t pad;            /* must be 0 */
+} bfp_launch;
+
+/* Current configuration used for (op, f) by bfp_binop (op BFP_SUB shares
+ * BFP_ADD's).  Returns BFP_OK and fills *out. */
+bfp_status bfp_launch_get(int op, bfp_format f, bfp_launch* out);
+
+/* Set the configuration for (op, f).  Invalid values give BFP_E_ARG. */
+bfp_status bfp_launch_set(int op, bfp_format f, const bfp_launch* cfg);
+
+/* Load / save the whole table as text, one line per entry:
+ * "op e m round words_per_lane block blocks_per_cu".  Lines starting with
+ * '#' are comments.  Unknown formats are skipped on load. */
+bfp_status bfp_launch_load(const char* path);
+bfp_status bfp_launch_save(const char* path);
+
+/* Gate count of one circuit instance (one group of 32 elements per word),
+ * constants folded: the cost model of Table 1.  Returns -1 if the format
+ * is not compiled. */
+long bfp_gate_count(int op, bfp_format f);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* BFP_H */

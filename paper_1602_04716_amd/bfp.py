@@ -1,0 +1,229 @@
+"""Python binding of libbfp (include/bfp.h): argument marshalling only.
+
+Every function named ``bfp_*`` calls the C function of the same name; all
+arithmetic and layout work happens in the library's HIP kernels.  Device
+buffers are torch CUDA tensors (or raw integer device addresses); ``stream``
+defaults to torch's current stream on the current device.  A non-OK status
+raises :class:`BfpError`.  If ``libbfp.so`` has not been built, :func:`lib`
+raises: there is no other execution path.
+"""
+from __future__ import annotations
+
+import ctypes
+import os
+
+_HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(_HERE, "libbfp.so")
+
+BFP_OK = 0
+BFP_RNE, BFP_RZ = 0, 1
+BFP_ADD, BFP_SUB, BFP_MUL = 0, 1, 2
+OPS = {"add": BFP_ADD, "sub": BFP_SUB, "mul": BFP_MUL}
+
+
+class bfp_format(ctypes.Structure):
+    _fields_ = [("e", ctypes.c_uint8), ("m", ctypes.c_uint8), ("round", ctypes.c_uint8),
+                ("pad", ctypes.c_uint8)]
+
+    def __repr__(self):
+        return "bfp_format(e=%d, m=%d, round=%d)" % (self.e, self.m, self.round)
+
+
+class bfp_launch(ctypes.Structure):
+    _fields_ = [("words_per_lane", ctypes.c_int32), ("block", ctypes.c_int32),
+                ("blocks_per_cu", ctypes.c_int32), ("pad", ctypes.c_int32)]
+
+    def __repr__(self):
+        return "bfp_launch(words_per_lane=%d, block=%d, blocks_per_cu=%d)" % (
+            self.words_per_lane, self.block, self.blocks_per_cu)
+
+
+class BfpError(RuntimeError):
+    def __init__(self, status: int, where: str):
+        self.status = status
+        super().__init__("%s: %s (%d)" % (where, lib().bfp_status_string(status).decode(), status))
+
+
+_lib = None
+
+_SIGS = {
+    "bfp_status_string": (ctypes.c_char_p, [ctypes.c_int]),
+    "bfp_version": (ctypes.c_char_p, []),
+    "bfp_format_supported": (ctypes.c_int, [bfp_format]),
+    "bfp_container_bytes": (ctypes.c_size_t, [bfp_format]),
+    "bfp_plane_stride_words": (ctypes.c_uint64, [ctypes.c_uint64]),
+    "bfp_bitslice_bytes": (ctypes.c_size_t, [bfp_format, ctypes.c_uint64]),
+    "bfp_pack": (ctypes.c_int, [bfp_format, ctypes.c_void_p, ctypes.c_void_p, ctypes.c_uint64, ctypes.c_void_p]),
+    "bfp_unpack": (ctypes.c_int, [bfp_format, ctypes.c_void_p, ctypes.c_void_p, ctypes.c_uint64,
+                                  ctypes.c_void_p]),
+    "bfp_binop": (ctypes.c_int, [ctypes.c_int, bfp_format, ctypes.c_void_p, ctypes.c_void_p, ctypes.c_void_p,
+                                 ctypes.c_uint64, ctypes.c_void_p]),
+    "bfp_add": (ctypes.c_int, [bfp_format, ctypes.c_void_p, ctypes.c_void_p, ctypes.c_void_p, ctypes.c_uint64,
+                               ctypes.c_void_p]),
+    "bfp_sub": (ctypes.c_int, [bfp_format, ctypes.c_void_p, ctypes.c_void_p, ctypes.c_void_p, ctypes.c_uint64,
+                               ctypes.c_void_p]),
+    "bfp_mul": (ctypes.c_int, [bfp_format, ctypes.c_void_p, ctypes.c_void_p, ctypes.c_void_p, ctypes.c_uint64,
+                               ctypes.c_void_p]),
+    "bfp_binop_std": (ctypes.c_int, [ctypes.c_int, bfp_format, ctypes.c_void_p, ctypes.c_void_p,
+                                     ctypes.c_void_p, ctypes.c_uint64, ctypes.c_void_p]),
+    "bfp_launch_get": (ctypes.c_int, [ctypes.c_int, bfp_format, ctypes.POINTER(bfp_launch)]),
+    "bfp_launch_set": (ctypes.c_int, [ctypes.c_int, bfp_format, ctypes.POINTER(bfp_launch)]),
+    "bfp_launch_load": (ctypes.c_int, [ctypes.c_char_p]),
+    "bfp_launch_save": (ctypes.c_int, [ctypes.c_char_p]),
+    "bfp_gate_count": (ctypes.c_long, [ctypes.c_int, bfp_format]),
+}
+
+
+def lib():
+    """Load libbfp.so; raise if it is not built."""
+    global _lib
+    if _lib is None:
+        if not os.path.exists(LIB_PATH):
+            raise ImportError("libbfp.so is not built (python -m paper_1602_04716_amd.build)")
+        L = ctypes.CDLL(LIB_PATH)
+        for name, (res, args) in _SIGS.items():
+            fn = getattr(L, name)
+            fn.restype = res
+            fn.argtypes = args
+        _lib = L
+    return _lib
+
+
+def declared_functions():
+    return sorted(_SIGS)
+
+
+def fmt(e: int, m: int, round: int = BFP_RNE) -> bfp_format:
+    return bfp_format(e, m, round, 0)
+
+
+def _op(op) -> int:
+    return OPS[op] if isinstance(op, str) else int(op)
+
+
+def _ptr(x) -> int:
+    if x is None:
+        return 0
+    if isinstance(x, int):
+        return x
+    if not x.is_cuda:
+        raise ValueError("expected a device tensor")
+    if not x.is_contiguous():
+        raise ValueError("expected a contiguous tensor")
+    return x.data_ptr()
+
+
+def _stream(s) -> int:
+    if s is None:
+        import torch
+        return torch.cuda.current_stream().cuda_stream
+    if isinstance(s, int):
+        return s
+    return s.cuda_stream
+
+
+def _check(st: int, where: str):
+    if st != BFP_OK:
+        raise BfpError(st, where)
+
+
+# ---- the C functions, same names -----------------------------------------
+def bfp_status_string(s: int) -> str:
+    return lib().bfp_status_string(s).decode()
+
+
+def bfp_version() -> str:
+    return lib().bfp_version().decode()
+
+
+def bfp_format_supported(f: bfp_format) -> bool:
+    return bool(lib().bfp_format_supported(f))
+
+
+def bfp_container_bytes(f: bfp_format) -> int:
+    return int(lib().bfp_container_bytes(f))
+
+
+def bfp_plane_stride_words(n: int) -> int:
+    return int(lib().bfp_plane_stride_words(n))
+
+
+def bfp_bitslice_bytes(f: bfp_format, n: int) -> int:
+    return int(lib().bfp_bitslice_bytes(f, n))
+
+
+def bfp_pack(f, std_in, bs_out, n: int, stream=None):
+    _check(lib().bfp_pack(f, _ptr(std_in), _ptr(bs_out), n, _stream(stream)), "bfp_pack")
+
+
+def bfp_unpack(f, bs_in, std_out, n: int, stream=None):
+    _check(lib().bfp_unpack(f, _ptr(bs_in), _ptr(std_out), n, _stream(stream)), "bfp_unpack")
+
+
+def bfp_binop(op, f, a, b, c, n: int, stream=None):
+    _check(lib().bfp_binop(_op(op), f, _ptr(a), _ptr(b), _ptr(c), n, _stream(stream)), "bfp_binop")
+
+
+def bfp_add(f, a, b, c, n: int, stream=None):
+    _check(lib().bfp_add(f, _ptr(a), _ptr(b), _ptr(c), n, _stream(stream)), "bfp_add")
+
+
+def bfp_sub(f, a, b, c, n: int, stream=None):
+    _check(lib().bfp_sub(f, _ptr(a), _ptr(b), _ptr(c), n, _stream(stream)), "bfp_sub")
+
+
+def bfp_mul(f, a, b, c, n: int, stream=None):
+    _check(lib().bfp_mul(f, _ptr(a), _ptr(b), _ptr(c), n, _stream(stream)), "bfp_mul")
+
+
+def bfp_binop_std(op, f, a, b, c, n: int, stream=None):
+    _check(lib().bfp_binop_std(_op(op), f, _ptr(a), _ptr(b), _ptr(c), n, _stream(stream)), "bfp_binop_std")
+
+
+def bfp_launch_get(op, f) -> bfp_launch:
+    out = bfp_launch()
+    _check(lib().bfp_launch_get(_op(op), f, ctypes.byref(out)), "bfp_launch_get")
+    return out
+
+
+def bfp_launch_set(op, f, words_per_lane: int, block: int, blocks_per_cu: int):
+    cfg = bfp_launch(words_per_lane, block, blocks_per_cu, 0)
+    _check(lib().bfp_launch_set(_op(op), f, ctypes.byref(cfg)), "bfp_launch_set")
+
+
+def bfp_launch_load(path: str):
+    _check(lib().bfp_launch_load(path.encode()), "bfp_launch_load")
+
+
+def bfp_launch_save(path: str):
+    _check(lib().bfp_launch_save(path.encode()), "bfp_launch_save")
+
+
+def bfp_gate_count(op, f) -> int:
+    return int(lib().bfp_gate_count(_op(op), f))
+
+
+# ---- conveniences over torch tensors ----------------------------------------
+def container_dtype(f: bfp_format):
+    import torch
+    return {1: torch.uint8, 2: torch.uint16, 4: torch.uint32}[bfp_container_bytes(f)]
+
+
+def empty_bitslice(f: bfp_format, n: int, device="cuda"):
+    """Uninitialised bitslice vector: (B, G_pad) uint32 planes."""
+    import torch
+    B = 1 + f.e + f.m
+    return torch.empty((B, bfp_plane_stride_words(n)), dtype=torch.uint32, device=device)
+
+
+def pack(f: bfp_format, std, stream=None):
+    out = empty_bitslice(f, std.numel(), std.device)
+    bfp_pack(f, std, out, std.numel(), stream)
+    return out
+
+
+def unpack(f: bfp_format, bs, n: int, stream=None):
+    import torch
+    out = torch.empty(n, dtype=container_dtype(f), device=bs.device)
+    bfp_unpack(f, bs, out, n, stream)
+    return out

@@ -1,0 +1,18 @@
+// bfp_formats.hpp -- the (e, m) formats compiled into the library.
+//
+// The paper's generator emits one library per (exponent bits, mantissa bits,
+// rounding mode) configuration (Section 5.1); here every format of the sweep
+// e in {3,4,5,6,8} x m in {1,2,3,5,7,10,15,23} is instantiated once per
+// operation class and rounding mode, which covers FP8 (4,3), FP16 (5,10) and
+// FP32 (8,23) of Section 5.2 and bfloat16 (8,7).
+#pragma once
+
+// X(e, m) for every compiled format
+#define BFP_FOR_EACH_M(X, e) X(e, 1) X(e, 2) X(e, 3) X(e, 5) X(e, 7) X(e, 10) X(e, 15) X(e, 23)
+#define BFP_FOR_EACH_FORMAT(X) \
+  BFP_FOR_EACH_M(X, 3) BFP_FOR_EACH_M(X, 4) BFP_FOR_EACH_M(X, 5) BFP_FOR_EACH_M(X, 6) BFP_FOR_EACH_M(X, 8)
+
+namespace bfp {
+constexpr int kMaxE = 8;
+constexpr int kMaxM = 23;
+}  // namespace bfp

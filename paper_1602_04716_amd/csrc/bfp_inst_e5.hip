@@ -1,0 +1,14 @@
+// Kernel instances for the formats with e = 5 (every compiled m), both
+// operation classes, both rounding modes and both word widths.
+#include "bfp_formats.hpp"
+#include "bfp_kernels.hpp"
+
+namespace {
+struct RegisterE5 {
+  RegisterE5() {
+#define BFP_REG(E, M) bfp::register_format<E, M>();
+    BFP_FOR_EACH_M(BFP_REG, 5)
+#undef BFP_REG
+  }
+} register_e5;
+}  // namespace

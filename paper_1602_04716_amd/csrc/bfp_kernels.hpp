@@ -1,0 +1,302 @@
+// bfp_kernels.hpp -- HIP kernels for gfx950 and their launchers.
+//
+// Data layout (plane-major bitslice, see include/bfp.h): plane k of a vector
+// is gpad consecutive 32-bit words.  A lane owns R adjacent words of every
+// plane (W = 32 R elements) and reads them with one coalesced load per
+// plane: consecutive lanes read consecutive words, so each plane load of a
+// wave is one contiguous 256 R-byte segment.  The circuit runs entirely in
+// VGPRs; nothing here is a contraction, so there is no MFMA and no LDS.
+#pragma once
+#include <hip/hip_runtime.h>
+
+#include "bfp_circuits.hpp"
+#include "bfp_transpose.hpp"
+
+namespace bfp {
+
+typedef uint32_t u32x2 __attribute__((ext_vector_type(2)));
+typedef uint32_t u32x4 __attribute__((ext_vector_type(4)));
+
+template <int R>
+__device__ __forceinline__ WordR<R> ld_words(const uint32_t* p) {
+  WordR<R> v;
+  if constexpr (R == 1) {
+    v.w[0] = __builtin_nontemporal_load(p);
+  } else if constexpr (R == 2) {
+    const u32x2 t = __builtin_nontemporal_load(reinterpret_cast<const u32x2*>(p));
+    v.w[0] = t.x;
+    v.w[1] = t.y;
+  } else {
+    static_assert(R == 4, "R must be 1, 2 or 4");
+    const u32x4 t = __builtin_nontemporal_load(reinterpret_cast<const u32x4*>(p));
+    v.w[0] = t.x;
+    v.w[1] = t.y;
+    v.w[2] = t.z;
+    v.w[3] = t.w;
+  }
+  return v;
+}
+
+template <int R>
+__device__ __forceinline__ void st_words(uint32_t* p, const WordR<R>& v) {
+  if constexpr (R == 1) {
+    __builtin_nontemporal_store(v.w[0], p);
+  } else if constexpr (R == 2) {
+    u32x2 t;
+    t.x = v.w[0];
+    t.y = v.w[1];
+    __builtin_nontemporal_store(t, reinterpret_cast<u32x2*>(p));
+  } else {
+    u32x4 t;
+    t.x = v.w[0];
+    t.y = v.w[1];
+    t.z = v.w[2];
+    t.w = v.w[3];
+    __builtin_nontemporal_store(t, reinterpret_cast<u32x4*>(p));
+  }
+}
+
+// One circuit instance on R words per plane.  OPC 0: add/sub (negb all ones
+// subtracts), 1: mul.
+template <int E, int M, bool RZ, int OPC, int R>
+__device__ __forceinline__ void circuit(const WordR<R>* x, const WordR<R>* y, uint32_t negb, WordR<R>* z) {
+  if constexpr (OPC == 0) {
+    WordR<R> nb;
+#pragma unroll
+    for (int i = 0; i < R; ++i) nb.w[i] = negb;
+    fp_add<E, M, RZ, WordR<R>>(x, y, nb, z);
+  } else {
+    fp_mul<E, M, RZ, WordR<R>>(x, y, z);
+  }
+}
+
+// c = a op b on resident bitslice vectors: every word of every plane.
+template <int E, int M, bool RZ, int OPC, int R>
+__global__ void __launch_bounds__(512) k_binop(const uint32_t* a, const uint32_t* b, uint32_t* c,
+                                               uint64_t gpad, uint32_t negb) {
+  constexpr int B = 1 + E + M;
+  const uint64_t nt = gpad / R;
+  const uint64_t stride = (uint64_t)gridDim.x * blockDim.x;
+  for (uint64_t t = (uint64_t)blockIdx.x * blockDim.x + threadIdx.x; t < nt; t += stride) {
+    const uint64_t off = t * R;
+    WordR<R> x[B], y[B], z[B];
+#pragma unroll
+    for (int k = 0; k < B; ++k) {
+      x[k] = ld_words<R>(a + (uint64_t)k * gpad + off);
+      y[k] = ld_words<R>(b + (uint64_t)k * gpad + off);
+    }
+    circuit<E, M, RZ, OPC, R>(x, y, negb, z);
+#pragma unroll
+    for (int k = 0; k < B; ++k) st_words<R>(c + (uint64_t)k * gpad + off, z[k]);
+  }
+}
+
+// Load the 32 R standard elements starting at element e0 (C bytes each) as
+// 8 C R dwords; elements at or past n read as zero.
+template <int C, int R>
+__device__ __forceinline__ void load_std(const uint8_t* src, uint64_t e0, uint64_t n, uint32_t (*in)[8 * C]) {
+  if (e0 + 32 * R <= n) {
+    const u32x4* p = reinterpret_cast<const u32x4*>(src + e0 * C);
+#pragma unroll
+    for (int r = 0; r < R; ++r) {
+#pragma unroll
+      for (int q = 0; q < 2 * C; ++q) {
+        const u32x4 v = __builtin_nontemporal_load(p + r * 2 * C + q);
+        in[r][4 * q + 0] = v.x;
+        in[r][4 * q + 1] = v.y;
+        in[r][4 * q + 2] = v.z;
+        in[r][4 * q + 3] = v.w;
+      }
+    }
+  } else {
+    // ragged tail or padding: byte loads, every array index a constant
+#pragma unroll
+    for (int r = 0; r < R; ++r) {
+#pragma unroll
+      for (int w = 0; w < 8 * C; ++w) {
+        uint32_t v = 0u;
+#pragma unroll
+        for (int q = 0; q < 4; ++q) {
+          const int byte = 4 * w + q;
+          const uint64_t idx = e0 + 32 * r + byte / C;
+          if (idx < n) v |= (uint32_t)src[idx * C + byte % C] << (8 * q);
+        }
+        in[r][w] = v;
+      }
+    }
+  }
+}
+
+// Store 32 R standard elements starting at e0; nothing at or past n.
+template <int C, int R>
+__device__ __forceinline__ void store_std(uint8_t* dst, uint64_t e0, uint64_t n, uint32_t (*out)[8 * C]) {
+  if (e0 + 32 * R <= n) {
+    u32x4* p = reinterpret_cast<u32x4*>(dst + e0 * C);
+#pragma unroll
+    for (int r = 0; r < R; ++r) {
+#pragma unroll
+      for (int q = 0; q < 2 * C; ++q) {
+        u32x4 v;
+        v.x = out[r][4 * q + 0];
+        v.y = out[r][4 * q + 1];
+        v.z = out[r][4 * q + 2];
+        v.w = out[r][4 * q + 3];
+        __builtin_nontemporal_store(v, p + r * 2 * C + q);
+      }
+    }
+  } else {
+    // ragged tail: one container store per element below n
+#pragma unroll
+    for (int j = 0; j < 32 * R; ++j) {
+      const uint64_t idx = e0 + j;
+      const int r = j >> 5, byte = (j & 31) * C;
+      const uint32_t w = out[r][byte >> 2] >> (8 * (byte & 3));
+      if (idx < n) {
+        if constexpr (C == 1) dst[idx] = (uint8_t)w;
+        else if constexpr (C == 2) reinterpret_cast<uint16_t*>(dst)[idx] = (uint16_t)w;
+        else reinterpret_cast<uint32_t*>(dst)[idx] = w;
+      }
+    }
+  }
+}
+
+// Standard -> bitslice over all gpad words of each plane (padding words get
+// zero bits).  B planes of the 8 C computed are stored.
+template <int C, int R>
+__global__ void __launch_bounds__(512) k_pack(const uint8_t* src, uint32_t* planes, uint64_t n,
+                                              uint64_t gpad, int B) {
+  const uint64_t nt = gpad / R;
+  const uint64_t stride = (uint64_t)gridDim.x * blockDim.x;
+  for (uint64_t t = (uint64_t)blockIdx.x * blockDim.x + threadIdx.x; t < nt; t += stride) {
+    const uint64_t g0 = t * R;
+    uint32_t in[R][8 * C];
+    load_std<C, R>(src, g0 * 32, n, in);
+    WordR<R> pl[8 * C];
+#pragma unroll
+    for (int r = 0; r < R; ++r) {
+      uint32_t tmp[8 * C];
+      transpose_pack<C>(in[r], tmp);
+#pragma unroll
+      for (int k = 0; k < 8 * C; ++k) pl[k].w[r] = tmp[k];
+    }
+#pragma unroll
+    for (int k = 0; k < 8 * C; ++k)
+      if (k < B) st_words<R>(planes + (uint64_t)k * gpad + g0, pl[k]);
+  }
+}
+
+// Bitslice -> standard for the ceil(n/32) words that hold elements.
+template <int C, int R>
+__global__ void __launch_bounds__(512) k_unpack(const uint32_t* planes, uint8_t* dst, uint64_t n,
+                                                uint64_t gpad, int B) {
+  const uint64_t groups = (n + 31) / 32;
+  const uint64_t nt = (groups + R - 1) / R;
+  const uint64_t stride = (uint64_t)gridDim.x * blockDim.x;
+  for (uint64_t t = (uint64_t)blockIdx.x * blockDim.x + threadIdx.x; t < nt; t += stride) {
+    const uint64_t g0 = t * R;
+    WordR<R> pl[8 * C];
+#pragma unroll
+    for (int k = 0; k < 8 * C; ++k) {
+      if (k < B) {
+        pl[k] = ld_words<R>(planes + (uint64_t)k * gpad + g0);
+      } else {
+#pragma unroll
+        for (int r = 0; r < R; ++r) pl[k].w[r] = 0u;
+      }
+    }
+    uint32_t out[R][8 * C];
+#pragma unroll
+    for (int r = 0; r < R; ++r) {
+      uint32_t tmp[8 * C];
+#pragma unroll
+      for (int k = 0; k < 8 * C; ++k) tmp[k] = pl[k].w[r];
+      transpose_unpack<C>(tmp, out[r]);
+    }
+    store_std<C, R>(dst, g0 * 32, n, out);
+  }
+}
+
+// Fused standard-in / standard-out op: transposes and circuit in registers.
+template <int E, int M, bool RZ, int OPC>
+__global__ void __launch_bounds__(512) k_binop_std(const uint8_t* a, const uint8_t* b, uint8_t* c,
+                                                   uint64_t n, uint32_t negb) {
+  constexpr int B = 1 + E + M;
+  constexpr int C = B <= 8 ? 1 : (B <= 16 ? 2 : 4);
+  const uint64_t groups = (n + 31) / 32;
+  const uint64_t stride = (uint64_t)gridDim.x * blockDim.x;
+  for (uint64_t t = (uint64_t)blockIdx.x * blockDim.x + threadIdx.x; t < groups; t += stride) {
+    uint32_t ia[1][8 * C], ib[1][8 * C];
+    load_std<C, 1>(a, t * 32, n, ia);
+    load_std<C, 1>(b, t * 32, n, ib);
+    uint32_t pa[8 * C], pb[8 * C];
+    transpose_pack<C>(ia[0], pa);
+    transpose_pack<C>(ib[0], pb);
+    WordR<1> x[B], y[B], z[B];
+#pragma unroll
+    for (int k = 0; k < B; ++k) {
+      x[k].w[0] = pa[k];
+      y[k].w[0] = pb[k];
+    }
+    circuit<E, M, RZ, OPC, 1>(x, y, negb, z);
+    uint32_t pz[8 * C];
+#pragma unroll
+    for (int k = 0; k < 8 * C; ++k) pz[k] = (k < B) ? z[k].w[0] : 0u;
+    uint32_t oc[1][8 * C];
+    transpose_unpack<C>(pz, oc[0]);
+    store_std<C, 1>(c, t * 32, n, oc);
+  }
+}
+
+// ---------------------------------------------------------------------------
+// Launchers and the registry of compiled variants
+// ---------------------------------------------------------------------------
+using BinopLauncher = hipError_t (*)(const void* a, const void* b, void* c, uint64_t gpad, uint32_t negb,
+                                     unsigned grid, unsigned block, hipStream_t s);
+using StdLauncher = hipError_t (*)(const void* a, const void* b, void* c, uint64_t n, uint32_t negb,
+                                   unsigned grid, unsigned block, hipStream_t s);
+
+constexpr int kMaxWordsPerLane = 2;  // R in {1, 2}
+
+struct Registry {
+  // [e][m][opclass][rz][R-1]
+  BinopLauncher binop[9][24][2][2][kMaxWordsPerLane] = {};
+  StdLauncher std_op[9][24][2][2] = {};
+};
+Registry& registry();
+
+template <int E, int M, bool RZ, int OPC, int R>
+hipError_t launch_binop(const void* a, const void* b, void* c, uint64_t gpad, uint32_t negb, unsigned grid,
+                        unsigned block, hipStream_t s) {
+  hipLaunchKernelGGL((k_binop<E, M, RZ, OPC, R>), dim3(grid), dim3(block), 0, s,
+                     static_cast<const uint32_t*>(a), static_cast<const uint32_t*>(b),
+                     static_cast<uint32_t*>(c), gpad, negb);
+  return hipGetLastError();
+}
+
+template <int E, int M, bool RZ, int OPC>
+hipError_t launch_binop_std(const void* a, const void* b, void* c, uint64_t n, uint32_t negb, unsigned grid,
+                            unsigned block, hipStream_t s) {
+  hipLaunchKernelGGL((k_binop_std<E, M, RZ, OPC>), dim3(grid), dim3(block), 0, s,
+                     static_cast<const uint8_t*>(a), static_cast<const uint8_t*>(b), static_cast<uint8_t*>(c),
+                     n, negb);
+  return hipGetLastError();
+}
+
+template <int E, int M>
+void register_format() {
+  Registry& r = registry();
+  r.binop[E][M][0][0][0] = launch_binop<E, M, false, 0, 1>;
+  r.binop[E][M][0][1][0] = launch_binop<E, M, true, 0, 1>;
+  r.binop[E][M][1][0][0] = launch_binop<E, M, false, 1, 1>;
+  r.binop[E][M][1][1][0] = launch_binop<E, M, true, 1, 1>;
+  r.binop[E][M][0][0][1] = launch_binop<E, M, false, 0, 2>;
+  r.binop[E][M][0][1][1] = launch_binop<E, M, true, 0, 2>;
+  r.binop[E][M][1][0][1] = launch_binop<E, M, false, 1, 2>;
+  r.binop[E][M][1][1][1] = launch_binop<E, M, true, 1, 2>;
+  r.std_op[E][M][0][0] = launch_binop_std<E, M, false, 0>;
+  r.std_op[E][M][0][1] = launch_binop_std<E, M, true, 0>;
+  r.std_op[E][M][1][0] = launch_binop_std<E, M, false, 1>;
+  r.std_op[E][M][1][1] = launch_binop_std<E, M, true, 1>;
+}
+
+}  // namespace bfp

@@ -1,0 +1,320 @@
+// bfp_runtime.hip -- the C ABI of include/bfp.h: argument checks, dispatch
+// to the compiled kernel variants, launch configuration table.
+#include <hip/hip_runtime.h>
+
+#include <mutex>
+#include <stdio.h>
+#include <string.h>
+
+#include "bfp.h"
+#include "bfp_formats.hpp"
+#include "bfp_kernels.hpp"
+
+namespace bfp {
+
+Registry& registry() {
+  static Registry r;
+  return r;
+}
+
+namespace {
+
+// Elements per vector are limited so that a lane's byte offset inside one
+// plane fits in 32 bits (planes of at most 2^32 bytes).
+constexpr uint64_t kMaxN = 1ull << 36;
+
+bool format_ok(const bfp_format& f) {
+  if (f.pad != 0 || (f.round != BFP_RNE && f.round != BFP_RZ)) return false;
+  if (f.e < 2 || f.e > kMaxE || f.m < 1 || f.m > kMaxM) return false;
+  return registry().binop[f.e][f.m][0][0][0] != nullptr;
+}
+
+int bits_of(const bfp_format& f) { return 1 + f.e + f.m; }
+int cbytes_of(const bfp_format& f) {
+  const int B = bits_of(f);
+  return B <= 8 ? 1 : (B <= 16 ? 2 : 4);
+}
+uint64_t gpad_of(uint64_t n) {
+  const uint64_t g = (n + 31) / 32;
+  return (g + 63) / 64 * 64;
+}
+bool aligned16(const void* p) { return (reinterpret_cast<uintptr_t>(p) & 15u) == 0; }
+bool overlap(const void* a, size_t na, const void* b, size_t nb) {
+  const uintptr_t a0 = reinterpret_cast<uintptr_t>(a), b0 = reinterpret_cast<uintptr_t>(b);
+  return a0 < b0 + nb && b0 < a0 + na;
+}
+
+// Compute units of the current device (cached per device).
+int cu_count() {
+  static int cache[64] = {0};
+  int dev = 0;
+  if (hipGetDevice(&dev) != hipSuccess || dev < 0 || dev >= 64) return 256;
+  if (cache[dev] == 0) {
+    hipDeviceProp_t p;
+    if (hipGetDeviceProperties(&p, dev) != hipSuccess) return 256;
+    cache[dev] = p.multiProcessorCount > 0 ? p.multiProcessorCount : 256;
+  }
+  return cache[dev];
+}
+
+unsigned grid_for(uint64_t items, int block, int blocks_per_cu) {
+  uint64_t g = (items + block - 1) / block;
+  if (blocks_per_cu > 0) {
+    const uint64_t cap = (uint64_t)cu_count() * blocks_per_cu;
+    if (g > cap) g = cap;
+  }
+  if (g < 1) g = 1;
+  if (g > 0x7FFFFFFFull) g = 0x7FFFFFFFull;
+  return (unsigned)g;
+}
+
+// Launch configuration table: [opclass][e][m][round]
+std::mutex g_cfg_mu;
+bfp_launch g_cfg[2][9][24][2];
+bool g_cfg_init = false;
+
+void cfg_init_locked() {
+  if (g_cfg_init) return;
+  for (int o = 0; o < 2; ++o)
+    for (int e = 0; e < 9; ++e)
+      for (int m = 0; m < 24; ++m)
+        for (int r = 0; r < 2; ++r) {
+          bfp_launch& c = g_cfg[o][e][m][r];
+          c.words_per_lane = 1;
+          c.block = 256;
+          c.blocks_per_cu = 0;
+          c.pad = 0;
+        }
+  g_cfg_init = true;
+}
+
+bfp_launch cfg_get(int opc, const bfp_format& f) {
+  std::lock_guard<std::mutex> lk(g_cfg_mu);
+  cfg_init_locked();
+  return g_cfg[opc][f.e][f.m][f.round];
+}
+
+bool cfg_valid(const bfp_launch& c) {
+  if (c.pad != 0) return false;
+  if (c.words_per_lane != 1 && c.words_per_lane != 2) return false;
+  if (c.block != 64 && c.block != 128 && c.block != 256 && c.block != 512) return false;
+  if (c.blocks_per_cu < 0 || c.blocks_per_cu > 64) return false;
+  return true;
+}
+
+bfp_status hip_status(hipError_t e) { return e == hipSuccess ? BFP_OK : BFP_E_HIP; }
+
+typedef hipError_t (*PackLauncher)(const void*, void*, uint64_t, uint64_t, int, unsigned, unsigned, hipStream_t);
+
+template <int C, int R>
+hipError_t launch_pack(const void* src, void* dst, uint64_t n, uint64_t gpad, int B, unsigned grid,
+                       unsigned block, hipStream_t s) {
+  hipLaunchKernelGGL((k_pack<C, R>), dim3(grid), dim3(block), 0, s, static_cast<const uint8_t*>(src),
+                     static_cast<uint32_t*>(dst), n, gpad, B);
+  return hipGetLastError();
+}
+template <int C, int R>
+hipError_t launch_unpack(const void* src, void* dst, uint64_t n, uint64_t gpad, int B, unsigned grid,
+                         unsigned block, hipStream_t s) {
+  hipLaunchKernelGGL((k_unpack<C, R>), dim3(grid), dim3(block), 0, s, static_cast<const uint32_t*>(src),
+                     static_cast<uint8_t*>(dst), n, gpad, B);
+  return hipGetLastError();
+}
+
+bfp_status check_op(int op) { return (op == BFP_ADD || op == BFP_SUB || op == BFP_MUL) ? BFP_OK : BFP_E_OP; }
+
+}  // namespace
+}  // namespace bfp
+
+using namespace bfp;
+
+extern "C" {
+
+const char* bfp_status_string(bfp_status s) {
+  switch (s) {
+    case BFP_OK: return "ok";
+    case BFP_E_FORMAT: return "unsupported format (e, m) or rounding mode";
+    case BFP_E_NULL: return "null pointer";
+    case BFP_E_ALIGN: return "pointer not 16-byte aligned";
+    case BFP_E_OP: return "unknown operation";
+    case BFP_E_HIP: return "HIP runtime error";
+    case BFP_E_ARG: return "invalid argument";
+    case BFP_E_ALIAS: return "input and output overlap";
+    case BFP_E_BUDGET: return "memory budget exceeded";
+    case BFP_E_NOMEM: return "out of memory";
+    case BFP_E_NODEV: return "no usable device";
+    default: return "unknown status";
+  }
+}
+
+const char* bfp_version(void) { return "0.1.0"; }
+
+int bfp_format_supported(bfp_format f) { return format_ok(f) ? 1 : 0; }
+
+size_t bfp_container_bytes(bfp_format f) { return format_ok(f) ? (size_t)cbytes_of(f) : 0; }
+
+uint64_t bfp_plane_stride_words(uint64_t n) { return gpad_of(n); }
+
+size_t bfp_bitslice_bytes(bfp_format f, uint64_t n) {
+  if (!format_ok(f)) return 0;
+  return (size_t)bits_of(f) * gpad_of(n) * 4u;
+}
+
+bfp_status bfp_pack(bfp_format f, const void* std_in, void* bs_out, uint64_t n, void* stream) {
+  if (!format_ok(f)) return BFP_E_FORMAT;
+  if (n == 0) return BFP_OK;
+  if (n > kMaxN) return BFP_E_ARG;
+  if (!std_in || !bs_out) return BFP_E_NULL;
+  if (!aligned16(std_in) || !aligned16(bs_out)) return BFP_E_ALIGN;
+  const int C = cbytes_of(f), B = bits_of(f);
+  const uint64_t gpad = gpad_of(n);
+  if (overlap(std_in, n * C, bs_out, (size_t)B * gpad * 4)) return BFP_E_ALIAS;
+  const int block = 256;
+  const unsigned grid = grid_for(gpad, block, 0);
+  PackLauncher L = C == 1 ? launch_pack<1, 1> : (C == 2 ? launch_pack<2, 1> : launch_pack<4, 1>);
+  return hip_status(L(std_in, bs_out, n, gpad, B, grid, block, (hipStream_t)stream));
+}
+
+bfp_status bfp_unpack(bfp_format f, const void* bs_in, void* std_out, uint64_t n, void* stream) {
+  if (!format_ok(f)) return BFP_E_FORMAT;
+  if (n == 0) return BFP_OK;
+  if (n > kMaxN) return BFP_E_ARG;
+  if (!bs_in || !std_out) return BFP_E_NULL;
+  if (!aligned16(bs_in) || !aligned16(std_out)) return BFP_E_ALIGN;
+  const int C = cbytes_of(f), B = bits_of(f);
+  const uint64_t gpad = gpad_of(n);
+  if (overlap(std_out, n * C, bs_in, (size_t)B * gpad * 4)) return BFP_E_ALIAS;
+  const int block = 256;
+  const unsigned grid = grid_for((n + 31) / 32, block, 0);
+  PackLauncher L = C == 1 ? launch_unpack<1, 1> : (C == 2 ? launch_unpack<2, 1> : launch_unpack<4, 1>);
+  return hip_status(L(bs_in, std_out, n, gpad, B, grid, block, (hipStream_t)stream));
+}
+
+bfp_status bfp_binop(int op, bfp_format f, const void* a, const void* b, void* c, uint64_t n, void* stream) {
+  bfp_status st = check_op(op);
+  if (st != BFP_OK) return st;
+  if (!format_ok(f)) return BFP_E_FORMAT;
+  if (n == 0) return BFP_OK;
+  if (n > kMaxN) return BFP_E_ARG;
+  if (!a || !b || !c) return BFP_E_NULL;
+  if (!aligned16(a) || !aligned16(b) || !aligned16(c)) return BFP_E_ALIGN;
+  const uint64_t gpad = gpad_of(n);
+  const size_t bytes = (size_t)bits_of(f) * gpad * 4;
+  if ((c != a && overlap(c, bytes, a, bytes)) || (c != b && overlap(c, bytes, b, bytes))) return BFP_E_ALIAS;
+  const int opc = op == BFP_MUL ? 1 : 0;
+  const bfp_launch cfg = cfg_get(opc, f);
+  BinopLauncher L = registry().binop[f.e][f.m][opc][f.round][cfg.words_per_lane - 1];
+  if (!L) return BFP_E_FORMAT;
+  const unsigned grid = grid_for(gpad / cfg.words_per_lane, cfg.block, cfg.blocks_per_cu);
+  const uint32_t negb = op == BFP_SUB ? 0xFFFFFFFFu : 0u;
+  return hip_status(L(a, b, c, gpad, negb, grid, (unsigned)cfg.block, (hipStream_t)stream));
+}
+
+bfp_status bfp_add(bfp_format f, const void* a, const void* b, void* c, uint64_t n, void* stream) {
+  return bfp_binop(BFP_ADD, f, a, b, c, n, stream);
+}
+bfp_status bfp_sub(bfp_format f, const void* a, const void* b, void* c, uint64_t n, void* stream) {
+  return bfp_binop(BFP_SUB, f, a, b, c, n, stream);
+}
+bfp_status bfp_mul(bfp_format f, const void* a, const void* b, void* c, uint64_t n, void* stream) {
+  return bfp_binop(BFP_MUL, f, a, b, c, n, stream);
+}
+
+bfp_status bfp_binop_std(int op, bfp_format f, const void* a, const void* b, void* c, uint64_t n,
+                         void* stream) {
+  bfp_status st = check_op(op);
+  if (st != BFP_OK) return st;
+  if (!format_ok(f)) return BFP_E_FORMAT;
+  if (n == 0) return BFP_OK;
+  if (n > kMaxN) return BFP_E_ARG;
+  if (!a || !b || !c) return BFP_E_NULL;
+  if (!aligned16(a) || !aligned16(b) || !aligned16(c)) return BFP_E_ALIGN;
+  const size_t bytes = (size_t)n * cbytes_of(f);
+  if ((c != a && overlap(c, bytes, a, bytes)) || (c != b && overlap(c, bytes, b, bytes))) return BFP_E_ALIAS;
+  const int opc = op == BFP_MUL ? 1 : 0;
+  StdLauncher L = registry().std_op[f.e][f.m][opc][f.round];
+  if (!L) return BFP_E_FORMAT;
+  const int block = 256;
+  const unsigned grid = grid_for((n + 31) / 32, block, 0);
+  const uint32_t negb = op == BFP_SUB ? 0xFFFFFFFFu : 0u;
+  return hip_status(L(a, b, c, n, negb, grid, block, (hipStream_t)stream));
+}
+
+bfp_status bfp_launch_get(int op, bfp_format f, bfp_launch* out) {
+  bfp_status st = check_op(op);
+  if (st != BFP_OK) return st;
+  if (!format_ok(f)) return BFP_E_FORMAT;
+  if (!out) return BFP_E_NULL;
+  *out = cfg_get(op == BFP_MUL ? 1 : 0, f);
+  return BFP_OK;
+}
+
+bfp_status bfp_launch_set(int op, bfp_format f, const bfp_launch* cfg) {
+  bfp_status st = check_op(op);
+  if (st != BFP_OK) return st;
+  if (!format_ok(f)) return BFP_E_FORMAT;
+  if (!cfg) return BFP_E_NULL;
+  if (!cfg_valid(*cfg)) return BFP_E_ARG;
+  std::lock_guard<std::mutex> lk(g_cfg_mu);
+  cfg_init_locked();
+  g_cfg[op == BFP_MUL ? 1 : 0][f.e][f.m][f.round] = *cfg;
+  return BFP_OK;
+}
+
+bfp_status bfp_launch_load(const char* path) {
+  if (!path) return BFP_E_NULL;
+  FILE* fp = fopen(path, "r");
+  if (!fp) return BFP_E_ARG;
+  char line[256];
+  bfp_status st = BFP_OK;
+  while (fgets(line, sizeof line, fp)) {
+    if (line[0] == '#' || line[0] == '\n') continue;
+    int op, e, m, r, wpl, block, bpc;
+    if (sscanf(line, "%d %d %d %d %d %d %d", &op, &e, &m, &r, &wpl, &block, &bpc) != 7) {
+      st = BFP_E_ARG;
+      break;
+    }
+    bfp_format f;
+    f.e = (uint8_t)e;
+    f.m = (uint8_t)m;
+    f.round = (uint8_t)r;
+    f.pad = 0;
+    if (e < 0 || e > 255 || m < 0 || m > 255 || !format_ok(f)) continue;
+    bfp_launch c;
+    c.words_per_lane = wpl;
+    c.block = block;
+    c.blocks_per_cu = bpc;
+    c.pad = 0;
+    const bfp_status s2 = bfp_launch_set(op, f, &c);
+    if (s2 != BFP_OK) {
+      st = s2;
+      break;
+    }
+  }
+  fclose(fp);
+  return st;
+}
+
+bfp_status bfp_launch_save(const char* path) {
+  if (!path) return BFP_E_NULL;
+  FILE* fp = fopen(path, "w");
+  if (!fp) return BFP_E_ARG;
+  fprintf(fp, "# op e m round words_per_lane block blocks_per_cu\n");
+  {
+    std::lock_guard<std::mutex> lk(g_cfg_mu);
+    cfg_init_locked();
+    for (int o = 0; o < 2; ++o)
+      for (int e = 0; e < 9; ++e)
+        for (int m = 0; m < 24; ++m)
+          for (int r = 0; r < 2; ++r) {
+            if (!registry().binop[e][m][0][0][0]) continue;
+            const bfp_launch& c = g_cfg[o][e][m][r];
+            fprintf(fp, "%d %d %d %d %d %d %d\n", o == 1 ? BFP_MUL : BFP_ADD, e, m, r, c.words_per_lane, c.block,
+                    c.blocks_per_cu);
+          }
+  }
+  fclose(fp);
+  return BFP_OK;
+}
+
+}  // extern "C"

@@ -1,0 +1,105 @@
+"""The C ABI without a GPU: the library loads, exports every function that
+include/bfp.h declares, and rejects bad arguments before touching a device."""
+import ctypes
+import os
+import re
+import subprocess
+
+import pytest
+
+from paper_1602_04716_amd import bfp
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+HEADERS = [os.path.join(ROOT, "include", f) for f in sorted(os.listdir(os.path.join(ROOT, "include")))
+           if f.endswith(".h")]
+
+
+def declared():
+    names = set()
+    for h in HEADERS:
+        text = open(h).read()
+        text = re.sub(r"/\*.*?\*/", "", text, flags=re.S)
+        for m in re.finditer(r"\b(bfp_\w+)\s*\(", text):
+            names.add(m.group(1))
+    return sorted(names)
+
+
+def test_header_declares_functions():
+    assert "bfp_pack" in declared() and "bfp_binop" in declared()
+
+
+def test_every_declared_symbol_is_exported():
+    out = subprocess.check_output(["nm", "-D", "--defined-only", bfp.LIB_PATH], text=True)
+    exported = {line.split()[-1] for line in out.splitlines() if " T " in line}
+    missing = [n for n in declared() if n not in exported]
+    assert not missing, missing
+
+
+def test_binding_covers_header():
+    missing = [n for n in declared() if not hasattr(bfp, n)]
+    assert not missing, missing
+
+
+def test_sizing():
+    f = bfp.fmt(5, 10)
+    assert bfp.bfp_container_bytes(f) == 2
+    assert bfp.bfp_container_bytes(bfp.fmt(5, 2)) == 1
+    assert bfp.bfp_container_bytes(bfp.fmt(8, 23)) == 4
+    assert bfp.bfp_plane_stride_words(1) == 64
+    assert bfp.bfp_plane_stride_words(64 * 32) == 64
+    assert bfp.bfp_plane_stride_words(64 * 32 + 1) == 128
+    assert bfp.bfp_bitslice_bytes(f, 1 << 26) == 16 * (1 << 21) * 4
+    assert bfp.bfp_bitslice_bytes(bfp.fmt(7, 3), 10) == 0  # not compiled
+
+
+def test_supported_formats():
+    from paper_1602_04716_amd import inputs
+    for (e, m) in inputs.sweep_formats():
+        for r in (0, 1):
+            assert bfp.bfp_format_supported(bfp.fmt(e, m, r))
+    assert not bfp.bfp_format_supported(bfp.fmt(5, 2, 2))
+    assert not bfp.bfp_format_supported(bfp.bfp_format(5, 2, 0, 1))
+    assert not bfp.bfp_format_supported(bfp.fmt(9, 2))
+
+
+def test_argument_errors_before_any_device_work():
+    L = bfp.lib()
+    f = bfp.fmt(5, 10)
+    assert L.bfp_pack(bfp.fmt(7, 4), 16, 4096, 10, None) == -1          # format
+    assert L.bfp_pack(f, 0, 4096, 10, None) == -2                        # null
+    assert L.bfp_pack(f, 17, 4096, 10, None) == -3                       # alignment
+    assert L.bfp_pack(f, 4096, 4096, 10, None) == -7                     # overlap
+    assert L.bfp_pack(f, 0, 0, 0, None) == 0                             # n == 0
+    assert L.bfp_binop(3, f, 16, 32, 48, 1, None) == -4                  # op
+    assert L.bfp_binop(0, f, 16, 32, 0, 1, None) == -2
+    assert L.bfp_binop(0, f, 4096, 1 << 20, 4096 + 16, 100, None) == -7  # partial overlap
+    assert L.bfp_binop(0, f, 4096, 1 << 20, 0, 0, None) == 0
+    assert L.bfp_binop_std(2, bfp.fmt(5, 10, 3), 16, 32, 48, 1, None) == -1
+    assert L.bfp_unpack(f, 16, 32, 1 << 40, None) == -6                  # too long
+    assert bfp.bfp_status_string(-5).startswith("HIP")
+
+
+def test_launch_table_roundtrip(tmp_path):
+    f = bfp.fmt(6, 7, 1)
+    old = bfp.bfp_launch_get("mul", f)
+    bfp.bfp_launch_set("mul", f, 2, 128, 4)
+    c = bfp.bfp_launch_get("mul", f)
+    assert (c.words_per_lane, c.block, c.blocks_per_cu) == (2, 128, 4)
+    assert bfp.bfp_launch_get("mul", f).block == 128
+    p = str(tmp_path / "t.txt")
+    bfp.bfp_launch_save(p)
+    bfp.bfp_launch_set("mul", f, old.words_per_lane, old.block, old.blocks_per_cu)
+    bfp.bfp_launch_load(p)
+    assert bfp.bfp_launch_get("mul", f).block == 128
+    bfp.bfp_launch_set("mul", f, old.words_per_lane, old.block, old.blocks_per_cu)
+    with pytest.raises(bfp.BfpError):
+        bfp.bfp_launch_set("add", f, 3, 256, 0)
+    with pytest.raises(bfp.BfpError):
+        bfp.bfp_launch_set("add", f, 1, 100, 0)
+
+
+def test_gate_counts_positive():
+    for op in ("add", "sub", "mul"):
+        assert bfp.bfp_gate_count(op, bfp.fmt(5, 10)) > 100
+    assert bfp.bfp_gate_count("add", bfp.fmt(5, 10)) == bfp.bfp_gate_count("sub", bfp.fmt(5, 10))
+    assert bfp.bfp_gate_count("add", bfp.fmt(7, 3)) == -1

@@ -1,0 +1,211 @@
+"""GPU parity: the HIP path (through the C ABI) against the oracle, bit-exact.
+
+Every test calls libbfp through its Python binding; expected values come only
+from ``oracle`` (CPU).  Integer/bit work, so the bar is equality of every
+bit, including the zero padding of the bitslice layout.
+"""
+import numpy as np
+import pytest
+
+torch = pytest.importorskip("torch")
+
+import oracle
+from paper_1602_04716_amd import bfp, inputs
+
+pytestmark = pytest.mark.gpu
+
+FORMATS = inputs.sweep_formats()
+OPS = ["add", "sub", "mul"]
+NPAR = 70000 + 13  # 2188 words per plane: several blocks and a ragged last word
+
+
+@pytest.fixture(scope="module", autouse=True)
+def gpu():
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+    bfp.lib()
+    oracle.build()
+    yield
+    torch.cuda.synchronize()
+
+
+def _dev(x):
+    return torch.from_numpy(np.ascontiguousarray(x)).cuda()
+
+
+def _host(t):
+    torch.cuda.synchronize()
+    return t.cpu().numpy()
+
+
+def _operands(e, m, n, seed):
+    """Half format-shaped values, a quarter uniform bit patterns (NaN/Inf,
+    upper garbage bits excluded by the container), a quarter near-cancelling."""
+    dt = inputs.container_dtype(e, m)
+    B = 1 + e + m
+    rng = np.random.default_rng(seed)
+    a = inputs.sweep_operands(e, m, n, seed).astype(np.uint64)
+    b = inputs.sweep_operands(e, m, n, seed + 1).astype(np.uint64)
+    q = n // 4
+    a[:q] = rng.integers(0, 1 << B, q, dtype=np.uint64)
+    b[:q] = rng.integers(0, 1 << B, q, dtype=np.uint64)
+    b[q:2 * q] = ((a[q:2 * q] + rng.integers(0, 3, q).astype(np.uint64)) % (1 << B)) ^ (1 << (e + m))
+    return a.astype(dt), b.astype(dt)
+
+
+def _set_wpl(op, f, wpl):
+    bfp.bfp_launch_set(op, f, wpl, 256, 0)
+
+
+@pytest.mark.parametrize("e,m", FORMATS)
+def test_pack_unpack(e, m):
+    f = bfp.fmt(e, m)
+    dt = inputs.container_dtype(e, m)
+    rng = np.random.default_rng(e * 100 + m)
+    for n in (1, 31, 33, 64 * 32 + 5, NPAR):
+        x = rng.integers(0, np.iinfo(dt).max, n, dtype=np.uint64, endpoint=True).astype(dt)
+        bs = bfp.pack(f, _dev(x))
+        want = oracle.pack(e, m, x)
+        assert np.array_equal(_host(bs), want), ("pack", n)
+        back = bfp.unpack(f, bs, n)
+        mask = (1 << (1 + e + m)) - 1
+        assert np.array_equal(_host(back), (x.astype(np.uint64) & mask).astype(dt)), ("unpack", n)
+
+
+@pytest.mark.parametrize("e,m", FORMATS)
+def test_binop_bitslice(e, m):
+    a, b = _operands(e, m, NPAR, 7 * e + m)
+    da, db = _dev(a), _dev(b)
+    for mode in (0, 1):
+        f = bfp.fmt(e, m, mode)
+        pa, pb = bfp.pack(f, da), bfp.pack(f, db)
+        for op in OPS:
+            want = oracle.binop(op, e, m, mode, a, b, nthreads=8)
+            want_planes = oracle.pack(e, m, want)
+            for wpl in (1, 2):
+                _set_wpl(op, f, wpl)
+                pc = bfp.empty_bitslice(f, NPAR)
+                bfp.bfp_binop(op, f, pa, pb, pc, NPAR)
+                got = _host(pc)
+                if not np.array_equal(got, want_planes):
+                    res = oracle.unpack(e, m, got, NPAR).astype(np.uint32)
+                    bad = np.flatnonzero(res != want)
+                    k = bad[0] if bad.size else -1
+                    pytest.fail("(%d,%d) %s mode %d wpl %d: %d bad elements, e.g. a=%#x b=%#x got=%#x want=%#x"
+                                % (e, m, op, mode, wpl, bad.size, a[k], b[k], res[k], want[k]))
+            _set_wpl(op, f, 1)
+            out = bfp.unpack(f, pc, NPAR)
+            assert np.array_equal(_host(out).astype(np.uint32), want)
+
+
+@pytest.mark.parametrize("e,m", FORMATS)
+def test_binop_std_fused(e, m):
+    a, b = _operands(e, m, NPAR, 11 * e + m)
+    da, db = _dev(a), _dev(b)
+    for mode in (0, 1):
+        f = bfp.fmt(e, m, mode)
+        for op in OPS:
+            want = oracle.binop(op, e, m, mode, a, b, nthreads=8)
+            dc = torch.empty_like(da)
+            bfp.bfp_binop_std(op, f, da, db, dc, NPAR)
+            got = _host(dc).astype(np.uint32)
+            bad = np.flatnonzero(got != want)
+            assert bad.size == 0, ((e, m, op, mode), hex(a[bad[0]]), hex(b[bad[0]]), hex(got[bad[0]]),
+                                   hex(want[bad[0]]))
+
+
+SMALL = [(e, m) for (e, m) in FORMATS if 1 + e + m <= 8]
+
+
+@pytest.mark.parametrize("e,m", SMALL)
+def test_exhaustive_small_formats(e, m):
+    """All 2^B x 2^B pairs (the 256 x 256 check at B = 8), both paths."""
+    B = 1 + e + m
+    a, b = inputs.exhaustive_pairs(B)
+    a8, b8 = a.astype(np.uint8), b.astype(np.uint8)
+    n = a.size
+    da, db = _dev(a8), _dev(b8)
+    for mode in (0, 1):
+        f = bfp.fmt(e, m, mode)
+        pa, pb = bfp.pack(f, da), bfp.pack(f, db)
+        for op in OPS:
+            want = oracle.binop(op, e, m, mode, a, b, nthreads=8)
+            dc = torch.empty_like(da)
+            bfp.bfp_binop_std(op, f, da, db, dc, n)
+            assert np.array_equal(_host(dc).astype(np.uint32), want), ("std", op, mode)
+            pc = bfp.empty_bitslice(f, n)
+            bfp.bfp_binop(op, f, pa, pb, pc, n)
+            assert np.array_equal(_host(bfp.unpack(f, pc, n)).astype(np.uint32), want), ("bs", op, mode)
+
+
+def test_plain_add_5_2_workload():
+    """65,536-element (5,2) add, 32-lane words, pack + add + unpack (fused and
+    three-kernel), uniform patterns without NaN/Inf."""
+    e, m = 5, 2
+    n = 65536
+    a = inputs.plain_8bit(n, seed=1)
+    b = inputs.plain_8bit(n, seed=101)
+    want = oracle.binop("add", e, m, 0, a, b)
+    f = bfp.fmt(e, m)
+    da, db = _dev(a), _dev(b)
+    dc = torch.empty_like(da)
+    bfp.bfp_binop_std("add", f, da, db, dc, n)
+    assert np.array_equal(_host(dc).astype(np.uint32), want)
+    _set_wpl("add", f, 1)
+    pa, pb = bfp.pack(f, da), bfp.pack(f, db)
+    pc = bfp.empty_bitslice(f, n)
+    bfp.bfp_add(f, pa, pb, pc, n)
+    assert np.array_equal(_host(bfp.unpack(f, pc, n)).astype(np.uint32), want)
+
+
+def test_in_place_and_zero_length():
+    e, m = 5, 10
+    f = bfp.fmt(e, m)
+    a, b = _operands(e, m, 5000, 3)
+    want = oracle.binop("mul", e, m, 0, a, b)
+    pa, pb = bfp.pack(f, _dev(a)), bfp.pack(f, _dev(b))
+    bfp.bfp_mul(f, pa, pb, pa, 5000)  # c == a
+    assert np.array_equal(_host(bfp.unpack(f, pa, 5000)).astype(np.uint32), want)
+    bfp.bfp_add(f, pa, pb, pa, 0)  # no-op
+    da = _dev(a)
+    bfp.bfp_binop_std("sub", f, da, _dev(b), da, 5000)  # c == a, fused path
+    assert np.array_equal(_host(da).astype(np.uint32), oracle.binop("sub", e, m, 0, a, b))
+
+
+@pytest.mark.parametrize("e,m", [(5, 10), (8, 7)])
+def test_full_size_2_26(e, m):
+    """2^26 elements, 64-element lane words (the benchmark's launch
+    configuration); sampled outputs against the oracle, and every output of
+    (5,10) against the GPU's native binary16 arithmetic, (8,7) against
+    bfloat16 computed in float32 (both correctly rounded to nearest-even)."""
+    n = 1 << 26
+    a = inputs.scaled_normal(e, m, n, 2)
+    b = inputs.scaled_normal(e, m, n, 3)
+    f = bfp.fmt(e, m)
+    da, db = _dev(a), _dev(b)
+    pa, pb = bfp.pack(f, da), bfp.pack(f, db)
+    rng = np.random.default_rng(5)
+    idx = np.concatenate([np.arange(4096), np.arange(n - 4096, n), rng.integers(0, n, 200000)])
+    for op in OPS:
+        bfp.bfp_launch_set(op, f, 2, 256, 0)
+        pc = bfp.empty_bitslice(f, n)
+        bfp.bfp_binop(op, f, pa, pb, pc, n)
+        out = bfp.unpack(f, pc, n)
+        got = _host(out).astype(np.uint32)
+        want = oracle.binop(op, e, m, 0, a[idx], b[idx], nthreads=8)
+        assert np.array_equal(got[idx], want), op
+        ta, tb = da.view(torch.int16), db.view(torch.int16)
+        if (e, m) == (5, 10):
+            ha, hb = ta.view(torch.float16), tb.view(torch.float16)
+        else:
+            ha, hb = ta.view(torch.bfloat16).float(), tb.view(torch.bfloat16).float()
+        r = {"add": ha + hb, "sub": ha - hb, "mul": ha * hb}[op]
+        if (e, m) == (8, 7):
+            r = r.to(torch.bfloat16)
+        nat = r.view(torch.int16).cpu().numpy().view(np.uint16).astype(np.uint32)
+        E = (nat >> m) & ((1 << e) - 1)
+        nat_nan = (E == (1 << e) - 1) & ((nat & ((1 << m) - 1)) != 0)
+        mism = (nat != got) & ~nat_nan
+        assert not mism.any(), (op, int(mism.sum()))
+        del pc, out
+    torch.cuda.synchronize()
