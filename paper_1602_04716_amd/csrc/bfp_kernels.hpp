@@ -5,7 +5,14 @@
 // plane (W = 32 R elements) and reads them with one coalesced load per
 // plane: consecutive lanes read consecutive words, so each plane load of a
 // wave is one contiguous 256 R-byte segment.  The circuit runs entirely in
-// VGPRs; nothing here is a contraction, so there is no MFMA and no LDS.
+// VGPRs; nothing here is a contraction, so there is no MFMA.
+//
+// Memory policy (measured on MI355X): plane loads are ordinary cached loads,
+// plane stores are non-temporal (streaming) stores; the standard-layout side
+// of pack uses ordinary loads (a lane's 32 C contiguous bytes span partial
+// cache lines that neighbouring lanes' loads reuse), and unpack stages its
+// output through LDS so that every global store of a wave writes one
+// contiguous 1 KiB segment.
 #pragma once
 #include <hip/hip_runtime.h>
 
@@ -21,14 +28,14 @@ template <int R>
 __device__ __forceinline__ WordR<R> ld_words(const uint32_t* p) {
   WordR<R> v;
   if constexpr (R == 1) {
-    v.w[0] = __builtin_nontemporal_load(p);
+    v.w[0] = *p;
   } else if constexpr (R == 2) {
-    const u32x2 t = __builtin_nontemporal_load(reinterpret_cast<const u32x2*>(p));
+    const u32x2 t = *reinterpret_cast<const u32x2*>(p);
     v.w[0] = t.x;
     v.w[1] = t.y;
   } else {
     static_assert(R == 4, "R must be 1, 2 or 4");
-    const u32x4 t = __builtin_nontemporal_load(reinterpret_cast<const u32x4*>(p));
+    const u32x4 t = *reinterpret_cast<const u32x4*>(p);
     v.w[0] = t.x;
     v.w[1] = t.y;
     v.w[2] = t.z;
@@ -101,7 +108,7 @@ __device__ __forceinline__ void load_std(const uint8_t* src, uint64_t e0, uint64
     for (int r = 0; r < R; ++r) {
 #pragma unroll
       for (int q = 0; q < 2 * C; ++q) {
-        const u32x4 v = __builtin_nontemporal_load(p + r * 2 * C + q);
+        const u32x4 v = p[r * 2 * C + q];
         in[r][4 * q + 0] = v.x;
         in[r][4 * q + 1] = v.y;
         in[r][4 * q + 2] = v.z;
@@ -141,7 +148,7 @@ __device__ __forceinline__ void store_std(uint8_t* dst, uint64_t e0, uint64_t n,
         v.y = out[r][4 * q + 1];
         v.z = out[r][4 * q + 2];
         v.w = out[r][4 * q + 3];
-        __builtin_nontemporal_store(v, p + r * 2 * C + q);
+        p[r * 2 * C + q] = v;
       }
     }
   } else {
@@ -185,34 +192,60 @@ __global__ void __launch_bounds__(512) k_pack(const uint8_t* src, uint32_t* plan
   }
 }
 
-// Bitslice -> standard for the ceil(n/32) words that hold elements.
-template <int C, int R>
+// Bitslice -> standard.  Work goes in wave tiles of 64 groups (2048
+// elements): a lane loads word g of each plane (coalesced) and transposes its
+// group in registers.  A tile wholly below n is written through LDS, so that
+// each store instruction of the wave covers one contiguous 1 KiB (the lane
+// chunks are XOR-swizzled in LDS to spread banks); the ragged last tile
+// stores element by element.  Loops run per block so that every thread of a
+// block meets the same barriers.  Dynamic LDS: (blockDim / 64) * 2048 C bytes.
+template <int C>
 __global__ void __launch_bounds__(512) k_unpack(const uint32_t* planes, uint8_t* dst, uint64_t n,
                                                 uint64_t gpad, int B) {
+  extern __shared__ u32x4 unpack_lds[];
+  constexpr int CH = 2 * C;  // 16-byte chunks per lane
+  const int nw = blockDim.x >> 6;
+  const int wave = threadIdx.x >> 6, lane = threadIdx.x & 63;
+  u32x4* tile = unpack_lds + wave * 64 * CH;
   const uint64_t groups = (n + 31) / 32;
-  const uint64_t nt = (groups + R - 1) / R;
-  const uint64_t stride = (uint64_t)gridDim.x * blockDim.x;
-  for (uint64_t t = (uint64_t)blockIdx.x * blockDim.x + threadIdx.x; t < nt; t += stride) {
-    const uint64_t g0 = t * R;
-    WordR<R> pl[8 * C];
+  const uint64_t tiles = (groups + 63) / 64;
+  const uint64_t block_tiles = (tiles + nw - 1) / nw;
+  for (uint64_t bt = blockIdx.x; bt < block_tiles; bt += gridDim.x) {
+    const uint64_t t = bt * nw + wave;
+    const bool active = t < tiles;
+    const bool full = (t + 1) * 2048 <= n;
+    uint32_t out[1][8 * C];
+    if (active) {
+      const uint64_t g = t * 64 + lane;  // < gpad: gpad = 64 * tiles
+      uint32_t pl[8 * C];
 #pragma unroll
-    for (int k = 0; k < 8 * C; ++k) {
-      if (k < B) {
-        pl[k] = ld_words<R>(planes + (uint64_t)k * gpad + g0);
+      for (int k = 0; k < 8 * C; ++k) pl[k] = (k < B) ? planes[(uint64_t)k * gpad + g] : 0u;
+      transpose_unpack<C>(pl, out[0]);
+      if (full) {
+#pragma unroll
+        for (int q = 0; q < CH; ++q) {
+          u32x4 v;
+          v.x = out[0][4 * q + 0];
+          v.y = out[0][4 * q + 1];
+          v.z = out[0][4 * q + 2];
+          v.w = out[0][4 * q + 3];
+          tile[lane * CH + (q ^ (lane & (CH - 1)))] = v;
+        }
       } else {
-#pragma unroll
-        for (int r = 0; r < R; ++r) pl[k].w[r] = 0u;
+        store_std<C, 1>(dst, g * 32, n, out);
       }
     }
-    uint32_t out[R][8 * C];
+    __syncthreads();
+    if (active && full) {
+      u32x4* p = reinterpret_cast<u32x4*>(dst + t * 2048 * C);
 #pragma unroll
-    for (int r = 0; r < R; ++r) {
-      uint32_t tmp[8 * C];
-#pragma unroll
-      for (int k = 0; k < 8 * C; ++k) tmp[k] = pl[k].w[r];
-      transpose_unpack<C>(tmp, out[r]);
+      for (int j = 0; j < CH; ++j) {
+        const int idx = lane + 64 * j;
+        const int owner = idx / CH, q = idx % CH;
+        p[idx] = tile[owner * CH + (q ^ (owner & (CH - 1)))];
+      }
     }
-    store_std<C, R>(dst, g0 * 32, n, out);
+    __syncthreads();
   }
 }
 

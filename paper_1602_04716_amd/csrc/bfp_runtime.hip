@@ -73,6 +73,10 @@ std::mutex g_cfg_mu;
 bfp_launch g_cfg[2][9][24][2];
 bool g_cfg_init = false;
 
+// Defaults before tuning (measured on MI355X at 2^26 elements): circuits
+// that move more bytes than they compute run best with 64-element lane words
+// (two dwords per lane per plane); 8-bit formats with 32-element words in
+// blocks of 128; circuits with many gates per bit (VALU-bound) with 32.
 void cfg_init_locked() {
   if (g_cfg_init) return;
   for (int o = 0; o < 2; ++o)
@@ -80,8 +84,10 @@ void cfg_init_locked() {
       for (int m = 0; m < 24; ++m)
         for (int r = 0; r < 2; ++r) {
           bfp_launch& c = g_cfg[o][e][m][r];
-          c.words_per_lane = 1;
-          c.block = 256;
+          const int B = 1 + e + m;
+          const bool valu_heavy = o == 1 && m >= 15;
+          c.words_per_lane = (B <= 8 || valu_heavy) ? 1 : 2;
+          c.block = B <= 8 ? 128 : 256;
           c.blocks_per_cu = 0;
           c.pad = 0;
         }
@@ -113,10 +119,11 @@ hipError_t launch_pack(const void* src, void* dst, uint64_t n, uint64_t gpad, in
                      static_cast<uint32_t*>(dst), n, gpad, B);
   return hipGetLastError();
 }
-template <int C, int R>
+template <int C>
 hipError_t launch_unpack(const void* src, void* dst, uint64_t n, uint64_t gpad, int B, unsigned grid,
                          unsigned block, hipStream_t s) {
-  hipLaunchKernelGGL((k_unpack<C, R>), dim3(grid), dim3(block), 0, s, static_cast<const uint32_t*>(src),
+  const size_t lds = (size_t)(block / 64) * 2048 * C;
+  hipLaunchKernelGGL((k_unpack<C>), dim3(grid), dim3(block), lds, s, static_cast<const uint32_t*>(src),
                      static_cast<uint8_t*>(dst), n, gpad, B);
   return hipGetLastError();
 }
@@ -185,8 +192,9 @@ bfp_status bfp_unpack(bfp_format f, const void* bs_in, void* std_out, uint64_t n
   const uint64_t gpad = gpad_of(n);
   if (overlap(std_out, n * C, bs_in, (size_t)B * gpad * 4)) return BFP_E_ALIAS;
   const int block = 256;
-  const unsigned grid = grid_for((n + 31) / 32, block, 0);
-  PackLauncher L = C == 1 ? launch_unpack<1, 1> : (C == 2 ? launch_unpack<2, 1> : launch_unpack<4, 1>);
+  const uint64_t tiles = ((n + 31) / 32 + 63) / 64;  // 64 groups per wave tile
+  const unsigned grid = grid_for(tiles * 64, block, 0);
+  PackLauncher L = C == 1 ? launch_unpack<1> : (C == 2 ? launch_unpack<2> : launch_unpack<4>);
   return hip_status(L(bs_in, std_out, n, gpad, B, grid, block, (hipStream_t)stream));
 }
 
