@@ -43,7 +43,48 @@ def parse():
     ap.add_argument("--n-log2", type=int, default=26)
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--kernel-reps", type=int, default=20)
+    ap.add_argument("--no-batched", action="store_true")
+    ap.add_argument("--batched-reps", type=int, default=10)
     return ap.parse_args()
+
+
+def bench_batched(torch, bfp, dev, reps):
+    """4096 vectors, lengths log-uniform in [1024, 2^20], random format of the
+    40-format sweep and random op: one graph launch of the persistent kernel
+    vs one launch per vector (both timed with events on one stream)."""
+    from paper_1602_04716_amd import inputs, workloads
+    specs = inputs.batch_tasks(4096, seed=4)
+    bt = workloads.build_batch(specs, seed=4, device=dev)
+    plan = bfp.BatchPlan(bt.tasks)
+    stream = torch.cuda.current_stream()
+    ops_alg = 0.0
+    for (n, e, m, op, rnd) in bt.specs:
+        ops_alg += bfp.bfp_gate_count(op, bfp.fmt(e, m, rnd)) * ((n + 31) // 32)
+
+    def timed(fn):
+        fn()
+        torch.cuda.synchronize()
+        ev0 = torch.cuda.Event(enable_timing=True)
+        ev1 = torch.cuda.Event(enable_timing=True)
+        ev0.record(stream)
+        for _ in range(reps):
+            fn()
+        ev1.record(stream)
+        torch.cuda.synchronize()
+        return ev0.elapsed_time(ev1) / reps
+
+    g_ms = timed(lambda: plan.run(stream))
+    e_ms = timed(lambda: plan.run_eager(stream))
+    v_ms = timed(lambda: plan.run_per_vector(stream))
+    info = plan.info()
+    plan.close()
+    nbytes = bt.bytes_moved()
+    elems = bt.elements()
+    return {"tasks": len(bt.specs), "elements": elems, "bytes": nbytes, "chunks": info["chunks"],
+            "grid": info["grid"], "graph_ms": g_ms, "eager_persistent_ms": e_ms, "per_vector_ms": v_ms,
+            "speedup_vs_per_vector": v_ms / g_ms, "elements_per_s": elems / (g_ms * 1e-3),
+            "per_vector_elements_per_s": elems / (v_ms * 1e-3),
+            "hbm_frac": nbytes / (g_ms * 1e-3) / HBM_PEAK, "valu_frac": ops_alg / (g_ms * 1e-3) / VALU_PEAK}
 
 
 def cpu_baseline(sample_log2=24):
@@ -193,6 +234,8 @@ def main():
         "roofline": roof,
         "kernels": kernels,
     }
+    if not args.no_batched:
+        res["batched"] = bench_batched(torch, bfp, dev, args.batched_reps)
     if not args.no_cpu_baseline:
         res["cpu_baseline"] = cpu_baseline()
     print(json.dumps(res), flush=True)

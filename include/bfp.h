@@ -171,6 +171,52 @@ bfp_status bfp_launch_save(const char* path);
  * is not compiled. */
 long bfp_gate_count(int op, bfp_format f);
 
+/* ---- batched persistent launch --------------------------------------------- */
+/* Many vectors of uneven length and mixed formats in one persistent kernel,
+ * captured once in a HIP graph.  (Not in the paper, whose operations act on
+ * one vector type at a time; this batches its Section 4 operations.)
+ *
+ * A task is c = a op b on bitslice vectors of n elements in format f, with
+ * the same layout and rules as bfp_binop (c may equal a or b).  The plan
+ * copies the descriptors to device memory and captures the graph at
+ * creation; the caller keeps every a, b, c allocated and unmoved for the
+ * plan's lifetime.  Runs of one plan must not overlap in time (they share
+ * the plan's work counter): issue them on one stream, or synchronise. */
+typedef struct {
+  const void* a; /* device, bitslice, format f, n elements */
+  const void* b;
+  void* c;
+  uint64_t n;
+  bfp_format f;
+  int32_t op; /* BFP_ADD, BFP_SUB or BFP_MUL */
+} bfp_task;
+
+typedef struct bfp_batch_plan bfp_batch_plan;
+
+/* Validate `count` tasks, cut them into chunks sorted by circuit variant,
+ * upload the descriptors and capture the graph on the current device.
+ * Errors: BFP_E_ARG (count 0, n 0), BFP_E_FORMAT, BFP_E_OP, BFP_E_NULL,
+ * BFP_E_ALIGN, BFP_E_NOMEM, BFP_E_HIP.  On error *out is NULL. */
+bfp_status bfp_batch_plan_create(const bfp_task* tasks, uint32_t count, bfp_batch_plan** out);
+
+/* Launch the captured graph on `stream` (one hipGraphLaunch). */
+bfp_status bfp_batch_run(bfp_batch_plan* plan, void* stream);
+
+/* The same two kernels launched directly on `stream`, without the graph. */
+bfp_status bfp_batch_run_eager(bfp_batch_plan* plan, void* stream);
+
+/* Baseline: one bfp_binop launch per task, in task order, on `stream`. */
+bfp_status bfp_batch_run_per_vector(bfp_batch_plan* plan, void* stream);
+
+/* Chunks, persistent grid size and total plane words per operand
+ * (sum over tasks of B * G_pad); any pointer may be NULL. */
+bfp_status bfp_batch_plan_info(const bfp_batch_plan* plan, uint32_t* nchunks, uint32_t* grid,
+                               uint64_t* words_per_operand);
+
+/* Free the plan's device memory and graph (NULL is a no-op).  Wait for its
+ * runs to finish first. */
+void bfp_batch_plan_destroy(bfp_batch_plan* plan);
+
 #ifdef __cplusplus
 }
 #endif

@@ -38,6 +38,11 @@ class bfp_launch(ctypes.Structure):
             self.words_per_lane, self.block, self.blocks_per_cu)
 
 
+class bfp_task(ctypes.Structure):
+    _fields_ = [("a", ctypes.c_void_p), ("b", ctypes.c_void_p), ("c", ctypes.c_void_p), ("n", ctypes.c_uint64),
+                ("f", bfp_format), ("op", ctypes.c_int32)]
+
+
 class BfpError(RuntimeError):
     def __init__(self, status: int, where: str):
         self.status = status
@@ -71,6 +76,14 @@ _SIGS = {
     "bfp_launch_load": (ctypes.c_int, [ctypes.c_char_p]),
     "bfp_launch_save": (ctypes.c_int, [ctypes.c_char_p]),
     "bfp_gate_count": (ctypes.c_long, [ctypes.c_int, bfp_format]),
+    "bfp_batch_plan_create": (ctypes.c_int, [ctypes.POINTER(bfp_task), ctypes.c_uint32,
+                                             ctypes.POINTER(ctypes.c_void_p)]),
+    "bfp_batch_run": (ctypes.c_int, [ctypes.c_void_p, ctypes.c_void_p]),
+    "bfp_batch_run_eager": (ctypes.c_int, [ctypes.c_void_p, ctypes.c_void_p]),
+    "bfp_batch_run_per_vector": (ctypes.c_int, [ctypes.c_void_p, ctypes.c_void_p]),
+    "bfp_batch_plan_info": (ctypes.c_int, [ctypes.c_void_p, ctypes.POINTER(ctypes.c_uint32),
+                                           ctypes.POINTER(ctypes.c_uint32), ctypes.POINTER(ctypes.c_uint64)]),
+    "bfp_batch_plan_destroy": (None, [ctypes.c_void_p]),
 }
 
 
@@ -201,6 +214,70 @@ def bfp_launch_save(path: str):
 
 def bfp_gate_count(op, f) -> int:
     return int(lib().bfp_gate_count(_op(op), f))
+
+
+def bfp_batch_plan_create(tasks) -> int:
+    """tasks: sequence of (a, b, c, n, format, op); returns the plan handle."""
+    arr = (bfp_task * len(tasks))()
+    for i, (a, b, c, n, f, op) in enumerate(tasks):
+        arr[i] = bfp_task(_ptr(a), _ptr(b), _ptr(c), n, f, _op(op))
+    h = ctypes.c_void_p()
+    _check(lib().bfp_batch_plan_create(arr, len(tasks), ctypes.byref(h)), "bfp_batch_plan_create")
+    return h.value
+
+
+def bfp_batch_run(plan: int, stream=None):
+    _check(lib().bfp_batch_run(plan, _stream(stream)), "bfp_batch_run")
+
+
+def bfp_batch_run_eager(plan: int, stream=None):
+    _check(lib().bfp_batch_run_eager(plan, _stream(stream)), "bfp_batch_run_eager")
+
+
+def bfp_batch_run_per_vector(plan: int, stream=None):
+    _check(lib().bfp_batch_run_per_vector(plan, _stream(stream)), "bfp_batch_run_per_vector")
+
+
+def bfp_batch_plan_info(plan: int):
+    nch, grid, words = ctypes.c_uint32(), ctypes.c_uint32(), ctypes.c_uint64()
+    _check(lib().bfp_batch_plan_info(plan, ctypes.byref(nch), ctypes.byref(grid), ctypes.byref(words)),
+           "bfp_batch_plan_info")
+    return {"chunks": nch.value, "grid": grid.value, "words_per_operand": words.value}
+
+
+def bfp_batch_plan_destroy(plan: int):
+    lib().bfp_batch_plan_destroy(plan)
+
+
+class BatchPlan:
+    """Owns a plan and keeps the task tensors alive while it exists."""
+
+    def __init__(self, tasks):
+        self._keep = [(a, b, c) for (a, b, c, *_r) in tasks]
+        self.handle = bfp_batch_plan_create(tasks)
+
+    def run(self, stream=None):
+        bfp_batch_run(self.handle, stream)
+
+    def run_eager(self, stream=None):
+        bfp_batch_run_eager(self.handle, stream)
+
+    def run_per_vector(self, stream=None):
+        bfp_batch_run_per_vector(self.handle, stream)
+
+    def info(self):
+        return bfp_batch_plan_info(self.handle)
+
+    def close(self):
+        if self.handle:
+            bfp_batch_plan_destroy(self.handle)
+            self.handle = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
 
 
 # ---- conveniences over torch tensors ----------------------------------------

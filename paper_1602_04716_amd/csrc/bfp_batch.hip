@@ -1,0 +1,272 @@
+// bfp_batch.hip -- many vectors of mixed formats and lengths in one
+// persistent kernel, captured once in a HIP graph.
+//
+// Plan (host): every task (a op b -> c on bitslice vectors of one format) is
+// cut into chunks of at most kChunkWords words per plane; chunks are sorted
+// by circuit variant so that consecutive chunks run the same code (one
+// instruction-cache footprint at a time) and, within a variant, longest task
+// first.  Descriptors go to device memory once.
+//
+// Device: a grid sized to the GPU's resident capacity; each block takes the
+// next chunk index from an atomic counter, reads the chunk's task, and
+// switches (block-uniformly) to the compiled circuit of the task's
+// (e, m, operation class, rounding mode).  The counter is cleared by a
+// one-thread kernel at the head of the graph, so each replay starts at chunk 0.
+#include <hip/hip_runtime.h>
+
+#include <algorithm>
+#include <mutex>
+#include <new>
+#include <vector>
+
+#include "bfp.h"
+#include "bfp_formats.hpp"
+#include "bfp_kernels.hpp"
+
+namespace bfp {
+
+struct BatchTask {
+  const uint32_t* a;
+  const uint32_t* b;
+  uint32_t* c;
+  uint64_t gpad;
+  uint32_t negb;
+  uint32_t variant;
+};
+
+struct BatchChunk {
+  uint64_t w0;      // first word of the chunk within each plane
+  uint32_t task;    // index into the task table
+  uint32_t nwords;  // words per plane in this chunk (multiple of 64)
+};
+
+constexpr uint32_t kChunkWords = 2048;
+constexpr int kBatchBlock = 256;
+
+// variant = ((format index) * 2 + opclass) * 2 + rz, format index in the
+// order of BFP_FOR_EACH_FORMAT
+constexpr int kNumFormats = 40;
+
+__host__ __device__ constexpr int format_index(int e, int m) {
+  const int ei = e == 3 ? 0 : e == 4 ? 1 : e == 5 ? 2 : e == 6 ? 3 : e == 8 ? 4 : -1;
+  const int mi = m == 1 ? 0 : m == 2 ? 1 : m == 3 ? 2 : m == 5 ? 3 : m == 7 ? 4 : m == 10 ? 5
+               : m == 15 ? 6 : m == 23 ? 7 : -1;
+  return (ei < 0 || mi < 0) ? -1 : ei * 8 + mi;
+}
+
+// One chunk of one task: the block's threads stride over the chunk's words.
+template <int E, int M, bool RZ, int OPC>
+__device__ __forceinline__ void batch_chunk(const BatchTask& tk, uint64_t w0, uint32_t nw) {
+  constexpr int B = 1 + E + M;
+  const uint64_t end = w0 + nw;
+  for (uint64_t off = w0 + threadIdx.x; off < end; off += blockDim.x) {
+    WordR<1> x[B], y[B], z[B];
+#pragma unroll
+    for (int k = 0; k < B; ++k) {
+      x[k] = ld_words<1>(tk.a + (uint64_t)k * tk.gpad + off);
+      y[k] = ld_words<1>(tk.b + (uint64_t)k * tk.gpad + off);
+    }
+    circuit<E, M, RZ, OPC, 1>(x, y, tk.negb, z);
+#pragma unroll
+    for (int k = 0; k < B; ++k) st_words<1>(tk.c + (uint64_t)k * tk.gpad + off, z[k]);
+  }
+}
+
+__global__ void k_batch_reset(uint32_t* counter) {
+  if (threadIdx.x == 0 && blockIdx.x == 0) *counter = 0u;
+}
+
+__global__ void __launch_bounds__(kBatchBlock) k_batch(const BatchTask* tasks, const BatchChunk* chunks,
+                                                       uint32_t nchunks, uint32_t* counter) {
+  __shared__ uint32_t s_next;
+  for (;;) {
+    if (threadIdx.x == 0) s_next = atomicAdd(counter, 1u);
+    __syncthreads();
+    const uint32_t ci = s_next;
+    __syncthreads();
+    if (ci >= nchunks) break;  // every block sees the counter pass nchunks and leaves
+    const BatchChunk ch = chunks[ci];
+    const BatchTask tk = tasks[ch.task];
+    switch (tk.variant) {
+#define BFP_BATCH_CASE(EE, MM)                                                                               \
+  case (format_index(EE, MM) * 2 + 0) * 2 + 0: batch_chunk<EE, MM, false, 0>(tk, ch.w0, ch.nwords); break; \
+  case (format_index(EE, MM) * 2 + 0) * 2 + 1: batch_chunk<EE, MM, true, 0>(tk, ch.w0, ch.nwords); break;  \
+  case (format_index(EE, MM) * 2 + 1) * 2 + 0: batch_chunk<EE, MM, false, 1>(tk, ch.w0, ch.nwords); break; \
+  case (format_index(EE, MM) * 2 + 1) * 2 + 1: batch_chunk<EE, MM, true, 1>(tk, ch.w0, ch.nwords); break;
+      BFP_FOR_EACH_FORMAT(BFP_BATCH_CASE)
+#undef BFP_BATCH_CASE
+      default: break;
+    }
+  }
+}
+
+}  // namespace bfp
+
+using namespace bfp;
+
+struct bfp_batch_plan {
+  int device = 0;
+  std::vector<bfp_task> tasks;  // as given (for the per-vector baseline)
+  BatchTask* d_tasks = nullptr;
+  BatchChunk* d_chunks = nullptr;
+  uint32_t* d_counter = nullptr;
+  uint32_t nchunks = 0;
+  unsigned grid = 0;
+  hipStream_t capture_stream = nullptr;
+  hipGraph_t graph = nullptr;
+  hipGraphExec_t exec = nullptr;
+  uint64_t words_total = 0;  // sum over tasks of B * gpad (per operand)
+  std::mutex mu;
+};
+
+namespace {
+
+uint64_t gpad_words(uint64_t n) { return ((n + 31) / 32 + 63) / 64 * 64; }
+
+void plan_free(bfp_batch_plan* p) {
+  if (!p) return;
+  if (p->exec) (void)hipGraphExecDestroy(p->exec);
+  if (p->graph) (void)hipGraphDestroy(p->graph);
+  if (p->capture_stream) (void)hipStreamDestroy(p->capture_stream);
+  if (p->d_tasks) (void)hipFree(p->d_tasks);
+  if (p->d_chunks) (void)hipFree(p->d_chunks);
+  if (p->d_counter) (void)hipFree(p->d_counter);
+  delete p;
+}
+
+}  // namespace
+
+extern "C" {
+
+bfp_status bfp_batch_plan_create(const bfp_task* tasks, uint32_t count, bfp_batch_plan** out) {
+  if (!out) return BFP_E_NULL;
+  *out = nullptr;
+  if (count == 0 || !tasks) return count == 0 ? BFP_E_ARG : BFP_E_NULL;
+  std::vector<BatchTask> dt(count);
+  std::vector<BatchChunk> chunks;
+  uint64_t words_total = 0;
+  for (uint32_t i = 0; i < count; ++i) {
+    const bfp_task& t = tasks[i];
+    if (!bfp_format_supported(t.f)) return BFP_E_FORMAT;
+    if (t.op != BFP_ADD && t.op != BFP_SUB && t.op != BFP_MUL) return BFP_E_OP;
+    if (t.n == 0 || t.n > (1ull << 36)) return BFP_E_ARG;
+    if (!t.a || !t.b || !t.c) return BFP_E_NULL;
+    if (((uintptr_t)t.a | (uintptr_t)t.b | (uintptr_t)t.c) & 15u) return BFP_E_ALIGN;
+    const uint64_t gpad = gpad_words(t.n);
+    const int fi = format_index(t.f.e, t.f.m);
+    if (fi < 0) return BFP_E_FORMAT;
+    const int opc = t.op == BFP_MUL ? 1 : 0;
+    dt[i].a = static_cast<const uint32_t*>(t.a);
+    dt[i].b = static_cast<const uint32_t*>(t.b);
+    dt[i].c = static_cast<uint32_t*>(t.c);
+    dt[i].gpad = gpad;
+    dt[i].negb = t.op == BFP_SUB ? 0xFFFFFFFFu : 0u;
+    dt[i].variant = (uint32_t)((fi * 2 + opc) * 2 + t.f.round);
+    words_total += (uint64_t)(1 + t.f.e + t.f.m) * gpad;
+    for (uint64_t w = 0; w < gpad; w += kChunkWords) {
+      BatchChunk ch;
+      ch.w0 = w;
+      ch.task = i;
+      ch.nwords = (uint32_t)std::min<uint64_t>(kChunkWords, gpad - w);
+      chunks.push_back(ch);
+    }
+  }
+  if (chunks.size() >= 0xFFFFFFF0ull) return BFP_E_ARG;
+  // variant order; within a variant, longer tasks first, then by position
+  std::stable_sort(chunks.begin(), chunks.end(), [&](const BatchChunk& x, const BatchChunk& y) {
+    const uint32_t vx = dt[x.task].variant, vy = dt[y.task].variant;
+    if (vx != vy) return vx < vy;
+    if (dt[x.task].gpad != dt[y.task].gpad) return dt[x.task].gpad > dt[y.task].gpad;
+    if (x.task != y.task) return x.task < y.task;
+    return x.w0 < y.w0;
+  });
+
+  bfp_batch_plan* p = new (std::nothrow) bfp_batch_plan();
+  if (!p) return BFP_E_NOMEM;
+  p->tasks.assign(tasks, tasks + count);
+  p->nchunks = (uint32_t)chunks.size();
+  p->words_total = words_total;
+  if (hipGetDevice(&p->device) != hipSuccess) {
+    plan_free(p);
+    return BFP_E_NODEV;
+  }
+  if (hipMalloc(&p->d_tasks, sizeof(BatchTask) * dt.size()) != hipSuccess ||
+      hipMalloc(&p->d_chunks, sizeof(BatchChunk) * chunks.size()) != hipSuccess ||
+      hipMalloc(&p->d_counter, 256) != hipSuccess) {
+    plan_free(p);
+    return BFP_E_NOMEM;
+  }
+  if (hipMemcpy(p->d_tasks, dt.data(), sizeof(BatchTask) * dt.size(), hipMemcpyHostToDevice) != hipSuccess ||
+      hipMemcpy(p->d_chunks, chunks.data(), sizeof(BatchChunk) * chunks.size(), hipMemcpyHostToDevice) !=
+          hipSuccess) {
+    plan_free(p);
+    return BFP_E_HIP;
+  }
+  // resident grid: as many blocks as fit on the device at once
+  int per_cu = 0;
+  hipDeviceProp_t prop;
+  if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, k_batch, kBatchBlock, 0) != hipSuccess ||
+      hipGetDeviceProperties(&prop, p->device) != hipSuccess) {
+    plan_free(p);
+    return BFP_E_HIP;
+  }
+  if (per_cu < 1) per_cu = 1;
+  p->grid = (unsigned)std::min<uint64_t>((uint64_t)per_cu * prop.multiProcessorCount, p->nchunks);
+  // capture reset + persistent kernel once
+  if (hipStreamCreateWithFlags(&p->capture_stream, hipStreamNonBlocking) != hipSuccess) {
+    plan_free(p);
+    return BFP_E_HIP;
+  }
+  hipError_t e = hipStreamBeginCapture(p->capture_stream, hipStreamCaptureModeThreadLocal);
+  if (e == hipSuccess) {
+    hipLaunchKernelGGL(k_batch_reset, dim3(1), dim3(64), 0, p->capture_stream, p->d_counter);
+    hipLaunchKernelGGL(k_batch, dim3(p->grid), dim3(kBatchBlock), 0, p->capture_stream,
+                       (const BatchTask*)p->d_tasks, (const BatchChunk*)p->d_chunks, p->nchunks, p->d_counter);
+    e = hipStreamEndCapture(p->capture_stream, &p->graph);
+  }
+  if (e == hipSuccess) e = hipGraphInstantiate(&p->exec, p->graph, nullptr, nullptr, 0);
+  if (e != hipSuccess) {
+    plan_free(p);
+    return BFP_E_HIP;
+  }
+  *out = p;
+  return BFP_OK;
+}
+
+bfp_status bfp_batch_run(bfp_batch_plan* plan, void* stream) {
+  if (!plan) return BFP_E_NULL;
+  std::lock_guard<std::mutex> lk(plan->mu);
+  return hipGraphLaunch(plan->exec, (hipStream_t)stream) == hipSuccess ? BFP_OK : BFP_E_HIP;
+}
+
+bfp_status bfp_batch_run_eager(bfp_batch_plan* plan, void* stream) {
+  if (!plan) return BFP_E_NULL;
+  std::lock_guard<std::mutex> lk(plan->mu);
+  hipStream_t s = (hipStream_t)stream;
+  hipLaunchKernelGGL(k_batch_reset, dim3(1), dim3(64), 0, s, plan->d_counter);
+  hipLaunchKernelGGL(k_batch, dim3(plan->grid), dim3(kBatchBlock), 0, s, (const BatchTask*)plan->d_tasks,
+                     (const BatchChunk*)plan->d_chunks, plan->nchunks, plan->d_counter);
+  return hipGetLastError() == hipSuccess ? BFP_OK : BFP_E_HIP;
+}
+
+bfp_status bfp_batch_run_per_vector(bfp_batch_plan* plan, void* stream) {
+  if (!plan) return BFP_E_NULL;
+  for (const bfp_task& t : plan->tasks) {
+    const bfp_status st = bfp_binop(t.op, t.f, t.a, t.b, t.c, t.n, stream);
+    if (st != BFP_OK) return st;
+  }
+  return BFP_OK;
+}
+
+bfp_status bfp_batch_plan_info(const bfp_batch_plan* plan, uint32_t* nchunks, uint32_t* grid,
+                               uint64_t* words_per_operand) {
+  if (!plan) return BFP_E_NULL;
+  if (nchunks) *nchunks = plan->nchunks;
+  if (grid) *grid = plan->grid;
+  if (words_per_operand) *words_per_operand = plan->words_total;
+  return BFP_OK;
+}
+
+void bfp_batch_plan_destroy(bfp_batch_plan* plan) { plan_free(plan); }
+
+}  // extern "C"
