@@ -9,10 +9,11 @@ operations (2 formats x 3 ops x 2^26 elements per step) per second with the
 inputs already in HBM.
 
 Also printed in the same JSON line:
-  roofline      the dominant kernel's achieved rate against MI355X's peak
-                (HBM 8 TB/s, or the bitwise VALU rate), from HIP events on the
-                stream the kernels run on;
-  kernels       every kernel's mean duration and rates;
+  roofline      the dominant kernel (largest share of the step) against
+                MI355X's peak (HBM 8 TB/s, or the bitwise VALU rate); its
+                duration is the mean over the timed steps of HIP events
+                recorded around each of its launches on the kernels' stream;
+  kernels       every kernel's mean duration and rates, measured the same way;
   batched       (with --batched) 4096 mixed vectors: one persistent launch vs
                 one launch per vector;
   cpu_baseline  the oracle timed on this host on a bounded sample.
@@ -42,8 +43,10 @@ def parse():
     ap.add_argument("--warmup", type=int, default=3)
     ap.add_argument("--n-log2", type=int, default=26)
     ap.add_argument("--no-cpu-baseline", action="store_true")
-    ap.add_argument("--kernel-reps", type=int, default=20)
     ap.add_argument("--no-batched", action="store_true")
+    ap.add_argument("--calibrate-copy", action="store_true",
+                    help="also run one int32->float32 conversion of 2^26 elements (256 MiB read, 256 MiB "
+                         "written) so hardware byte counters can be scaled against a kernel of known traffic")
     ap.add_argument("--batched-reps", type=int, default=10)
     return ap.parse_args()
 
@@ -85,6 +88,34 @@ def bench_batched(torch, bfp, dev, reps):
             "speedup_vs_per_vector": v_ms / g_ms, "elements_per_s": elems / (g_ms * 1e-3),
             "per_vector_elements_per_s": elems / (v_ms * 1e-3),
             "hbm_frac": nbytes / (g_ms * 1e-3) / HBM_PEAK, "valu_frac": ops_alg / (g_ms * 1e-3) / VALU_PEAK}
+
+
+def device_kernel(label):
+    """Device kernel that a bench label ("unpack(8,7)", "mul(5,10)") launches
+    with the bench's configuration (64-element lane words, nearest-even)."""
+    kind, _, fm = label.partition("(")
+    e, m = (int(x) for x in fm.rstrip(")").split(","))
+    B = 1 + e + m
+    C = 1 if B <= 8 else (2 if B <= 16 else 4)
+    if kind == "pack":
+        return "bfp::k_pack<%d, 1>" % C
+    if kind == "unpack":
+        return "bfp::k_unpack<%d>" % C
+    return "bfp::k_binop<%d, %d, false, %d, 2>" % (e, m, 1 if kind == "mul" else 0)
+
+
+def committed_traffic(kernel):
+    """HBM bytes per launch of `kernel` from the committed rocprofv3 counter
+    summaries (profiles/*.traffic.txt), or None if there is none for the
+    current kernel sources."""
+    import glob
+
+    from paper_1602_04716_amd import profiling
+    for path in sorted(glob.glob(os.path.join(ROOT, "profiles", "*.traffic.txt"))):
+        t = profiling.read_traffic(path)
+        if t and t["kernel"] == kernel:
+            return t["bytes"]
+    return None
 
 
 def cpu_baseline(sample_log2=24):
@@ -143,76 +174,83 @@ def main():
         data[(e, m)] = (f, a, b, pa, pb, pc, out)
     torch.cuda.synchronize()
 
-    def step():
-        for (e, m) in FORMATS:
-            f, a, b, pa, pb, pc, out = data[(e, m)]
-            bfp.bfp_pack(f, a, pa, n, stream)
-            bfp.bfp_pack(f, b, pb, n, stream)
-            for op in OPS:
-                bfp.bfp_binop(op, f, pa, pb, pc[op], n, stream)
-            for op in OPS:
-                bfp.bfp_unpack(f, pc[op], out[op], n, stream)
-
-    for _ in range(args.warmup):
-        step()
-    torch.cuda.synchronize()
-    t0 = torch.cuda.Event(enable_timing=True)
-    t1 = torch.cuda.Event(enable_timing=True)
-    wall0 = time.perf_counter()
-    t0.record(stream)
-    for _ in range(args.steps):
-        step()
-    t1.record(stream)
-    torch.cuda.synchronize()
-    wall = time.perf_counter() - wall0
-    ms_step = t0.elapsed_time(t1) / args.steps
-    elems_per_step = len(FORMATS) * len(OPS) * n
-    value = elems_per_step / (ms_step / 1e3)
-
-    # per-kernel durations (events on the same stream the kernels run on)
-    kernels = {}
-    reps = args.kernel_reps
-
-    def timed(name, fn, bytes_alg, ops_alg):
-        ev0 = torch.cuda.Event(enable_timing=True)
-        ev1 = torch.cuda.Event(enable_timing=True)
-        fn()
-        ev0.record(stream)
-        for _ in range(reps):
-            fn()
-        ev1.record(stream)
+    if args.calibrate_copy:
+        src = torch.zeros(1 << 26, dtype=torch.int32, device=dev)
+        dst = torch.empty(1 << 26, dtype=torch.float32, device=dev)
+        dst.copy_(src)
         torch.cuda.synchronize()
-        us = ev0.elapsed_time(ev1) * 1e3 / reps
-        k = {"us": us, "GB/s": bytes_alg / (us * 1e-6) / 1e9, "hbm_frac": bytes_alg / (us * 1e-6) / HBM_PEAK}
-        if ops_alg:
-            k["Gops/s"] = ops_alg / (us * 1e-6) / 1e9
-            k["valu_frac"] = ops_alg / (us * 1e-6) / VALU_PEAK
-        kernels[name] = k
+        del src, dst
 
+    # one step = for each format: pack a, pack b, add, sub, mul, unpack x3.
+    # Launches of one kernel that follow each other form a group bracketed by
+    # two events on the stream the kernels run on, so per-kernel durations come
+    # from the timed steps themselves (group time / launches in the group).
+    groups = []  # (name, [launch fns], algorithmic bytes per launch, gate ops per launch)
     for (e, m) in FORMATS:
         f, a, b, pa, pb, pc, out = data[(e, m)]
         B = 1 + e + m
         C = bfp.bfp_container_bytes(f)
-        timed("pack(%d,%d)" % (e, m), lambda: bfp.bfp_pack(f, a, pa, n, stream), n * (C + B / 8), 0)
+        tag = "(%d,%d)" % (e, m)
+        io = n * (C + B / 8)
+        groups.append(("pack" + tag, [lambda f=f, a=a, pa=pa: bfp.bfp_pack(f, a, pa, n, stream),
+                                      lambda f=f, b=b, pb=pb: bfp.bfp_pack(f, b, pb, n, stream)], io, 0))
         for op in OPS:
             G = bfp.bfp_gate_count(op, f)
-            timed("%s(%d,%d)" % (op, e, m), lambda: bfp.bfp_binop(op, f, pa, pb, pc[op], n, stream),
-                  n * 3 * B / 8, G * n / 32)
-        timed("unpack(%d,%d)" % (e, m), lambda: bfp.bfp_unpack(f, pc["add"], out["add"], n, stream),
-              n * (C + B / 8), 0)
-    # the dominant kernel: largest share of the step (pack/unpack run 2x/3x per step)
-    share = {}
+            groups.append((op + tag, [lambda f=f, pa=pa, pb=pb, pc=pc, op=op:
+                                      bfp.bfp_binop(op, f, pa, pb, pc[op], n, stream)], n * 3 * B / 8, G * n / 32))
+        groups.append(("unpack" + tag, [lambda f=f, pc=pc, out=out, op=op: bfp.bfp_unpack(f, pc[op], out[op], n, stream)
+                                        for op in OPS], io, 0))
+
+    def step(evs=None):
+        for i, (name, fns, _b, _o) in enumerate(groups):
+            if evs is not None:
+                evs[i][0].record(stream)
+            for fn in fns:
+                fn()
+            if evs is not None:
+                evs[i][1].record(stream)
+
+    for _ in range(args.warmup):
+        step()
+    torch.cuda.synchronize()
+    evs = [[(torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True))
+            for _ in groups] for _ in range(args.steps)]
+    wall0 = time.perf_counter()
+    for k in range(args.steps):
+        step(evs[k])
+    torch.cuda.synchronize()
+    wall = time.perf_counter() - wall0
+    ms_step = evs[0][0][0].elapsed_time(evs[-1][-1][1]) / args.steps
+    elems_per_step = len(FORMATS) * len(OPS) * n
+    value = elems_per_step / (ms_step / 1e3)
+
+    kernels = {}
+    for i, (name, fns, nbytes, nops) in enumerate(groups):
+        k = kernels.setdefault(name, {"launches": 0, "us_total": 0.0, "bytes": nbytes, "ops": nops})
+        for st in range(args.steps):
+            k["us_total"] += evs[st][i][0].elapsed_time(evs[st][i][1]) * 1e3
+            k["launches"] += len(fns)
     for name, k in kernels.items():
-        mult = 2 if name.startswith("pack") else (3 if name.startswith("unpack") else 1)
-        share[name] = k["us"] * mult
-    dom = max(share, key=share.get)
+        us = k["us_total"] / k["launches"]
+        k["us"] = us
+        k["GB/s"] = k["bytes"] / (us * 1e-6) / 1e9
+        k["hbm_frac"] = k["bytes"] / (us * 1e-6) / HBM_PEAK
+        if k["ops"]:
+            k["Tops/s"] = k["ops"] / (us * 1e-6) / 1e12
+            k["valu_frac"] = k["ops"] / (us * 1e-6) / VALU_PEAK
+    # the dominant kernel: largest total time per step
+    dom = max(kernels, key=lambda nm: kernels[nm]["us_total"])
     dk = kernels[dom]
     if dk.get("valu_frac", 0) > dk["hbm_frac"]:
-        roof = {"kernel": dom, "bound": "alu", "achieved": dk["Gops/s"] * 1e9 / 1e12, "peak": VALU_PEAK / 1e12,
+        roof = {"kernel": dom, "bound": "alu", "achieved": dk["Tops/s"], "peak": VALU_PEAK / 1e12,
                 "unit": "Tops/s", "frac": dk["valu_frac"], "traffic": None}
     else:
         roof = {"kernel": dom, "bound": "hbm", "achieved": dk["GB/s"], "peak": HBM_PEAK / 1e9, "unit": "GB/s",
                 "frac": dk["hbm_frac"], "traffic": None}
+    roof["us_per_launch"] = dk["us"]
+    roof["algorithmic_bytes_per_launch"] = dk["bytes"]
+    roof["device_kernel"] = device_kernel(dom)
+    roof["traffic"] = committed_traffic(roof["device_kernel"])
 
     res = {
         "metric": "custom-FP elements/s & % VALU/HBM peak, bit-exact; batched vs per-vector launch",
@@ -232,7 +270,8 @@ def main():
                    "n": n, "formats": ["(5,10)", "(8,7)"], "words_per_lane": 2},
         "wall_s_timed": wall,
         "roofline": roof,
-        "kernels": kernels,
+        "kernels": {k: {x: v[x] for x in ("us", "launches", "GB/s", "hbm_frac", "Tops/s", "valu_frac") if x in v}
+                    for k, v in kernels.items()},
     }
     if not args.no_batched:
         res["batched"] = bench_batched(torch, bfp, dev, args.batched_reps)

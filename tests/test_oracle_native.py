@@ -153,3 +153,20 @@ def test_bfloat16_rne_torch(oracle_lib, op):
     want = r.view(torch.int16).numpy().view(np.uint16).astype(np.uint32)
     got = oracle_lib.binop(op, 8, 7, 0, a, b, nthreads=4)
     _compare(8, 7, got, want, a, b, ("bf16", op))
+
+
+def test_from_double_matches_native_conversions(oracle_lib):
+    """oracle_from_double (round a binary64 value once) against numpy's
+    binary64 -> binary16 and -> binary32 conversions (nearest-even), over
+    random magnitudes spanning subnormals, normals and overflow."""
+    rng = np.random.default_rng(64)
+    x = rng.standard_normal(20000) * np.exp2(rng.uniform(-160, 140, 20000))
+    x = np.concatenate([x, [0.0, -0.0, np.inf, -np.inf, 65520.0, 65519.99, 2.0 ** -25, 2.0 ** -24 * 1.5,
+                            -(2.0 ** -149), 2.0 ** -150, 3.4028235677973366e38]])
+    with np.errstate(all="ignore"):
+        h = x.astype(np.float16).view(np.uint16)
+        f = x.astype(np.float32).view(np.uint32)
+    for i, v in enumerate(x):
+        assert oracle_lib.from_double(5, 10, 0, v) == int(h[i]), v
+        assert oracle_lib.from_double(8, 23, 0, v) == int(f[i]), v
+    assert oracle_lib.from_double(5, 10, 0, float("nan")) == 0x7E00
