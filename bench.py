@@ -48,6 +48,8 @@ def parse():
                     help="also run one int32->float32 conversion of 2^26 elements (256 MiB read, 256 MiB "
                          "written) so hardware byte counters can be scaled against a kernel of known traffic")
     ap.add_argument("--batched-reps", type=int, default=10)
+    ap.add_argument("--no-serving", action="store_true")
+    ap.add_argument("--serving-requests", type=int, default=20000)
     return ap.parse_args()
 
 
@@ -88,6 +90,34 @@ def bench_batched(torch, bfp, dev, reps):
             "speedup_vs_per_vector": v_ms / g_ms, "elements_per_s": elems / (g_ms * 1e-3),
             "per_vector_elements_per_s": elems / (v_ms * 1e-3),
             "hbm_frac": nbytes / (g_ms * 1e-3) / HBM_PEAK, "valu_frac": ops_alg / (g_ms * 1e-3) / VALU_PEAK}
+
+
+def bench_serving(torch, bfp, dev, n_req):
+    """Serving loop: resident pool of two 2^22-element vectors per format of
+    the 40-format sweep, requests with n = 2^U(10,22), random format and op,
+    64 GB budget.  Saturation throughput mu from all requests submitted at
+    once; then Poisson arrivals at 0.5 mu and 0.9 mu (1000 warm-up requests
+    not counted), p50/p99 of completion minus submission."""
+    from paper_1602_04716_amd import inputs, serving
+    fmts = inputs.sweep_formats()
+    srv = serving.Server(64 << 30, 4096)
+    pool = serving.build_pool(srv, fmts, 1 << 22, seed=5, device=dev)
+    sat = serving.run(srv, pool, serving.request_stream(n_req, fmts, seed=50))
+    mu = sat["requests_per_s"]
+    out = {"budget_bytes": 64 << 30, "slots": 4096, "pool_bytes": srv.stats()["used"],
+           "saturation": {k: sat[k] for k in ("requests", "requests_per_s", "elements_per_s", "p50_us", "p99_us")}}
+    for frac in (0.5, 0.9):
+        r = serving.run(srv, pool, serving.request_stream(n_req + 1000, fmts, seed=int(60 + 10 * frac)),
+                        rate=frac * mu, seed=7, skip=1000)
+        out["lambda_%.1f_mu" % frac] = {k: r[k] for k in ("rate", "requests", "requests_per_s", "elements_per_s",
+                                                           "p50_us", "p99_us", "mean_us", "errors")}
+    st = srv.stats()
+    out["high_water_bytes"] = st["high_water"]
+    out["ticks"] = st["ticks"]
+    out["max_tick_requests"] = st["max_tick_requests"]
+    out["max_inflight_ticks"] = st["max_inflight_ticks"]
+    srv.close()
+    return out
 
 
 def device_kernel(label):
@@ -275,6 +305,8 @@ def main():
     }
     if not args.no_batched:
         res["batched"] = bench_batched(torch, bfp, dev, args.batched_reps)
+    if not args.no_serving:
+        res["serving"] = bench_serving(torch, bfp, dev, args.serving_requests)
     if not args.no_cpu_baseline:
         res["cpu_baseline"] = cpu_baseline()
     print(json.dumps(res), flush=True)

@@ -166,6 +166,19 @@ bfp_status bfp_launch_set(int op, bfp_format f, const bfp_launch* cfg);
 bfp_status bfp_launch_load(const char* path);
 bfp_status bfp_launch_save(const char* path);
 
+/* Autotune bfp_binop for (op, f): time every words_per_lane allowed by
+ * `words_per_lane_mask` (bit 0: 1 word, bit 1: 2 words) x block
+ * {64,128,256,512} x blocks_per_cu {0,4,8} on a probe vector of n_probe
+ * random elements (median of `reps` runs, each after a 512 MiB read sweep
+ * that clears the last-level cache), install the fastest with
+ * bfp_launch_set and return it in *best (and its median microseconds in
+ * *best_us; either may be NULL).  Allocates and frees its own probe buffers
+ * (about 3 * bfp_bitslice_bytes(f, n_probe) + 512 MiB) and synchronises
+ * `stream`.  1 <= n_probe <= 2^30, 1 <= reps <= 1000.  On error the previous
+ * configuration stays in place. */
+bfp_status bfp_autotune(int op, bfp_format f, uint64_t n_probe, int words_per_lane_mask, int reps, void* stream,
+                        bfp_launch* best, double* best_us);
+
 /* Gate count of one circuit instance (one group of 32 elements per word),
  * constants folded: the cost model of Table 1.  Returns -1 if the format
  * is not compiled. */
@@ -216,6 +229,79 @@ bfp_status bfp_batch_plan_info(const bfp_batch_plan* plan, uint32_t* nchunks, ui
 /* Free the plan's device memory and graph (NULL is a no-op).  Wait for its
  * runs to finish first. */
 void bfp_batch_plan_destroy(bfp_batch_plan* plan);
+
+/* ---- serving loop ---------------------------------------------------------- */
+/* A request loop over device-resident bitslice vectors (not in the paper;
+ * it serves the Section 4 operations).  The server owns one device arena of
+ * `hbm_budget_bytes` (allocated at creation): every resident vector -- the
+ * caller's operands and every request's result -- is carved from it, so the
+ * memory in use never exceeds the budget.  Requests wait in FIFO order and
+ * are admitted when one of `slots` request slots is free and the arena can
+ * hold the result.  A worker thread launches all requests admitted since its
+ * last launch as one batched persistent kernel on whichever of two streams
+ * is free (continuous batching: requests that arrive while a batch runs join
+ * the next one, which may start before the first ends).
+ *
+ * Handles are uint32 (0 is never a handle).  A request computes its op on
+ * the first n elements of both operands (same format as the request's e, m;
+ * the rounding mode comes from the request); its result is a new resident
+ * vector of n elements.  When a request's n is shorter than an operand, the
+ * result's padding bits hold the op of the operands' following elements
+ * (unpack never reads them).  Times are steady-clock nanoseconds. */
+typedef struct bfp_server bfp_server;
+
+typedef struct {
+  uint64_t req_id;
+  uint32_t result; /* handle of the result vector (0 on error) */
+  int32_t status;  /* BFP_OK or an error */
+  uint64_t n;
+  int64_t t_submit_ns, t_admit_ns, t_launch_ns, t_done_ns; /* t_done: completion observed */
+} bfp_completion;
+
+typedef struct {
+  uint64_t budget, used, high_water;            /* arena bytes */
+  uint64_t submitted, admitted, completed, ticks;
+  uint64_t max_tick_requests, max_inflight_ticks, deferred_budget;
+  uint64_t pending, inflight;
+} bfp_server_stats;
+
+/* Create a server on the current device.  Errors: BFP_E_ARG (budget < 256
+ * bytes, slots outside 1..2^20), BFP_E_NOMEM (arena), BFP_E_HIP. */
+bfp_status bfp_server_create(uint64_t hbm_budget_bytes, int32_t slots, bfp_server** out);
+
+/* Pack n standard containers (device memory, read in order on `stream`)
+ * into a new resident vector; synchronises `stream` before returning, so the
+ * vector is ready for any later request.  BFP_E_BUDGET if the arena is full. */
+bfp_status bfp_server_put(bfp_server* s, bfp_format f, const void* std_dev, uint64_t n, void* stream,
+                          uint32_t* handle);
+
+/* Queue c = a op b on the first n elements of resident vectors a and b
+ * (n <= both lengths).  Returns at once with the request id.  BFP_E_BUDGET if
+ * the result could never fit in the arena. */
+bfp_status bfp_server_submit(bfp_server* s, int op, bfp_format f, uint32_t a, uint32_t b, uint64_t n,
+                             uint64_t* req_id);
+
+/* Move up to `max` completions (oldest first) to `out`; *count is set. */
+bfp_status bfp_server_poll(bfp_server* s, bfp_completion* out, uint32_t max, uint32_t* count);
+
+/* Wait until no request is queued, admitted or running (BFP_E_ARG on timeout). */
+bfp_status bfp_server_wait_idle(bfp_server* s, int64_t timeout_ms);
+
+/* Device address and length of a resident vector (valid until it is freed). */
+bfp_status bfp_server_view(bfp_server* s, uint32_t handle, void** bitslice_dev, uint64_t* n);
+
+/* Unpack a resident vector of format f into its n standard containers at
+ * std_dev_out (device), on `stream`, and synchronise `stream`.  Call it only
+ * for vectors whose request has completed. */
+bfp_status bfp_server_get(bfp_server* s, uint32_t handle, bfp_format f, void* std_dev_out, void* stream);
+
+/* Release a resident vector (operand or result) back to the arena. */
+bfp_status bfp_server_free(bfp_server* s, uint32_t handle);
+
+bfp_status bfp_server_stats_get(bfp_server* s, bfp_server_stats* out);
+
+/* Stop the worker (running batches finish first) and free everything. */
+void bfp_server_destroy(bfp_server* s);
 
 #ifdef __cplusplus
 }

@@ -14,6 +14,9 @@ import os
 
 _HERE = os.path.dirname(os.path.abspath(__file__))
 LIB_PATH = os.path.join(_HERE, "libbfp.so")
+# launch configurations measured by the autotuner on MI355X; BFP_TUNE_FILE
+# overrides the path, and an empty BFP_TUNE_FILE keeps the built-in defaults
+TUNE_TABLE = os.path.join(_HERE, "tuning", "gfx950.txt")
 
 BFP_OK = 0
 BFP_RNE, BFP_RZ = 0, 1
@@ -41,6 +44,21 @@ class bfp_launch(ctypes.Structure):
 class bfp_task(ctypes.Structure):
     _fields_ = [("a", ctypes.c_void_p), ("b", ctypes.c_void_p), ("c", ctypes.c_void_p), ("n", ctypes.c_uint64),
                 ("f", bfp_format), ("op", ctypes.c_int32)]
+
+
+class bfp_completion(ctypes.Structure):
+    _fields_ = [("req_id", ctypes.c_uint64), ("result", ctypes.c_uint32), ("status", ctypes.c_int32),
+                ("n", ctypes.c_uint64), ("t_submit_ns", ctypes.c_int64), ("t_admit_ns", ctypes.c_int64),
+                ("t_launch_ns", ctypes.c_int64), ("t_done_ns", ctypes.c_int64)]
+
+
+class bfp_server_stats(ctypes.Structure):
+    _fields_ = [(k, ctypes.c_uint64) for k in (
+        "budget", "used", "high_water", "submitted", "admitted", "completed", "ticks", "max_tick_requests",
+        "max_inflight_ticks", "deferred_budget", "pending", "inflight")]
+
+    def as_dict(self):
+        return {k: int(getattr(self, k)) for (k, _t) in self._fields_}
 
 
 class BfpError(RuntimeError):
@@ -76,6 +94,8 @@ _SIGS = {
     "bfp_launch_load": (ctypes.c_int, [ctypes.c_char_p]),
     "bfp_launch_save": (ctypes.c_int, [ctypes.c_char_p]),
     "bfp_gate_count": (ctypes.c_long, [ctypes.c_int, bfp_format]),
+    "bfp_autotune": (ctypes.c_int, [ctypes.c_int, bfp_format, ctypes.c_uint64, ctypes.c_int, ctypes.c_int,
+                                    ctypes.c_void_p, ctypes.POINTER(bfp_launch), ctypes.POINTER(ctypes.c_double)]),
     "bfp_batch_plan_create": (ctypes.c_int, [ctypes.POINTER(bfp_task), ctypes.c_uint32,
                                              ctypes.POINTER(ctypes.c_void_p)]),
     "bfp_batch_run": (ctypes.c_int, [ctypes.c_void_p, ctypes.c_void_p]),
@@ -84,6 +104,21 @@ _SIGS = {
     "bfp_batch_plan_info": (ctypes.c_int, [ctypes.c_void_p, ctypes.POINTER(ctypes.c_uint32),
                                            ctypes.POINTER(ctypes.c_uint32), ctypes.POINTER(ctypes.c_uint64)]),
     "bfp_batch_plan_destroy": (None, [ctypes.c_void_p]),
+    "bfp_server_create": (ctypes.c_int, [ctypes.c_uint64, ctypes.c_int32, ctypes.POINTER(ctypes.c_void_p)]),
+    "bfp_server_put": (ctypes.c_int, [ctypes.c_void_p, bfp_format, ctypes.c_void_p, ctypes.c_uint64,
+                                      ctypes.c_void_p, ctypes.POINTER(ctypes.c_uint32)]),
+    "bfp_server_submit": (ctypes.c_int, [ctypes.c_void_p, ctypes.c_int, bfp_format, ctypes.c_uint32,
+                                         ctypes.c_uint32, ctypes.c_uint64, ctypes.POINTER(ctypes.c_uint64)]),
+    "bfp_server_poll": (ctypes.c_int, [ctypes.c_void_p, ctypes.POINTER(bfp_completion), ctypes.c_uint32,
+                                       ctypes.POINTER(ctypes.c_uint32)]),
+    "bfp_server_wait_idle": (ctypes.c_int, [ctypes.c_void_p, ctypes.c_int64]),
+    "bfp_server_view": (ctypes.c_int, [ctypes.c_void_p, ctypes.c_uint32, ctypes.POINTER(ctypes.c_void_p),
+                                       ctypes.POINTER(ctypes.c_uint64)]),
+    "bfp_server_get": (ctypes.c_int, [ctypes.c_void_p, ctypes.c_uint32, bfp_format, ctypes.c_void_p,
+                                      ctypes.c_void_p]),
+    "bfp_server_free": (ctypes.c_int, [ctypes.c_void_p, ctypes.c_uint32]),
+    "bfp_server_stats_get": (ctypes.c_int, [ctypes.c_void_p, ctypes.POINTER(bfp_server_stats)]),
+    "bfp_server_destroy": (None, [ctypes.c_void_p]),
 }
 
 
@@ -99,6 +134,9 @@ def lib():
             fn.restype = res
             fn.argtypes = args
         _lib = L
+        table = os.environ.get("BFP_TUNE_FILE", TUNE_TABLE)
+        if table and os.path.exists(table):
+            _check(L.bfp_launch_load(table.encode()), "bfp_launch_load")
     return _lib
 
 
@@ -212,6 +250,15 @@ def bfp_launch_save(path: str):
     _check(lib().bfp_launch_save(path.encode()), "bfp_launch_save")
 
 
+def bfp_autotune(op, f, n_probe: int = 1 << 24, words_per_lane_mask: int = 3, reps: int = 7, stream=None):
+    """Returns (best bfp_launch, median microseconds); installs the best."""
+    best = bfp_launch()
+    us = ctypes.c_double()
+    _check(lib().bfp_autotune(_op(op), f, n_probe, words_per_lane_mask, reps, _stream(stream), ctypes.byref(best),
+                              ctypes.byref(us)), "bfp_autotune")
+    return best, us.value
+
+
 def bfp_gate_count(op, f) -> int:
     return int(lib().bfp_gate_count(_op(op), f))
 
@@ -278,6 +325,59 @@ class BatchPlan:
             self.close()
         except Exception:
             pass
+
+
+def bfp_server_create(budget_bytes: int, slots: int) -> int:
+    h = ctypes.c_void_p()
+    _check(lib().bfp_server_create(budget_bytes, slots, ctypes.byref(h)), "bfp_server_create")
+    return h.value
+
+
+def bfp_server_put(server: int, f, std_dev, n: int, stream=None) -> int:
+    h = ctypes.c_uint32()
+    _check(lib().bfp_server_put(server, f, _ptr(std_dev), n, _stream(stream), ctypes.byref(h)), "bfp_server_put")
+    return h.value
+
+
+def bfp_server_submit(server: int, op, f, a: int, b: int, n: int) -> int:
+    rid = ctypes.c_uint64()
+    _check(lib().bfp_server_submit(server, _op(op), f, a, b, n, ctypes.byref(rid)), "bfp_server_submit")
+    return rid.value
+
+
+def bfp_server_poll(server: int, max_items: int = 4096):
+    buf = (bfp_completion * max_items)()
+    cnt = ctypes.c_uint32()
+    _check(lib().bfp_server_poll(server, buf, max_items, ctypes.byref(cnt)), "bfp_server_poll")
+    return [buf[i] for i in range(cnt.value)]
+
+
+def bfp_server_wait_idle(server: int, timeout_ms: int = 60000):
+    _check(lib().bfp_server_wait_idle(server, timeout_ms), "bfp_server_wait_idle")
+
+
+def bfp_server_view(server: int, handle: int):
+    p, n = ctypes.c_void_p(), ctypes.c_uint64()
+    _check(lib().bfp_server_view(server, handle, ctypes.byref(p), ctypes.byref(n)), "bfp_server_view")
+    return p.value, n.value
+
+
+def bfp_server_get(server: int, handle: int, f, std_dev_out, stream=None):
+    _check(lib().bfp_server_get(server, handle, f, _ptr(std_dev_out), _stream(stream)), "bfp_server_get")
+
+
+def bfp_server_free(server: int, handle: int):
+    _check(lib().bfp_server_free(server, handle), "bfp_server_free")
+
+
+def bfp_server_stats_get(server: int) -> dict:
+    st = bfp_server_stats()
+    _check(lib().bfp_server_stats_get(server, ctypes.byref(st)), "bfp_server_stats_get")
+    return st.as_dict()
+
+
+def bfp_server_destroy(server: int):
+    lib().bfp_server_destroy(server)
 
 
 # ---- conveniences over torch tensors ----------------------------------------

@@ -21,31 +21,13 @@
 
 #include "bfp.h"
 #include "bfp_formats.hpp"
+#include "bfp_batch.hpp"
 #include "bfp_kernels.hpp"
 
 namespace bfp {
 
-struct BatchTask {
-  const uint32_t* a;
-  const uint32_t* b;
-  uint32_t* c;
-  uint64_t gpad;
-  uint32_t negb;
-  uint32_t variant;
-};
-
-struct BatchChunk {
-  uint64_t w0;      // first word of the chunk within each plane
-  uint32_t task;    // index into the task table
-  uint32_t nwords;  // words per plane in this chunk (multiple of 64)
-};
-
-constexpr uint32_t kChunkWords = 2048;
-constexpr int kBatchBlock = 256;
-
 // variant = ((format index) * 2 + opclass) * 2 + rz, format index in the
 // order of BFP_FOR_EACH_FORMAT
-constexpr int kNumFormats = 40;
 
 __host__ __device__ constexpr int format_index(int e, int m) {
   const int ei = e == 3 ? 0 : e == 4 ? 1 : e == 5 ? 2 : e == 6 ? 3 : e == 8 ? 4 : -1;
@@ -63,12 +45,12 @@ __device__ __forceinline__ void batch_chunk(const BatchTask& tk, uint64_t w0, ui
     WordR<1> x[B], y[B], z[B];
 #pragma unroll
     for (int k = 0; k < B; ++k) {
-      x[k] = ld_words<1>(tk.a + (uint64_t)k * tk.gpad + off);
-      y[k] = ld_words<1>(tk.b + (uint64_t)k * tk.gpad + off);
+      x[k] = ld_words<1>(tk.a + (uint64_t)k * tk.sa + off);
+      y[k] = ld_words<1>(tk.b + (uint64_t)k * tk.sb + off);
     }
     circuit<E, M, RZ, OPC, 1>(x, y, tk.negb, z);
 #pragma unroll
-    for (int k = 0; k < B; ++k) st_words<1>(tk.c + (uint64_t)k * tk.gpad + off, z[k]);
+    for (int k = 0; k < B; ++k) st_words<1>(tk.c + (uint64_t)k * tk.sc + off, z[k]);
   }
 }
 
@@ -100,6 +82,61 @@ __global__ void __launch_bounds__(kBatchBlock) k_batch(const BatchTask* tasks, c
   }
 }
 
+bool batch_task(const void* a, uint64_t na, const void* b, uint64_t nb, void* c, uint64_t n, bfp_format f, int op,
+                BatchTask* out) {
+  const int fi = format_index(f.e, f.m);
+  if (fi < 0 || f.round > 1 || (op != BFP_ADD && op != BFP_SUB && op != BFP_MUL)) return false;
+  if (na < n || nb < n) return false;
+  out->a = static_cast<const uint32_t*>(a);
+  out->b = static_cast<const uint32_t*>(b);
+  out->c = static_cast<uint32_t*>(c);
+  out->sa = bfp_plane_stride_words(na);
+  out->sb = bfp_plane_stride_words(nb);
+  out->sc = bfp_plane_stride_words(n);
+  out->words = out->sc;
+  out->negb = op == BFP_SUB ? 0xFFFFFFFFu : 0u;
+  out->variant = (uint32_t)((fi * 2 + (op == BFP_MUL ? 1 : 0)) * 2 + f.round);
+  return true;
+}
+
+void batch_chunks(const std::vector<BatchTask>& dt, std::vector<BatchChunk>* out) {
+  std::vector<BatchChunk>& chunks = *out;
+  chunks.clear();
+  for (uint32_t i = 0; i < (uint32_t)dt.size(); ++i) {
+    for (uint64_t w = 0; w < dt[i].words; w += kChunkWords) {
+      BatchChunk ch;
+      ch.w0 = w;
+      ch.task = i;
+      ch.nwords = (uint32_t)std::min<uint64_t>(kChunkWords, dt[i].words - w);
+      chunks.push_back(ch);
+    }
+  }
+  // variant order; within a variant, longer tasks first, then by position
+  std::stable_sort(chunks.begin(), chunks.end(), [&](const BatchChunk& x, const BatchChunk& y) {
+    const uint32_t vx = dt[x.task].variant, vy = dt[y.task].variant;
+    if (vx != vy) return vx < vy;
+    if (dt[x.task].words != dt[y.task].words) return dt[x.task].words > dt[y.task].words;
+    if (x.task != y.task) return x.task < y.task;
+    return x.w0 < y.w0;
+  });
+}
+
+int batch_resident_blocks() {
+  int dev = 0, per_cu = 0;
+  hipDeviceProp_t prop;
+  if (hipGetDevice(&dev) != hipSuccess || hipGetDeviceProperties(&prop, dev) != hipSuccess) return 0;
+  if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, k_batch, kBatchBlock, 0) != hipSuccess) return 0;
+  if (per_cu < 1) per_cu = 1;
+  return per_cu * prop.multiProcessorCount;
+}
+
+hipError_t batch_launch(const BatchTask* d_tasks, const BatchChunk* d_chunks, uint32_t nchunks, uint32_t* d_counter,
+                        unsigned grid, hipStream_t s) {
+  hipLaunchKernelGGL(k_batch_reset, dim3(1), dim3(64), 0, s, d_counter);
+  hipLaunchKernelGGL(k_batch, dim3(grid), dim3(kBatchBlock), 0, s, d_tasks, d_chunks, nchunks, d_counter);
+  return hipGetLastError();
+}
+
 }  // namespace bfp
 
 using namespace bfp;
@@ -120,8 +157,6 @@ struct bfp_batch_plan {
 };
 
 namespace {
-
-uint64_t gpad_words(uint64_t n) { return ((n + 31) / 32 + 63) / 64 * 64; }
 
 void plan_free(bfp_batch_plan* p) {
   if (!p) return;
@@ -152,34 +187,11 @@ bfp_status bfp_batch_plan_create(const bfp_task* tasks, uint32_t count, bfp_batc
     if (t.n == 0 || t.n > (1ull << 36)) return BFP_E_ARG;
     if (!t.a || !t.b || !t.c) return BFP_E_NULL;
     if (((uintptr_t)t.a | (uintptr_t)t.b | (uintptr_t)t.c) & 15u) return BFP_E_ALIGN;
-    const uint64_t gpad = gpad_words(t.n);
-    const int fi = format_index(t.f.e, t.f.m);
-    if (fi < 0) return BFP_E_FORMAT;
-    const int opc = t.op == BFP_MUL ? 1 : 0;
-    dt[i].a = static_cast<const uint32_t*>(t.a);
-    dt[i].b = static_cast<const uint32_t*>(t.b);
-    dt[i].c = static_cast<uint32_t*>(t.c);
-    dt[i].gpad = gpad;
-    dt[i].negb = t.op == BFP_SUB ? 0xFFFFFFFFu : 0u;
-    dt[i].variant = (uint32_t)((fi * 2 + opc) * 2 + t.f.round);
-    words_total += (uint64_t)(1 + t.f.e + t.f.m) * gpad;
-    for (uint64_t w = 0; w < gpad; w += kChunkWords) {
-      BatchChunk ch;
-      ch.w0 = w;
-      ch.task = i;
-      ch.nwords = (uint32_t)std::min<uint64_t>(kChunkWords, gpad - w);
-      chunks.push_back(ch);
-    }
+    if (!batch_task(t.a, t.n, t.b, t.n, t.c, t.n, t.f, t.op, &dt[i])) return BFP_E_FORMAT;
+    words_total += (uint64_t)(1 + t.f.e + t.f.m) * dt[i].words;
   }
+  batch_chunks(dt, &chunks);
   if (chunks.size() >= 0xFFFFFFF0ull) return BFP_E_ARG;
-  // variant order; within a variant, longer tasks first, then by position
-  std::stable_sort(chunks.begin(), chunks.end(), [&](const BatchChunk& x, const BatchChunk& y) {
-    const uint32_t vx = dt[x.task].variant, vy = dt[y.task].variant;
-    if (vx != vy) return vx < vy;
-    if (dt[x.task].gpad != dt[y.task].gpad) return dt[x.task].gpad > dt[y.task].gpad;
-    if (x.task != y.task) return x.task < y.task;
-    return x.w0 < y.w0;
-  });
 
   bfp_batch_plan* p = new (std::nothrow) bfp_batch_plan();
   if (!p) return BFP_E_NOMEM;
@@ -203,15 +215,12 @@ bfp_status bfp_batch_plan_create(const bfp_task* tasks, uint32_t count, bfp_batc
     return BFP_E_HIP;
   }
   // resident grid: as many blocks as fit on the device at once
-  int per_cu = 0;
-  hipDeviceProp_t prop;
-  if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, k_batch, kBatchBlock, 0) != hipSuccess ||
-      hipGetDeviceProperties(&prop, p->device) != hipSuccess) {
+  const int resident = batch_resident_blocks();
+  if (resident <= 0) {
     plan_free(p);
     return BFP_E_HIP;
   }
-  if (per_cu < 1) per_cu = 1;
-  p->grid = (unsigned)std::min<uint64_t>((uint64_t)per_cu * prop.multiProcessorCount, p->nchunks);
+  p->grid = (unsigned)std::min<uint64_t>((uint64_t)resident, p->nchunks);
   // capture reset + persistent kernel once
   if (hipStreamCreateWithFlags(&p->capture_stream, hipStreamNonBlocking) != hipSuccess) {
     plan_free(p);
@@ -219,10 +228,9 @@ bfp_status bfp_batch_plan_create(const bfp_task* tasks, uint32_t count, bfp_batc
   }
   hipError_t e = hipStreamBeginCapture(p->capture_stream, hipStreamCaptureModeThreadLocal);
   if (e == hipSuccess) {
-    hipLaunchKernelGGL(k_batch_reset, dim3(1), dim3(64), 0, p->capture_stream, p->d_counter);
-    hipLaunchKernelGGL(k_batch, dim3(p->grid), dim3(kBatchBlock), 0, p->capture_stream,
-                       (const BatchTask*)p->d_tasks, (const BatchChunk*)p->d_chunks, p->nchunks, p->d_counter);
+    const hipError_t le = batch_launch(p->d_tasks, p->d_chunks, p->nchunks, p->d_counter, p->grid, p->capture_stream);
     e = hipStreamEndCapture(p->capture_stream, &p->graph);
+    if (le != hipSuccess) e = le;
   }
   if (e == hipSuccess) e = hipGraphInstantiate(&p->exec, p->graph, nullptr, nullptr, 0);
   if (e != hipSuccess) {
@@ -242,11 +250,8 @@ bfp_status bfp_batch_run(bfp_batch_plan* plan, void* stream) {
 bfp_status bfp_batch_run_eager(bfp_batch_plan* plan, void* stream) {
   if (!plan) return BFP_E_NULL;
   std::lock_guard<std::mutex> lk(plan->mu);
-  hipStream_t s = (hipStream_t)stream;
-  hipLaunchKernelGGL(k_batch_reset, dim3(1), dim3(64), 0, s, plan->d_counter);
-  hipLaunchKernelGGL(k_batch, dim3(plan->grid), dim3(kBatchBlock), 0, s, (const BatchTask*)plan->d_tasks,
-                     (const BatchChunk*)plan->d_chunks, plan->nchunks, plan->d_counter);
-  return hipGetLastError() == hipSuccess ? BFP_OK : BFP_E_HIP;
+  return batch_launch(plan->d_tasks, plan->d_chunks, plan->nchunks, plan->d_counter, plan->grid,
+                      (hipStream_t)stream) == hipSuccess ? BFP_OK : BFP_E_HIP;
 }
 
 bfp_status bfp_batch_run_per_vector(bfp_batch_plan* plan, void* stream) {

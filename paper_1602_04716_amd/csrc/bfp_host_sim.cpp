@@ -112,3 +112,113 @@ int bfpsim_transpose(int C, int inverse, const uint32_t* in, uint32_t* out) {
   }
 }
 }
+
+// ---------------------------------------------------------------------------
+// Serving scheduler core with a fake executor whose ticks complete only when
+// the test releases them (the host forces every condition: full budget, full
+// slots, both streams busy, launch failure).
+// ---------------------------------------------------------------------------
+#include <deque>
+
+#include "bfp_sched.hpp"
+
+namespace {
+struct FakeExecutor {
+  static constexpr int kStreams = 2;
+  std::deque<std::vector<bfp::SchedRequest>> running;
+  int releasable = 0;
+  int fail_next = 0;
+  int launch(const std::vector<bfp::SchedRequest>& reqs) {
+    if (fail_next) {
+      fail_next = 0;
+      return -5;
+    }
+    running.push_back(reqs);
+    return 0;
+  }
+  bool poll_done(std::vector<bfp::SchedRequest>* out) {
+    if (running.empty() || releasable <= 0) return false;
+    *out = running.front();
+    running.pop_front();
+    releasable--;
+    return true;
+  }
+};
+struct SimServer {
+  FakeExecutor ex;
+  bfp::Scheduler<FakeExecutor> sched;
+  uint64_t next_id = 1;
+  SimServer(uint64_t budget, int slots) : sched(ex, budget, slots) {}
+};
+}  // namespace
+
+extern "C" {
+void* simsrv_create(uint64_t budget, int slots) { return new SimServer(budget, slots); }
+void simsrv_destroy(void* p) { delete static_cast<SimServer*>(p); }
+uint32_t simsrv_put(void* p, uint64_t bytes, uint64_t n) {
+  auto* s = static_cast<SimServer*>(p);
+  uint32_t h;
+  uint64_t off;
+  return s->sched.alloc_resident(bytes, 5, 10, n, &h, &off) ? h : 0;
+}
+int simsrv_free(void* p, uint32_t h) { return static_cast<SimServer*>(p)->sched.free_resident(h) ? 0 : -1; }
+uint64_t simsrv_submit(void* p, uint64_t n, uint64_t c_bytes) {
+  auto* s = static_cast<SimServer*>(p);
+  bfp::SchedRequest r;
+  r.id = s->next_id++;
+  r.n = n;
+  r.c_bytes = c_bytes;
+  s->sched.submit(r);
+  return r.id;
+}
+int simsrv_step(void* p) { return static_cast<SimServer*>(p)->sched.step() ? 1 : 0; }
+void simsrv_release(void* p, int k) { static_cast<SimServer*>(p)->ex.releasable += k; }
+void simsrv_fail_next(void* p) { static_cast<SimServer*>(p)->ex.fail_next = 1; }
+int simsrv_running_ticks(void* p) { return (int)static_cast<SimServer*>(p)->ex.running.size(); }
+// completions: ids[i], handles[i], status[i]; returns count
+int simsrv_take(void* p, uint64_t* ids, uint32_t* handles, int32_t* status, int max) {
+  auto* s = static_cast<SimServer*>(p);
+  std::vector<bfp::SchedRequest> tmp((size_t)max);
+  const size_t k = s->sched.take_completed(tmp.data(), (size_t)max);
+  for (size_t i = 0; i < k; ++i) {
+    ids[i] = tmp[i].id;
+    handles[i] = tmp[i].c_handle;
+    status[i] = tmp[i].status;
+  }
+  return (int)k;
+}
+// used, high_water, capacity, pending, inflight requests, ticks, max_tick_requests,
+// max_inflight_ticks, deferred_budget, admitted, completed
+void simsrv_stats(void* p, uint64_t* out) {
+  auto* s = static_cast<SimServer*>(p);
+  const bfp::SchedStats& st = s->sched.stats();
+  out[0] = s->sched.used();
+  out[1] = s->sched.high_water();
+  out[2] = s->sched.capacity();
+  out[3] = s->sched.pending();
+  out[4] = (uint64_t)s->sched.inflight_requests();
+  out[5] = st.ticks;
+  out[6] = st.max_tick_requests;
+  out[7] = st.max_inflight_ticks;
+  out[8] = st.deferred_budget;
+  out[9] = st.admitted;
+  out[10] = st.completed;
+}
+
+// Arena alone
+void* simarena_create(uint64_t cap) { return new bfp::Arena(cap); }
+void simarena_destroy(void* a) { delete static_cast<bfp::Arena*>(a); }
+int64_t simarena_alloc(void* a, uint64_t bytes) {
+  uint64_t off;
+  return static_cast<bfp::Arena*>(a)->alloc(bytes, &off) ? (int64_t)off : -1;
+}
+uint64_t simarena_release(void* a, uint64_t off) { return static_cast<bfp::Arena*>(a)->release(off); }
+void simarena_stats(void* a, uint64_t* out) {
+  auto* ar = static_cast<bfp::Arena*>(a);
+  out[0] = ar->used();
+  out[1] = ar->high_water();
+  out[2] = ar->capacity();
+  out[3] = ar->live_count();
+  out[4] = ar->free_ranges();
+}
+}

@@ -1,0 +1,64 @@
+"""Autotuner: installs a valid configuration that it measured, and results
+stay bit-exact under every configuration it can choose."""
+import numpy as np
+import pytest
+
+torch = pytest.importorskip("torch")
+
+import oracle
+from paper_1602_04716_amd import bfp, inputs
+
+pytestmark = pytest.mark.gpu
+
+
+@pytest.fixture(scope="module", autouse=True)
+def gpu():
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+    bfp.lib()
+    oracle.build()
+
+
+@pytest.mark.parametrize("e,m,op", [(5, 10, "add"), (8, 23, "mul"), (3, 1, "sub")])
+def test_autotune_installs_measured_best(e, m, op):
+    f = bfp.fmt(e, m)
+    old = bfp.bfp_launch_get(op, f)
+    best, us = bfp.bfp_autotune(op, f, 1 << 20, 3, 2)
+    assert us > 0
+    cur = bfp.bfp_launch_get(op, f)
+    assert (cur.words_per_lane, cur.block, cur.blocks_per_cu) == (best.words_per_lane, best.block, best.blocks_per_cu)
+    assert best.words_per_lane in (1, 2) and best.block in (64, 128, 256, 512) and best.blocks_per_cu in (0, 4, 8)
+    best1, _ = bfp.bfp_autotune(op, f, 1 << 18, 1, 1)
+    assert best1.words_per_lane == 1
+    bfp.bfp_launch_set(op, f, old.words_per_lane, old.block, old.blocks_per_cu)
+
+
+def test_every_candidate_configuration_is_exact():
+    """All 24 launch variants give identical, oracle-exact results (ragged n)."""
+    e, m = 6, 7
+    n = 300000 + 5
+    a = inputs.sweep_operands(e, m, n, 1)
+    b = inputs.sweep_operands(e, m, n, 2)
+    want = oracle.binop("mul", e, m, 0, a, b, nthreads=8)
+    f = bfp.fmt(e, m)
+    pa, pb = bfp.pack(f, torch.from_numpy(a).cuda()), bfp.pack(f, torch.from_numpy(b).cuda())
+    old = bfp.bfp_launch_get("mul", f)
+    for wpl in (1, 2):
+        for blk in (64, 128, 256, 512):
+            for bpc in (0, 4, 8):
+                bfp.bfp_launch_set("mul", f, wpl, blk, bpc)
+                pc = bfp.empty_bitslice(f, n)
+                bfp.bfp_mul(f, pa, pb, pc, n)
+                got = bfp.unpack(f, pc, n).cpu().numpy().astype(np.uint32)
+                assert np.array_equal(got, want), (wpl, blk, bpc)
+    bfp.bfp_launch_set("mul", f, old.words_per_lane, old.block, old.blocks_per_cu)
+
+
+def test_autotune_errors():
+    f = bfp.fmt(5, 10)
+    with pytest.raises(bfp.BfpError):
+        bfp.bfp_autotune("add", f, 0, 3, 1)
+    with pytest.raises(bfp.BfpError):
+        bfp.bfp_autotune("add", f, 1024, 0, 1)
+    with pytest.raises(bfp.BfpError):
+        bfp.bfp_autotune("add", bfp.fmt(7, 4), 1024, 3, 1)
