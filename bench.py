@@ -128,7 +128,7 @@ def device_kernel(label):
     B = 1 + e + m
     C = 1 if B <= 8 else (2 if B <= 16 else 4)
     if kind == "pack":
-        return "bfp::k_pack<%d, 1>" % C
+        return "bfp::k_pack<%d>" % C
     if kind == "unpack":
         return "bfp::k_unpack<%d>" % C
     return "bfp::k_binop<%d, %d, false, %d, 2>" % (e, m, 1 if kind == "mul" else 0)

@@ -168,27 +168,61 @@ __device__ __forceinline__ void store_std(uint8_t* dst, uint64_t e0, uint64_t n,
 }
 
 // Standard -> bitslice over all gpad words of each plane (padding words get
-// zero bits).  B planes of the 8 C computed are stored.
-template <int C, int R>
+// zero bits); B of the 8 C planes computed are stored.  Work goes in wave
+// tiles of 64 groups (2048 elements): a tile wholly below n is read with
+// coalesced streaming 16-byte loads (each load instruction of the wave covers
+// one contiguous 1 KiB) into LDS, XOR-swizzled per lane so that each lane then
+// reads its own 32 C bytes without bank conflicts; the ragged last tile and
+// padding tiles read element by element.  Plane stores are ordinary stores,
+// so the planes stay cache-resident for the operation that follows.  Loops run
+// per block so every thread meets the same barriers.  Dynamic LDS:
+// (blockDim / 64) * 2048 C bytes.
+template <int C>
 __global__ void __launch_bounds__(512) k_pack(const uint8_t* src, uint32_t* planes, uint64_t n,
                                               uint64_t gpad, int B) {
-  const uint64_t nt = gpad / R;
-  const uint64_t stride = (uint64_t)gridDim.x * blockDim.x;
-  for (uint64_t t = (uint64_t)blockIdx.x * blockDim.x + threadIdx.x; t < nt; t += stride) {
-    const uint64_t g0 = t * R;
-    uint32_t in[R][8 * C];
-    load_std<C, R>(src, g0 * 32, n, in);
-    WordR<R> pl[8 * C];
+  extern __shared__ u32x4 pack_lds[];
+  constexpr int CH = 2 * C;  // 16-byte chunks per lane
+  const int nw = blockDim.x >> 6;
+  const int wave = threadIdx.x >> 6, lane = threadIdx.x & 63;
+  u32x4* tile = pack_lds + wave * 64 * CH;
+  const uint64_t tiles = gpad / 64;  // gpad is a multiple of 64
+  const uint64_t block_tiles = (tiles + nw - 1) / nw;
+  for (uint64_t bt = blockIdx.x; bt < block_tiles; bt += gridDim.x) {
+    const uint64_t t = bt * nw + wave;
+    const bool active = t < tiles;
+    const bool full = (t + 1) * 2048 <= n;
+    if (active && full) {
+      const u32x4* p = reinterpret_cast<const u32x4*>(src + t * 2048 * C);
 #pragma unroll
-    for (int r = 0; r < R; ++r) {
-      uint32_t tmp[8 * C];
-      transpose_pack<C>(in[r], tmp);
-#pragma unroll
-      for (int k = 0; k < 8 * C; ++k) pl[k].w[r] = tmp[k];
+      for (int j = 0; j < CH; ++j) {
+        const int idx = lane + 64 * j;
+        const int owner = idx / CH, q = idx % CH;
+        tile[owner * CH + (q ^ (owner & (CH - 1)))] = __builtin_nontemporal_load(p + idx);
+      }
     }
+    __syncthreads();
+    if (active) {
+      const uint64_t g = t * 64 + lane;
+      uint32_t in[1][8 * C];
+      if (full) {
 #pragma unroll
-    for (int k = 0; k < 8 * C; ++k)
-      if (k < B) st_words<R>(planes + (uint64_t)k * gpad + g0, pl[k]);
+        for (int q = 0; q < CH; ++q) {
+          const u32x4 v = tile[lane * CH + (q ^ (lane & (CH - 1)))];
+          in[0][4 * q + 0] = v.x;
+          in[0][4 * q + 1] = v.y;
+          in[0][4 * q + 2] = v.z;
+          in[0][4 * q + 3] = v.w;
+        }
+      } else {
+        load_std<C, 1>(src, g * 32, n, in);
+      }
+      uint32_t pl[8 * C];
+      transpose_pack<C>(in[0], pl);
+#pragma unroll
+      for (int k = 0; k < 8 * C; ++k)
+        if (k < B) planes[(uint64_t)k * gpad + g] = pl[k];
+    }
+    __syncthreads();
   }
 }
 

@@ -112,10 +112,11 @@ bfp_status hip_status(hipError_t e) { return e == hipSuccess ? BFP_OK : BFP_E_HI
 
 typedef hipError_t (*PackLauncher)(const void*, void*, uint64_t, uint64_t, int, unsigned, unsigned, hipStream_t);
 
-template <int C, int R>
+template <int C>
 hipError_t launch_pack(const void* src, void* dst, uint64_t n, uint64_t gpad, int B, unsigned grid,
                        unsigned block, hipStream_t s) {
-  hipLaunchKernelGGL((k_pack<C, R>), dim3(grid), dim3(block), 0, s, static_cast<const uint8_t*>(src),
+  const size_t lds = (size_t)(block / 64) * 2048 * C;
+  hipLaunchKernelGGL((k_pack<C>), dim3(grid), dim3(block), lds, s, static_cast<const uint8_t*>(src),
                      static_cast<uint32_t*>(dst), n, gpad, B);
   return hipGetLastError();
 }
@@ -178,7 +179,7 @@ bfp_status bfp_pack(bfp_format f, const void* std_in, void* bs_out, uint64_t n, 
   if (overlap(std_in, n * C, bs_out, (size_t)B * gpad * 4)) return BFP_E_ALIAS;
   const int block = 256;
   const unsigned grid = grid_for(gpad, block, 0);
-  PackLauncher L = C == 1 ? launch_pack<1, 1> : (C == 2 ? launch_pack<2, 1> : launch_pack<4, 1>);
+  PackLauncher L = C == 1 ? launch_pack<1> : (C == 2 ? launch_pack<2> : launch_pack<4>);
   return hip_status(L(std_in, bs_out, n, gpad, B, grid, block, (hipStream_t)stream));
 }
 
