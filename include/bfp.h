@@ -284,6 +284,28 @@ bfp_status bfp_server_submit(bfp_server* s, int op, bfp_format f, uint32_t a, ui
 /* Move up to `max` completions (oldest first) to `out`; *count is set. */
 bfp_status bfp_server_poll(bfp_server* s, bfp_completion* out, uint32_t max, uint32_t* count);
 
+/* One entry of an arrival schedule for bfp_server_replay. */
+typedef struct {
+  int32_t op;
+  bfp_format f;
+  uint32_t a, b;       /* operand handles */
+  uint64_t n;
+  int64_t arrival_ns;  /* submission time, ns after the replay call starts; non-decreasing */
+} bfp_request;
+
+/* Submit `count` requests from the calling thread, each at its arrival time
+ * (the thread sleeps until shortly before and then spins), so an arrival
+ * process is driven at native speed.  Ids are consecutive from *first_id.
+ * Ops, formats and the arrival order are checked before the first entry is
+ * submitted; an invalid handle or length stops the replay at that entry
+ * with its error (earlier entries stay submitted).  Returns when the last
+ * entry is submitted; completions are polled as usual. */
+bfp_status bfp_server_replay(bfp_server* s, const bfp_request* reqs, uint32_t count, uint64_t* first_id);
+
+/* With `on` nonzero, each result vector is returned to the arena as soon as
+ * its request completes (its completion reports result 0). */
+bfp_status bfp_server_set_autofree(bfp_server* s, int32_t on);
+
 /* Wait until no request is queued, admitted or running (BFP_E_ARG on timeout). */
 bfp_status bfp_server_wait_idle(bfp_server* s, int64_t timeout_ms);
 

@@ -52,6 +52,11 @@ class bfp_completion(ctypes.Structure):
                 ("t_launch_ns", ctypes.c_int64), ("t_done_ns", ctypes.c_int64)]
 
 
+class bfp_request(ctypes.Structure):
+    _fields_ = [("op", ctypes.c_int32), ("f", bfp_format), ("a", ctypes.c_uint32), ("b", ctypes.c_uint32),
+                ("n", ctypes.c_uint64), ("arrival_ns", ctypes.c_int64)]
+
+
 class bfp_server_stats(ctypes.Structure):
     _fields_ = [(k, ctypes.c_uint64) for k in (
         "budget", "used", "high_water", "submitted", "admitted", "completed", "ticks", "max_tick_requests",
@@ -112,6 +117,9 @@ _SIGS = {
     "bfp_server_poll": (ctypes.c_int, [ctypes.c_void_p, ctypes.POINTER(bfp_completion), ctypes.c_uint32,
                                        ctypes.POINTER(ctypes.c_uint32)]),
     "bfp_server_wait_idle": (ctypes.c_int, [ctypes.c_void_p, ctypes.c_int64]),
+    "bfp_server_replay": (ctypes.c_int, [ctypes.c_void_p, ctypes.POINTER(bfp_request), ctypes.c_uint32,
+                                         ctypes.POINTER(ctypes.c_uint64)]),
+    "bfp_server_set_autofree": (ctypes.c_int, [ctypes.c_void_p, ctypes.c_int32]),
     "bfp_server_view": (ctypes.c_int, [ctypes.c_void_p, ctypes.c_uint32, ctypes.POINTER(ctypes.c_void_p),
                                        ctypes.POINTER(ctypes.c_uint64)]),
     "bfp_server_get": (ctypes.c_int, [ctypes.c_void_p, ctypes.c_uint32, bfp_format, ctypes.c_void_p,
@@ -350,6 +358,20 @@ def bfp_server_poll(server: int, max_items: int = 4096):
     cnt = ctypes.c_uint32()
     _check(lib().bfp_server_poll(server, buf, max_items, ctypes.byref(cnt)), "bfp_server_poll")
     return [buf[i] for i in range(cnt.value)]
+
+
+def bfp_server_replay(server: int, reqs) -> int:
+    """reqs: sequence of (op, format, a, b, n, arrival_ns); returns the first id."""
+    arr = (bfp_request * len(reqs))()
+    for i, (op, f, a, b, n, t) in enumerate(reqs):
+        arr[i] = bfp_request(_op(op), f, a, b, n, int(t))
+    first = ctypes.c_uint64()
+    _check(lib().bfp_server_replay(server, arr, len(reqs), ctypes.byref(first)), "bfp_server_replay")
+    return first.value
+
+
+def bfp_server_set_autofree(server: int, on: bool):
+    _check(lib().bfp_server_set_autofree(server, 1 if on else 0), "bfp_server_set_autofree")
 
 
 def bfp_server_wait_idle(server: int, timeout_ms: int = 60000):

@@ -124,6 +124,10 @@ class Scheduler {
 
   std::mutex& mutex() { return mu_; }
 
+  // Free each result as soon as its request completes (the completion is
+  // still reported, with result handle 0).
+  void set_autofree(bool on) { autofree_ = on; }
+
   // ---- resident vectors (caller holds mutex) ----
   bool alloc_resident(uint64_t bytes, uint8_t e, uint8_t m, uint64_t n, uint32_t* handle, uint64_t* off) {
     if (!arena_.alloc(bytes, off)) return false;
@@ -168,6 +172,10 @@ class Scheduler {
       for (auto& r : done) {
         r.t_done = t;
         inflight_reqs_--;
+        if (autofree_ && r.status == 0) {
+          free_resident(r.c_handle);
+          r.c_handle = 0;
+        }
         completed_.push_back(r);
         stats_.completed++;
       }
@@ -246,6 +254,7 @@ class Scheduler {
   std::deque<SchedRequest> completed_;
   int inflight_reqs_ = 0;
   int inflight_ticks_ = 0;
+  bool autofree_ = false;
   SchedStats stats_;
 };
 

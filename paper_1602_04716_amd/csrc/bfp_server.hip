@@ -296,6 +296,39 @@ bfp_status bfp_server_submit(bfp_server* s, int op, bfp_format f, uint32_t a, ui
   return BFP_OK;
 }
 
+bfp_status bfp_server_set_autofree(bfp_server* s, int32_t on) {
+  if (!s) return BFP_E_NULL;
+  std::lock_guard<std::mutex> lk(s->sched->mutex());
+  s->sched->set_autofree(on != 0);
+  return BFP_OK;
+}
+
+bfp_status bfp_server_replay(bfp_server* s, const bfp_request* reqs, uint32_t count, uint64_t* first_id) {
+  if (!s || (count && !reqs)) return BFP_E_NULL;
+  // check everything first so a bad entry cannot leave a half-submitted schedule
+  for (uint32_t i = 0; i < count; ++i) {
+    const bfp_request& r = reqs[i];
+    if (r.op != BFP_ADD && r.op != BFP_SUB && r.op != BFP_MUL) return BFP_E_OP;
+    if (!bfp_format_supported(r.f)) return BFP_E_FORMAT;
+    if (r.arrival_ns < 0 || (i && r.arrival_ns < reqs[i - 1].arrival_ns)) return BFP_E_ARG;
+  }
+  const int64_t t0 = now_ns();
+  for (uint32_t i = 0; i < count; ++i) {
+    const int64_t due = t0 + reqs[i].arrival_ns;
+    for (;;) {  // sleep while far from the arrival time, spin close to it
+      const int64_t left = due - now_ns();
+      if (left <= 0) break;
+      if (left > 200000) std::this_thread::sleep_for(std::chrono::nanoseconds(left - 100000));
+      else std::this_thread::yield();
+    }
+    uint64_t id;
+    const bfp_status st = bfp_server_submit(s, reqs[i].op, reqs[i].f, reqs[i].a, reqs[i].b, reqs[i].n, &id);
+    if (st != BFP_OK) return st;
+    if (i == 0 && first_id) *first_id = id;
+  }
+  return BFP_OK;
+}
+
 bfp_status bfp_server_poll(bfp_server* s, bfp_completion* out, uint32_t max, uint32_t* count) {
   if (!s || !count || (max && !out)) return BFP_E_NULL;
   std::vector<SchedRequest> tmp(max);

@@ -60,6 +60,12 @@ class Server:
     def stats(self) -> dict:
         return bfp.bfp_server_stats_get(self.h)
 
+    def replay(self, reqs) -> int:
+        return bfp.bfp_server_replay(self.h, reqs)
+
+    def set_autofree(self, on: bool):
+        bfp.bfp_server_set_autofree(self.h, on)
+
     def wait_idle(self, timeout_ms: int = 60000):
         bfp.bfp_server_wait_idle(self.h, timeout_ms)
 
@@ -154,3 +160,46 @@ def run(server: Server, pool, reqs, rate=None, rnd: int = 0, seed: int = 0, keep
             "requests_per_s": len(meas) / window, "elements_per_s": elements / window,
             "p50_us": float(np.percentile(lat, 50)), "p99_us": float(np.percentile(lat, 99)),
             "mean_us": float(lat.mean()), "rate": rate, "ids": ids, "completions": comp}
+
+
+def run_native(server: Server, pool, reqs, rate=None, rnd: int = 0, seed: int = 0, skip: int = 0,
+               timeout_s: float = 120.0):
+    """Like run(), but the arrival schedule is submitted by bfp_server_replay
+    from native code and results are freed by the server on completion, so
+    the measurement is of the server, not of a Python loop."""
+    rng = np.random.default_rng(seed)
+    n_req = len(reqs)
+    if rate is None:
+        arrivals = np.zeros(n_req, dtype=np.int64)
+    else:
+        arrivals = np.floor(np.cumsum(rng.exponential(1e9 / rate, n_req))).astype(np.int64)
+    sched = []
+    for k, (op, (e, m), n) in enumerate(reqs):
+        a, b, _n0 = pool[(e, m)]
+        sched.append((op, bfp.fmt(e, m, rnd), a, b, n, int(arrivals[k])))
+    server.set_autofree(True)
+    first = server.replay(sched)
+    comp = {}
+    deadline = time.perf_counter() + timeout_s
+    while len(comp) < n_req:
+        got = server.poll()
+        for c in got:
+            comp[c.req_id] = (c.status, c.result, c.t_submit_ns, c.t_done_ns, c.t_launch_ns)
+        if not got:
+            if time.perf_counter() > deadline:
+                raise RuntimeError("serving stalled: %d of %d complete, stats %s" % (len(comp), n_req,
+                                                                                     server.stats()))
+            time.sleep(0.0005)
+    server.set_autofree(False)
+    ids = list(range(first, first + n_req))
+    meas = ids[skip:]
+    lat = np.array([(comp[r][3] - comp[r][2]) / 1e3 for r in meas])
+    t_first = min(comp[r][2] for r in meas)
+    t_last = max(comp[r][3] for r in meas)
+    window = (t_last - t_first) / 1e9
+    elements = sum(reqs[k][2] for k in range(skip, n_req))
+    bad = sum(1 for r in ids if comp[r][0] != 0)
+    return {"requests": len(meas), "errors": bad, "elements": elements, "window_s": window,
+            "requests_per_s": len(meas) / window, "elements_per_s": elements / window,
+            "p50_us": float(np.percentile(lat, 50)), "p99_us": float(np.percentile(lat, 99)),
+            "mean_us": float(lat.mean()), "rate": rate}

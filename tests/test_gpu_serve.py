@@ -115,3 +115,23 @@ def test_server_errors():
     with pytest.raises(bfp.BfpError):
         srv.free(h)
     srv.close()
+
+
+def test_native_replay_poisson_autofree():
+    srv = serving.Server(1 << 30, 128)
+    pool = serving.build_pool(srv, FMTS, N0, seed=9, device="cuda")
+    pool_bytes = srv.stats()["used"]
+    reqs = serving.request_stream(2000, FMTS, seed=10, nmin_log2=5, nmax_log2=15.5, nmax=N0)
+    sat = serving.run_native(srv, pool, reqs)
+    assert sat["errors"] == 0 and sat["requests"] == 2000
+    r = serving.run_native(srv, pool, reqs, rate=0.5 * sat["requests_per_s"], seed=3, skip=100)
+    assert r["errors"] == 0 and r["requests"] == 1900 and r["p99_us"] >= r["p50_us"] > 0
+    srv.wait_idle()
+    st = srv.stats()
+    assert st["used"] == pool_bytes  # every result went back to the arena
+    assert st["max_inflight_ticks"] >= 1 and st["high_water"] <= st["budget"]
+    with pytest.raises(bfp.BfpError):  # arrivals out of order are rejected before submission
+        srv.replay([("add", bfp.fmt(5, 10), pool[(5, 10)][0], pool[(5, 10)][1], 10, 1000),
+                    ("add", bfp.fmt(5, 10), pool[(5, 10)][0], pool[(5, 10)][1], 10, 0)])
+    assert srv.stats()["submitted"] == st["submitted"]
+    srv.close()
