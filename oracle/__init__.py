@@ -5,9 +5,9 @@ check in ``__graft_entry__`` and by the CPU-baseline leg of ``bench.py``.  The
 GPU library and its Python binding never import it.
 
 The arithmetic lives in ``bfp_oracle.c`` (plain C, exact integers): decode to
-(sign, integer significand, exponent), compute the exact sum or product, round
-once to nearest-even or toward zero (Section 4 of the paper fixes the two
-modes; Table 1 the operations).  This module only marshals numpy arrays.
+(sign, integer significand, exponent), compute the exact sum, product or
+quotient, round once to nearest-even or toward zero (Section 4 of the paper
+fixes the two modes; Table 1 the operations).  This module only marshals numpy arrays.
 """
 from __future__ import annotations
 
@@ -21,9 +21,9 @@ _HERE = os.path.dirname(os.path.abspath(__file__))
 _SRC = os.path.join(_HERE, "bfp_oracle.c")
 _LIB = os.path.join(_HERE, "liboracle.so")
 
-ADD, SUB, MUL = 0, 1, 2
+ADD, SUB, MUL, DIV = 0, 1, 2, 3
 RNE, RZ = 0, 1
-OPS = {"add": ADD, "sub": SUB, "mul": MUL}
+OPS = {"add": ADD, "sub": SUB, "mul": MUL, "div": DIV}
 
 
 def build(force: bool = False) -> str:

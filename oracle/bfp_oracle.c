@@ -12,7 +12,7 @@
  * product with wide unsigned integers, and round once.  The paper fixes the
  * two rounding modes (Section 4: round toward zero, and round to nearest with
  * ties to even) and the three arithmetic operations (Section 4, Table 1:
- * add/sub, mul; div is not built here).  Everything the paper leaves open
+ * add/sub, mul, div).  Everything the paper leaves open
  * (bias, subnormals, infinities and NaN, overflow, the sign of an exact zero,
  * NaN output bits) follows IEEE 754-2008 binary interchange semantics
  * generalised to (e, m); each such reading is listed in the design notes.
@@ -31,6 +31,7 @@
 #define ORACLE_ADD 0
 #define ORACLE_SUB 1
 #define ORACLE_MUL 2
+#define ORACLE_DIV 3
 
 /* ------------------------------------------------------------------------ */
 /* 384-bit unsigned integers                                                 */
@@ -265,9 +266,36 @@ static uint32_t op_mul(uint32_t a, uint32_t b, int e, int m, int mode) {
     return round_exact(s, &S, x.q + y.q, e, m, mode);
 }
 
+/* a / b.  The exact quotient sig_a / sig_b is represented for rounding as
+ * S = 2 * floor(sig_a * 2^k / sig_b) + [remainder != 0] at exponent
+ * qa - qb - k - 1: with k chosen so the integer quotient has at least m + 3
+ * bits, no rounding boundary of the format lies strictly between the exact
+ * quotient and S * 2^(qa-qb-k-1) (both lie in the same open interval between
+ * consecutive multiples of 2^(qa-qb-k), and every boundary is a multiple of
+ * that unit), so rounding S rounds the exact quotient. */
+static uint32_t op_div(uint32_t a, uint32_t b, int e, int m, int mode) {
+    decoded x = decode(a, e, m), y = decode(b, e, m);
+    int s = x.s ^ y.s; /* sign of the quotient */
+    if (x.cls == CLS_NAN || y.cls == CLS_NAN) return canonical_nan(e, m);
+    if (x.cls == CLS_INF && y.cls == CLS_INF) return canonical_nan(e, m);
+    if (x.cls == CLS_ZERO && y.cls == CLS_ZERO) return canonical_nan(e, m);
+    if (x.cls == CLS_INF) return infinity(s, e, m);
+    if (y.cls == CLS_INF) return encode(s, 0, 0, e, m);
+    if (y.cls == CLS_ZERO) return infinity(s, e, m); /* finite nonzero / 0 */
+    if (x.cls == CLS_ZERO) return encode(s, 0, 0, e, m);
+    const int k = 2 * m + 6; /* sig_a * 2^k / sig_b >= 2^k / 2^(m+1) = 2^(m+5) */
+    unsigned __int128 num = (unsigned __int128)x.sig << k; /* < 2^(3m+7) <= 2^76 */
+    unsigned __int128 quo = num / y.sig;
+    unsigned __int128 rem = num % y.sig;
+    unsigned __int128 s2 = 2 * quo + (rem != 0); /* < 2^77 */
+    big S = big_from_u64((uint64_t)s2);
+    S.w[1] = (uint64_t)(s2 >> 64);
+    return round_exact(s, &S, x.q - y.q - k - 1, e, m, mode);
+}
+
 static int format_ok(int e, int m) { return e >= 2 && e <= 8 && m >= 1 && m <= 23; }
 
-/* One element.  op: 0 add, 1 sub, 2 mul.  mode: 0 RNE, 1 RZ.
+/* One element.  op: 0 add, 1 sub, 2 mul, 3 div.  mode: 0 RNE, 1 RZ.
  * Returns the result pattern, or 0xFFFFFFFF for an invalid argument. */
 uint32_t oracle_op1(int op, int e, int m, int mode, uint32_t a, uint32_t b) {
     if (!format_ok(e, m) || (mode != ORACLE_RNE && mode != ORACLE_RZ)) return 0xFFFFFFFFu;
@@ -278,6 +306,7 @@ uint32_t oracle_op1(int op, int e, int m, int mode, uint32_t a, uint32_t b) {
     case ORACLE_ADD: return op_add(a, b, e, m, mode);
     case ORACLE_SUB: return op_add(a, b ^ (1u << (e + m)), e, m, mode); /* a + (-b) */
     case ORACLE_MUL: return op_mul(a, b, e, m, mode);
+    case ORACLE_DIV: return op_div(a, b, e, m, mode);
     default: return 0xFFFFFFFFu;
     }
 }
@@ -320,7 +349,7 @@ static void *run_job(void *p) {
  * Returns 0, or -1 for an invalid argument. */
 int oracle_binop(int op, int e, int m, int mode, const uint32_t *a, const uint32_t *b,
                  uint32_t *c, uint64_t n, int nthreads) {
-    if (!format_ok(e, m) || op < 0 || op > 2 || (mode != 0 && mode != 1)) return -1;
+    if (!format_ok(e, m) || op < 0 || op > 3 || (mode != 0 && mode != 1)) return -1;
     if (nthreads < 1) nthreads = 1;
     if (nthreads > 256) nthreads = 256;
     if ((uint64_t)nthreads > n) nthreads = n ? (int)n : 1;

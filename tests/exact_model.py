@@ -64,8 +64,9 @@ class Table:
         emax = f.emax_field - 1 - f.bias
         self.virtual = int(Fraction(2) ** (emax + 1) * 2 ** shift)
 
-    def round_mag(self, X: int, mode: int) -> int:
-        """Round a non-negative scaled exact magnitude; returns a pattern (sign 0)."""
+    def round_mag(self, X, mode: int) -> int:
+        """Round a non-negative scaled exact magnitude (int or Fraction);
+        returns a pattern (sign 0)."""
         f = self.f
         i = bisect.bisect_right(self.vals, X) - 1  # vals[i] <= X
         lo_v, lo_p = self.vals[i], self.pats[i]
@@ -103,10 +104,19 @@ def ref_special(f: Fmt, op: str, a: int, b: int):
         return None
     za = (a & ~f.sign_bit) == 0
     zb = (b & ~f.sign_bit) == 0
+    sgn = (sa ^ sb) << (f.e + f.m)
+    if op == "div":
+        if (ia and ib) or (za and zb):
+            return f.nan
+        if ia or zb:
+            return f.pinf | sgn       # Inf / x, and x / 0 for finite nonzero x
+        if ib or za:
+            return sgn                # x / Inf, 0 / x: signed zero
+        return None
     if ia or ib:
         if za or zb:
             return f.nan
-        return f.pinf | ((sa ^ sb) << (f.e + f.m))
+        return f.pinf | sgn
     return None
 
 
@@ -120,6 +130,8 @@ def exact_result(f: Fmt, op: str, a: int, b: int):
         x = va + vb
         zsign = sa if sa == sb else 0  # exact zero: +0 unless both addends are -0-signed
         return x, zsign
+    if op == "div":
+        return va / vb, sa ^ sb
     return va * vb, sa ^ sb
 
 
@@ -132,8 +144,10 @@ def table_round(f: Fmt, tab_add: Table, tab_mul: Table, op: str, mode: int, a: i
     if x == 0:
         return zsign << (f.e + f.m)
     X = abs(x) * 2 ** tab.shift
-    assert X.denominator == 1
-    p = tab.round_mag(int(X), mode)
+    if op != "div":
+        assert X.denominator == 1
+        X = int(X)
+    p = tab.round_mag(X, mode)
     neg = x < 0
     return p | (f.sign_bit if neg else 0)
 

@@ -16,7 +16,7 @@ static unsigned clear_ftz_daz(void) {
     return old;
 }
 
-/* op: 0 add, 1 sub, 2 mul; mode: 0 nearest-even, 1 toward zero */
+/* op: 0 add, 1 sub, 2 mul, 3 div; mode: 0 nearest-even, 1 toward zero */
 void f32_binop(int op, int mode, const uint32_t *a, const uint32_t *b, uint32_t *c, size_t n) {
     unsigned csr = clear_ftz_daz();
     int old = fegetround();
@@ -30,7 +30,8 @@ void f32_binop(int op, int mode, const uint32_t *a, const uint32_t *b, uint32_t 
         y = ty;
         if (op == 0) r = x + y;
         else if (op == 1) r = x - y;
-        else r = x * y;
+        else if (op == 2) r = x * y;
+        else r = x / y;
         float tr = r;
         memcpy(&c[i], &tr, 4);
     }
@@ -42,7 +43,12 @@ void f32_binop(int op, int mode, const uint32_t *a, const uint32_t *b, uint32_t 
  * product of two of them is exact in double (at most 40 significant bits);
  * double -> float under FE_TOWARDZERO and float -> half with the F16C
  * truncating conversion round toward zero twice on nested grids, which equals
- * one rounding toward zero. */
+ * one rounding toward zero.  For division the double quotient is rounded
+ * (to nearest), but a quotient p/q of binary16 values (q < 2^11 as an integer
+ * significand) is either a float or at relative distance at least
+ * 2^-24 / q > 2^-35 from every float, far more than the 2^-53 of that
+ * rounding, so the rounded quotient stays on the exact quotient's side of
+ * every float and half grid point. */
 void f16_binop_rz(int op, const uint16_t *a, const uint16_t *b, uint16_t *c, size_t n) {
     unsigned csr = clear_ftz_daz();
     int old = fegetround();
@@ -52,7 +58,8 @@ void f16_binop_rz(int op, const uint16_t *a, const uint16_t *b, uint16_t *c, siz
         volatile double x = fa, y = fb, r;
         if (op == 0) r = x + y;
         else if (op == 1) r = x - y;
-        else r = x * y;
+        else if (op == 2) r = x * y;
+        else r = x / y;
         fesetround(FE_TOWARDZERO);
         volatile float rf = (float)r;
         fesetround(old);

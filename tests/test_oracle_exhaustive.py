@@ -1,7 +1,7 @@
 """Pin the oracle against an independent exact model (no GPU).
 
 * Every format of at most 8 bits in the sweep: all 2^B x 2^B operand pairs,
-  add/sub/mul, both rounding modes (Section 4: round toward zero and round to
+  add/sub/mul/div, both rounding modes (Section 4: round toward zero and round to
   nearest, ties to even), against exact-rational table search.
 * Every sweep format: random pairs plus the edge set, checked with the
   neighbour test (the result is correctly rounded iff no adjacent pattern is
@@ -17,7 +17,7 @@ SMALL = [(e, m) for (e, m) in sweep_formats() if 1 + e + m <= 8]
 
 
 @pytest.mark.parametrize("e,m", SMALL)
-@pytest.mark.parametrize("op", ["add", "sub", "mul"])
+@pytest.mark.parametrize("op", ["add", "sub", "mul", "div"])
 @pytest.mark.parametrize("mode", [0, 1])
 def test_exhaustive_small_formats(oracle_lib, e, m, op, mode):
     f = Fmt(e, m)
@@ -56,7 +56,7 @@ def test_nine_and_ten_bit_formats_sampled_table(oracle_lib, e, m):
     n = 4000
     a = rng.integers(0, 1 << f.B, n, dtype=np.uint32)
     b = rng.integers(0, 1 << f.B, n, dtype=np.uint32)
-    for op in ("add", "sub", "mul"):
+    for op in ("add", "sub", "mul", "div"):
         for mode in (0, 1):
             got = oracle_lib.binop(op, e, m, mode, a, b)
             for k in range(n):
@@ -66,7 +66,7 @@ def test_nine_and_ten_bit_formats_sampled_table(oracle_lib, e, m):
 
 def _neighbour_case(oracle_lib, e, m, a, b):
     f = Fmt(e, m)
-    for op in ("add", "sub", "mul"):
+    for op in ("add", "sub", "mul", "div"):
         for mode in (0, 1):
             got = oracle_lib.binop(op, e, m, mode, a, b)
             for k in range(a.size):

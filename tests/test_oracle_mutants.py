@@ -27,13 +27,22 @@ MUTANTS = [
     ("subnormal exponent off by one", "d.q = 1 - bias_of(e) - m;", "d.q = 0 - bias_of(e) - m;"),
     ("RZ overflow gives Inf", "if (mode == ORACLE_RNE) return infinity(s, e, m);", "return infinity(s, e, m);"),
     ("carry renormalisation dropped", "sig >>= 1;\n        qt += 1;", "qt += 0;"),
-    ("mul sign not xor", "int s = x.s ^ y.s;", "int s = x.s;"),
+    ("mul sign not xor", "int s = x.s ^ y.s;\n", "int s = x.s;\n"),
     ("sub does not negate", "return op_add(a, b ^ (1u << (e + m)), e, m, mode);", "return op_add(a, b, e, m, mode);"),
     ("inf*0 not NaN", "if (x.cls == CLS_ZERO || y.cls == CLS_ZERO) return canonical_nan(e, m);", ""),
     ("wrong bias", "static int bias_of(int e) { return (1 << (e - 1)) - 1; }",
      "static int bias_of(int e) { return (1 << (e - 1)); }"),
     ("borrow dropped in sub", "borrow = b1 | b2;", "borrow = b1;"),
     ("min exponent alignment", "int q0 = x.q < y.q ? x.q : y.q;", "int q0 = x.q > y.q ? y.q : y.q + 1;"),
+    ("div sticky dropped", "2 * quo + (rem != 0);", "2 * quo;"),
+    ("div exponent off by one", "x.q - y.q - k - 1, e, m, mode", "x.q - y.q - k, e, m, mode"),
+    ("div sign not xor", "int s = x.s ^ y.s; /* sign of the quotient */", "int s = x.s;"),
+    ("x/0 gives NaN", "if (y.cls == CLS_ZERO) return infinity(s, e, m);",
+     "if (y.cls == CLS_ZERO) return canonical_nan(e, m);"),
+    ("0/0 not NaN", "if (x.cls == CLS_ZERO && y.cls == CLS_ZERO) return canonical_nan(e, m);", ""),
+    ("x/Inf gives Inf", "if (y.cls == CLS_INF) return encode(s, 0, 0, e, m);",
+     "if (y.cls == CLS_INF) return infinity(s, e, m);"),
+    ("div guard bits too few", "const int k = 2 * m + 6;", "const int k = 1;"),
 ]
 
 
@@ -59,7 +68,20 @@ def _wide_gap_pairs():
     return a.astype(np.uint32), b.astype(np.uint32)
 
 
+def _small_dividend_quotients_disagree(L):
+    """binary16 subnormal / lowest-binade quotients against numpy's float16
+    division (round to nearest even): the fewest bits below the rounding point."""
+    a = np.repeat(np.arange(1, 1024, dtype=np.uint32), 1024)
+    b = np.tile(np.arange(1024, 2048, dtype=np.uint32), 1023)
+    c = np.empty_like(a)
+    L.oracle_binop(3, 5, 10, 0, a.ctypes.data, b.ctypes.data, c.ctypes.data, a.size, 8)
+    ha, hb = a.astype(np.uint16).view(np.float16), b.astype(np.uint16).view(np.float16)
+    return not np.array_equal(c, (ha / hb).view(np.uint16).astype(np.uint32))
+
+
 def _disagrees(L):
+    if _small_dividend_quotients_disagree(L):
+        return True
     f = Fmt(8, 23)
     a, b = _wide_gap_pairs()
     c = np.empty_like(a)
@@ -75,7 +97,7 @@ def _disagrees(L):
         a = np.repeat(np.arange(n, dtype=np.uint32), n)
         b = np.tile(np.arange(n, dtype=np.uint32), n)
         c = np.empty_like(a)
-        for opi, op in enumerate(("add", "sub", "mul")):
+        for opi, op in enumerate(("add", "sub", "mul", "div")):
             for mode in (0, 1):
                 L.oracle_binop(opi, e, m, mode, a.ctypes.data, b.ctypes.data, c.ctypes.data, a.size, 1)
                 for i in range(0, a.size, 5):

@@ -81,7 +81,7 @@ def _edges(e, m):
 
 
 @pytest.mark.parametrize("mode", [0, 1])
-@pytest.mark.parametrize("op", [0, 1, 2])
+@pytest.mark.parametrize("op", [0, 1, 2, 3])
 def test_binary32(oracle_lib, native, op, mode):
     rng = np.random.default_rng(23 + 3 * op + mode)
     a, b = _operands(rng, 8, 23, 200000)
@@ -93,7 +93,7 @@ def test_binary32(oracle_lib, native, op, mode):
     _compare(8, 23, got, want, a, b, ("f32", op, mode))
 
 
-@pytest.mark.parametrize("op", ["add", "sub", "mul"])
+@pytest.mark.parametrize("op", ["add", "sub", "mul", "div"])
 def test_binary16_rne_numpy(oracle_lib, op):
     rng = np.random.default_rng(16)
     a, b = _operands(rng, 5, 10, 400000)
@@ -101,13 +101,13 @@ def test_binary16_rne_numpy(oracle_lib, op):
     a, b = np.concatenate([a, ea]), np.concatenate([b, eb])
     ha, hb = a.astype(np.uint16).view(np.float16), b.astype(np.uint16).view(np.float16)
     with np.errstate(all="ignore"):
-        r = {"add": ha + hb, "sub": ha - hb, "mul": ha * hb}[op]
+        r = {"add": ha + hb, "sub": ha - hb, "mul": ha * hb, "div": ha / hb}[op]
     want = r.view(np.uint16).astype(np.uint32)
     got = oracle_lib.binop(op, 5, 10, 0, a, b, nthreads=4)
     _compare(5, 10, got, want, a, b, ("f16 rne", op))
 
 
-@pytest.mark.parametrize("op", [0, 1, 2])
+@pytest.mark.parametrize("op", [0, 1, 2, 3])
 def test_binary16_rz_f16c(oracle_lib, native, op):
     rng = np.random.default_rng(160 + op)
     a, b = _operands(rng, 5, 10, 400000)
@@ -127,14 +127,44 @@ def test_binary16_exhaustive_slice(oracle_lib):
     for av in rng.integers(0, 65536, 64):
         a = np.full(65536, av, dtype=np.uint32)
         ha, hb = a.astype(np.uint16).view(np.float16), bs.astype(np.uint16).view(np.float16)
-        for op in ("add", "mul"):
+        for op in ("add", "mul", "div"):
             with np.errstate(all="ignore"):
-                r = ha + hb if op == "add" else ha * hb
+                r = {"add": ha + hb, "mul": ha * hb, "div": ha / hb}[op]
             got = oracle_lib.binop(op, 5, 10, 0, a, bs)
             _compare(5, 10, got, r.view(np.uint16).astype(np.uint32), a, bs, ("f16 slice", op))
 
 
-@pytest.mark.parametrize("op", ["add", "sub", "mul"])
+def test_division_small_dividends(oracle_lib, native):
+    """Quotients of a subnormal by a value of the lowest binades: the integer
+    quotient then has the fewest bits below the rounding point, so a dropped
+    remainder (a tie mistaken for an exact half) shows.  binary16: every
+    subnormal against every divisor with biased exponent 1 or 2, both modes;
+    binary32: small subnormal dividends against sampled low-binade divisors."""
+    a1 = np.arange(1024, dtype=np.uint32)
+    b1 = np.arange(1024, 3072, dtype=np.uint32)
+    a = np.repeat(a1, b1.size)
+    b = np.tile(b1, a1.size) | (np.arange(a.size, dtype=np.uint32) & 1) << 15
+    ha, hb = a.astype(np.uint16).view(np.float16), b.astype(np.uint16).view(np.float16)
+    with np.errstate(all="ignore"):
+        want = (ha / hb).view(np.uint16).astype(np.uint32)
+    _compare(5, 10, oracle_lib.binop("div", 5, 10, 0, a, b, nthreads=8), want, a, b, ("f16 div", 0))
+    a16, b16 = a.astype(np.uint16), b.astype(np.uint16)
+    w16 = np.empty_like(a16)
+    native.f16_binop_rz(3, a16.ctypes.data, b16.ctypes.data, w16.ctypes.data, a16.size)
+    _compare(5, 10, oracle_lib.binop("div", 5, 10, 1, a, b, nthreads=8), w16.astype(np.uint32),
+             a, b, ("f16 div", 1))
+    rng = np.random.default_rng(41)
+    bs = ((rng.integers(1, 4, 20000) << 23) | rng.integers(0, 1 << 23, 20000)).astype(np.uint32)
+    a = np.repeat(np.arange(1, 33, dtype=np.uint32), bs.size)
+    b = np.tile(bs, 32)
+    for mode in (0, 1):
+        want = np.empty_like(a)
+        native.f32_binop(3, mode, a.ctypes.data, b.ctypes.data, want.ctypes.data, a.size)
+        _compare(8, 23, oracle_lib.binop("div", 8, 23, mode, a, b, nthreads=8), want, a, b,
+                 ("f32 div", mode))
+
+
+@pytest.mark.parametrize("op", ["add", "sub", "mul", "div"])
 def test_bfloat16_rne_torch(oracle_lib, op):
     torch = pytest.importorskip("torch")
     torch.set_flush_denormal(False)
@@ -149,7 +179,7 @@ def test_bfloat16_rne_torch(oracle_lib, op):
     a, b = np.concatenate([a, ea]), np.concatenate([b, eb])
     ta = torch.from_numpy(a.astype(np.uint16).view(np.int16)).view(torch.bfloat16)
     tb = torch.from_numpy(b.astype(np.uint16).view(np.int16)).view(torch.bfloat16)
-    r = {"add": ta + tb, "sub": ta - tb, "mul": ta * tb}[op]
+    r = {"add": ta + tb, "sub": ta - tb, "mul": ta * tb, "div": ta / tb}[op]
     want = r.view(torch.int16).numpy().view(np.uint16).astype(np.uint32)
     got = oracle_lib.binop(op, 8, 7, 0, a, b, nthreads=4)
     _compare(8, 7, got, want, a, b, ("bf16", op))
