@@ -64,7 +64,7 @@ typedef int bfp_status;
 #define BFP_E_FORMAT (-1)   /* (e, m) not compiled, or round not RNE/RZ */
 #define BFP_E_NULL (-2)     /* null pointer with n > 0 */
 #define BFP_E_ALIGN (-3)    /* pointer not 16-byte aligned */
-#define BFP_E_OP (-4)       /* op not BFP_ADD/BFP_SUB/BFP_MUL */
+#define BFP_E_OP (-4)       /* op not BFP_ADD/BFP_SUB/BFP_MUL/BFP_DIV */
 #define BFP_E_HIP (-5)      /* HIP runtime error on launch */
 #define BFP_E_ARG (-6)      /* other invalid argument (size, count, handle) */
 #define BFP_E_ALIAS (-7)    /* forbidden overlap of input and output */
@@ -75,10 +75,14 @@ typedef int bfp_status;
 #define BFP_RNE 0 /* round to nearest, ties to even (Section 4) */
 #define BFP_RZ 1  /* round toward zero (Section 4) */
 
-/* Operation codes (Section 4, Table 1: Add/Sub, Mul). */
+/* Operation codes (Section 4, Table 1: Add/Sub, Mul, Div).  Division is
+ * correctly rounded in both modes: an operand pair gives the pattern that
+ * rounding the exact quotient once gives (x / 0 = signed Inf for finite
+ * nonzero x, 0 / 0 and Inf / Inf = NaN, x / Inf = signed zero). */
 #define BFP_ADD 0
 #define BFP_SUB 1
 #define BFP_MUL 2
+#define BFP_DIV 3
 
 /* A custom format: e exponent bits, m mantissa bits, rounding mode. */
 typedef struct {
@@ -123,9 +127,10 @@ bfp_status bfp_unpack(bfp_format f, const void* bs_in, void* std_out, uint64_t n
 
 /* ---- arithmetic on resident bitslice vectors (Section 4, Table 1) --------- */
 
-/* c = a op b elementwise, op in {BFP_ADD, BFP_SUB, BFP_MUL}.  a, b, c:
+/* c = a op b elementwise, op in {BFP_ADD, BFP_SUB, BFP_MUL, BFP_DIV}.  a, b, c:
  * device bitslice vectors of n elements in format f (same G_pad); all
- * G_pad words of every plane of c are written.  c may be the same buffer as
+ * G_pad words of every plane of c are written, and bits of elements at and
+ * above n are zero (as bfp_pack leaves them).  c may be the same buffer as
  * a or b (each lane reads all of its words before writing); partial
  * overlaps are not allowed. */
 bfp_status bfp_binop(int op, bfp_format f, const void* a, const void* b, void* c, uint64_t n,
@@ -133,6 +138,7 @@ bfp_status bfp_binop(int op, bfp_format f, const void* a, const void* b, void* c
 bfp_status bfp_add(bfp_format f, const void* a, const void* b, void* c, uint64_t n, void* stream);
 bfp_status bfp_sub(bfp_format f, const void* a, const void* b, void* c, uint64_t n, void* stream);
 bfp_status bfp_mul(bfp_format f, const void* a, const void* b, void* c, uint64_t n, void* stream);
+bfp_status bfp_div(bfp_format f, const void* a, const void* b, void* c, uint64_t n, void* stream);
 
 /* Fused standard-in / standard-out op: pack both operands in registers, run
  * the circuit, unpack, in one kernel with no bitslice round trip to memory.
@@ -201,7 +207,7 @@ typedef struct {
   void* c;
   uint64_t n;
   bfp_format f;
-  int32_t op; /* BFP_ADD, BFP_SUB or BFP_MUL */
+  int32_t op; /* BFP_ADD, BFP_SUB, BFP_MUL or BFP_DIV */
 } bfp_task;
 
 typedef struct bfp_batch_plan bfp_batch_plan;

@@ -20,8 +20,8 @@ TUNE_TABLE = os.path.join(_HERE, "tuning", "gfx950.txt")
 
 BFP_OK = 0
 BFP_RNE, BFP_RZ = 0, 1
-BFP_ADD, BFP_SUB, BFP_MUL = 0, 1, 2
-OPS = {"add": BFP_ADD, "sub": BFP_SUB, "mul": BFP_MUL}
+BFP_ADD, BFP_SUB, BFP_MUL, BFP_DIV = 0, 1, 2, 3
+OPS = {"add": BFP_ADD, "sub": BFP_SUB, "mul": BFP_MUL, "div": BFP_DIV}
 
 
 class bfp_format(ctypes.Structure):
@@ -91,6 +91,8 @@ _SIGS = {
     "bfp_sub": (ctypes.c_int, [bfp_format, ctypes.c_void_p, ctypes.c_void_p, ctypes.c_void_p, ctypes.c_uint64,
                                ctypes.c_void_p]),
     "bfp_mul": (ctypes.c_int, [bfp_format, ctypes.c_void_p, ctypes.c_void_p, ctypes.c_void_p, ctypes.c_uint64,
+                               ctypes.c_void_p]),
+    "bfp_div": (ctypes.c_int, [bfp_format, ctypes.c_void_p, ctypes.c_void_p, ctypes.c_void_p, ctypes.c_uint64,
                                ctypes.c_void_p]),
     "bfp_binop_std": (ctypes.c_int, [ctypes.c_int, bfp_format, ctypes.c_void_p, ctypes.c_void_p,
                                      ctypes.c_void_p, ctypes.c_uint64, ctypes.c_void_p]),
@@ -233,6 +235,10 @@ def bfp_sub(f, a, b, c, n: int, stream=None):
 
 def bfp_mul(f, a, b, c, n: int, stream=None):
     _check(lib().bfp_mul(f, _ptr(a), _ptr(b), _ptr(c), n, _stream(stream)), "bfp_mul")
+
+
+def bfp_div(f, a, b, c, n: int, stream=None):
+    _check(lib().bfp_div(f, _ptr(a), _ptr(b), _ptr(c), n, _stream(stream)), "bfp_div")
 
 
 def bfp_binop_std(op, f, a, b, c, n: int, stream=None):

@@ -10,7 +10,9 @@
 // Device: a grid sized to the GPU's resident capacity; each block takes the
 // next chunk index from an atomic counter, reads the chunk's task, and
 // switches (block-uniformly) to the compiled circuit of the task's
-// (e, m, operation class, rounding mode).  The counter is cleared by a
+// (e, m, operation class, rounding mode).  Division chunks go to a second
+// persistent kernel after the first, so that the divider's registers do not
+// lower the first kernel's occupancy.  The counters are cleared by a
 // one-thread kernel at the head of the graph, so each replay starts at chunk 0.
 #include <hip/hip_runtime.h>
 
@@ -26,8 +28,8 @@
 
 namespace bfp {
 
-// variant = ((format index) * 2 + opclass) * 2 + rz, format index in the
-// order of BFP_FOR_EACH_FORMAT
+// variant = ((format index) * kOpClasses + opclass) * 2 + rz, format index in
+// the order of BFP_FOR_EACH_FORMAT
 
 __host__ __device__ constexpr int format_index(int e, int m) {
   const int ei = e == 3 ? 0 : e == 4 ? 1 : e == 5 ? 2 : e == 6 ? 3 : e == 8 ? 4 : -1;
@@ -53,17 +55,26 @@ __device__ __forceinline__ void batch_chunk(const BatchTask& tk, uint64_t w0, ui
       y[k] = ld_words<R>(tk.b + (uint64_t)k * tk.sb + off);
     }
     circuit<E, M, RZ, OPC, R>(x, y, tk.negb, z);
+    mask_padding<OPC, R, B>(z, off, tk.n);
 #pragma unroll
     for (int k = 0; k < B; ++k) st_words<R>(tk.c + (uint64_t)k * tk.sc + off, z[k]);
   }
 }
 
+constexpr bool variant_is_div(uint32_t v) { return (v / 2) % kOpClasses == 2; }
+
 __global__ void k_batch_reset(uint32_t* counter) {
-  if (threadIdx.x == 0 && blockIdx.x == 0) *counter = 0u;
+  if (threadIdx.x == 0 && blockIdx.x == 0) {
+    counter[0] = 0u;
+    counter[1] = 0u;
+  }
 }
 
+// Persistent kernel over chunks [first, first + nchunks).  DIV selects the
+// division variants; the other kernel holds add/sub and mul.
+template <bool DIV>
 __global__ void __launch_bounds__(kBatchBlock) k_batch(const BatchTask* tasks, const BatchChunk* chunks,
-                                                       uint32_t nchunks, uint32_t* counter) {
+                                                       uint32_t first, uint32_t nchunks, uint32_t* counter) {
   __shared__ uint32_t s_next;
   for (;;) {
     if (threadIdx.x == 0) s_next = atomicAdd(counter, 1u);
@@ -71,17 +82,27 @@ __global__ void __launch_bounds__(kBatchBlock) k_batch(const BatchTask* tasks, c
     const uint32_t ci = s_next;
     __syncthreads();
     if (ci >= nchunks) break;  // every block sees the counter pass nchunks and leaves
-    const BatchChunk ch = chunks[ci];
+    const BatchChunk ch = chunks[first + ci];
     const BatchTask tk = tasks[ch.task];
-    switch (tk.variant) {
-#define BFP_BATCH_CASE(EE, MM)                                                                               \
-  case (format_index(EE, MM) * 2 + 0) * 2 + 0: batch_chunk<EE, MM, false, 0>(tk, ch.w0, ch.nwords); break; \
-  case (format_index(EE, MM) * 2 + 0) * 2 + 1: batch_chunk<EE, MM, true, 0>(tk, ch.w0, ch.nwords); break;  \
-  case (format_index(EE, MM) * 2 + 1) * 2 + 0: batch_chunk<EE, MM, false, 1>(tk, ch.w0, ch.nwords); break; \
-  case (format_index(EE, MM) * 2 + 1) * 2 + 1: batch_chunk<EE, MM, true, 1>(tk, ch.w0, ch.nwords); break;
-      BFP_FOR_EACH_FORMAT(BFP_BATCH_CASE)
+    if constexpr (DIV) {
+      switch (tk.variant) {
+#define BFP_BATCH_VARIANT(EE, MM, OPC, RZ) \
+  case (format_index(EE, MM) * kOpClasses + OPC) * 2 + RZ: batch_chunk<EE, MM, RZ, OPC>(tk, ch.w0, ch.nwords); break;
+#define BFP_BATCH_CASE(EE, MM) BFP_BATCH_VARIANT(EE, MM, 2, false) BFP_BATCH_VARIANT(EE, MM, 2, true)
+        BFP_FOR_EACH_FORMAT(BFP_BATCH_CASE)
 #undef BFP_BATCH_CASE
-      default: break;
+        default: break;
+      }
+    } else {
+      switch (tk.variant) {
+#define BFP_BATCH_CASE(EE, MM)                                                                           \
+  BFP_BATCH_VARIANT(EE, MM, 0, false) BFP_BATCH_VARIANT(EE, MM, 0, true) BFP_BATCH_VARIANT(EE, MM, 1, false) \
+  BFP_BATCH_VARIANT(EE, MM, 1, true)
+        BFP_FOR_EACH_FORMAT(BFP_BATCH_CASE)
+#undef BFP_BATCH_CASE
+#undef BFP_BATCH_VARIANT
+        default: break;
+      }
     }
   }
 }
@@ -89,7 +110,7 @@ __global__ void __launch_bounds__(kBatchBlock) k_batch(const BatchTask* tasks, c
 bool batch_task(const void* a, uint64_t na, const void* b, uint64_t nb, void* c, uint64_t n, bfp_format f, int op,
                 BatchTask* out) {
   const int fi = format_index(f.e, f.m);
-  if (fi < 0 || f.round > 1 || (op != BFP_ADD && op != BFP_SUB && op != BFP_MUL)) return false;
+  if (fi < 0 || f.round > 1 || !op_valid(op)) return false;
   if (na < n || nb < n) return false;
   out->a = static_cast<const uint32_t*>(a);
   out->b = static_cast<const uint32_t*>(b);
@@ -98,8 +119,9 @@ bool batch_task(const void* a, uint64_t na, const void* b, uint64_t nb, void* c,
   out->sb = bfp_plane_stride_words(nb);
   out->sc = bfp_plane_stride_words(n);
   out->words = out->sc;
+  out->n = n;
   out->negb = op == BFP_SUB ? 0xFFFFFFFFu : 0u;
-  out->variant = (uint32_t)((fi * 2 + (op == BFP_MUL ? 1 : 0)) * 2 + f.round);
+  out->variant = (uint32_t)((fi * kOpClasses + opclass_of(op)) * 2 + f.round);
   return true;
 }
 
@@ -115,9 +137,11 @@ void batch_chunks(const std::vector<BatchTask>& dt, std::vector<BatchChunk>* out
       chunks.push_back(ch);
     }
   }
-  // variant order; within a variant, longer tasks first, then by position
+  // division last, then variant order; within a variant, longer tasks
+  // first, then by position
   std::stable_sort(chunks.begin(), chunks.end(), [&](const BatchChunk& x, const BatchChunk& y) {
     const uint32_t vx = dt[x.task].variant, vy = dt[y.task].variant;
+    if (variant_is_div(vx) != variant_is_div(vy)) return variant_is_div(vy);
     if (vx != vy) return vx < vy;
     if (dt[x.task].words != dt[y.task].words) return dt[x.task].words > dt[y.task].words;
     if (x.task != y.task) return x.task < y.task;
@@ -125,19 +149,38 @@ void batch_chunks(const std::vector<BatchTask>& dt, std::vector<BatchChunk>* out
   });
 }
 
-int batch_resident_blocks() {
+int batch_resident_blocks(bool div) {
   int dev = 0, per_cu = 0;
   hipDeviceProp_t prop;
   if (hipGetDevice(&dev) != hipSuccess || hipGetDeviceProperties(&prop, dev) != hipSuccess) return 0;
-  if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, k_batch, kBatchBlock, 0) != hipSuccess) return 0;
+  const hipError_t e = div ? hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, k_batch<true>, kBatchBlock, 0)
+                           : hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, k_batch<false>, kBatchBlock, 0);
+  if (e != hipSuccess) return 0;
   if (per_cu < 1) per_cu = 1;
   return per_cu * prop.multiProcessorCount;
 }
 
-hipError_t batch_launch(const BatchTask* d_tasks, const BatchChunk* d_chunks, uint32_t nchunks, uint32_t* d_counter,
-                        unsigned grid, hipStream_t s) {
+BatchSplit batch_split(const std::vector<BatchTask>& tasks, const std::vector<BatchChunk>& chunks, int cap_main,
+                       int cap_div) {
+  BatchSplit sp;
+  for (const BatchChunk& ch : chunks) {
+    if (variant_is_div(tasks[ch.task].variant)) ++sp.n_div;
+    else ++sp.n_main;
+  }
+  sp.grid_main = (unsigned)std::min<uint64_t>((uint64_t)std::max(cap_main, 1), sp.n_main);
+  sp.grid_div = (unsigned)std::min<uint64_t>((uint64_t)std::max(cap_div, 1), sp.n_div);
+  return sp;
+}
+
+hipError_t batch_launch(const BatchTask* d_tasks, const BatchChunk* d_chunks, const BatchSplit& sp,
+                        uint32_t* d_counter, hipStream_t s) {
   hipLaunchKernelGGL(k_batch_reset, dim3(1), dim3(64), 0, s, d_counter);
-  hipLaunchKernelGGL(k_batch, dim3(grid), dim3(kBatchBlock), 0, s, d_tasks, d_chunks, nchunks, d_counter);
+  if (sp.n_main > 0)
+    hipLaunchKernelGGL((k_batch<false>), dim3(sp.grid_main), dim3(kBatchBlock), 0, s, d_tasks, d_chunks, 0u,
+                       sp.n_main, d_counter);
+  if (sp.n_div > 0)
+    hipLaunchKernelGGL((k_batch<true>), dim3(sp.grid_div), dim3(kBatchBlock), 0, s, d_tasks, d_chunks, sp.n_main,
+                       sp.n_div, d_counter + 1);
   return hipGetLastError();
 }
 
@@ -152,7 +195,7 @@ struct bfp_batch_plan {
   BatchChunk* d_chunks = nullptr;
   uint32_t* d_counter = nullptr;
   uint32_t nchunks = 0;
-  unsigned grid = 0;
+  BatchSplit split;
   hipStream_t capture_stream = nullptr;
   hipGraph_t graph = nullptr;
   hipGraphExec_t exec = nullptr;
@@ -187,7 +230,7 @@ bfp_status bfp_batch_plan_create(const bfp_task* tasks, uint32_t count, bfp_batc
   for (uint32_t i = 0; i < count; ++i) {
     const bfp_task& t = tasks[i];
     if (!bfp_format_supported(t.f)) return BFP_E_FORMAT;
-    if (t.op != BFP_ADD && t.op != BFP_SUB && t.op != BFP_MUL) return BFP_E_OP;
+    if (!op_valid(t.op)) return BFP_E_OP;
     if (t.n == 0 || t.n > (1ull << 36)) return BFP_E_ARG;
     if (!t.a || !t.b || !t.c) return BFP_E_NULL;
     if (((uintptr_t)t.a | (uintptr_t)t.b | (uintptr_t)t.c) & 15u) return BFP_E_ALIGN;
@@ -218,13 +261,13 @@ bfp_status bfp_batch_plan_create(const bfp_task* tasks, uint32_t count, bfp_batc
     plan_free(p);
     return BFP_E_HIP;
   }
-  // resident grid: as many blocks as fit on the device at once
-  const int resident = batch_resident_blocks();
-  if (resident <= 0) {
+  // resident grids: as many blocks as fit on the device at once
+  const int cap_main = batch_resident_blocks(false), cap_div = batch_resident_blocks(true);
+  if (cap_main <= 0 || cap_div <= 0) {
     plan_free(p);
     return BFP_E_HIP;
   }
-  p->grid = (unsigned)std::min<uint64_t>((uint64_t)resident, p->nchunks);
+  p->split = batch_split(dt, chunks, cap_main, cap_div);
   // capture reset + persistent kernel once
   if (hipStreamCreateWithFlags(&p->capture_stream, hipStreamNonBlocking) != hipSuccess) {
     plan_free(p);
@@ -232,7 +275,7 @@ bfp_status bfp_batch_plan_create(const bfp_task* tasks, uint32_t count, bfp_batc
   }
   hipError_t e = hipStreamBeginCapture(p->capture_stream, hipStreamCaptureModeThreadLocal);
   if (e == hipSuccess) {
-    const hipError_t le = batch_launch(p->d_tasks, p->d_chunks, p->nchunks, p->d_counter, p->grid, p->capture_stream);
+    const hipError_t le = batch_launch(p->d_tasks, p->d_chunks, p->split, p->d_counter, p->capture_stream);
     e = hipStreamEndCapture(p->capture_stream, &p->graph);
     if (le != hipSuccess) e = le;
   }
@@ -254,8 +297,10 @@ bfp_status bfp_batch_run(bfp_batch_plan* plan, void* stream) {
 bfp_status bfp_batch_run_eager(bfp_batch_plan* plan, void* stream) {
   if (!plan) return BFP_E_NULL;
   std::lock_guard<std::mutex> lk(plan->mu);
-  return batch_launch(plan->d_tasks, plan->d_chunks, plan->nchunks, plan->d_counter, plan->grid,
-                      (hipStream_t)stream) == hipSuccess ? BFP_OK : BFP_E_HIP;
+  return batch_launch(plan->d_tasks, plan->d_chunks, plan->split, plan->d_counter, (hipStream_t)stream) ==
+                 hipSuccess
+             ? BFP_OK
+             : BFP_E_HIP;
 }
 
 bfp_status bfp_batch_run_per_vector(bfp_batch_plan* plan, void* stream) {
@@ -271,7 +316,7 @@ bfp_status bfp_batch_plan_info(const bfp_batch_plan* plan, uint32_t* nchunks, ui
                                uint64_t* words_per_operand) {
   if (!plan) return BFP_E_NULL;
   if (nchunks) *nchunks = plan->nchunks;
-  if (grid) *grid = plan->grid;
+  if (grid) *grid = plan->split.grid_main > plan->split.grid_div ? plan->split.grid_main : plan->split.grid_div;
   if (words_per_operand) *words_per_operand = plan->words_total;
   return BFP_OK;
 }

@@ -16,6 +16,7 @@ struct BatchTask {
   uint32_t* c;
   uint64_t sa, sb, sc;  // plane strides of a, b, c in 32-bit words
   uint64_t words;       // words per plane to compute (a multiple of 64)
+  uint64_t n;           // elements of c (division masks lanes at and above n)
   uint32_t negb;
   uint32_t variant;
 };
@@ -37,14 +38,30 @@ bool batch_task(const void* a, uint64_t na, const void* b, uint64_t nb, void* c,
                 BatchTask* out);
 
 // Cut tasks into chunks of at most kChunkWords words, sorted by circuit
-// variant and, within a variant, longest task first.
+// variant and, within a variant, longest task first; chunks of the division
+// circuit come last.
 void batch_chunks(const std::vector<BatchTask>& tasks, std::vector<BatchChunk>* out);
 
-// Blocks of the persistent kernel that fit on the current device at once.
-int batch_resident_blocks();
+// Division chunks run in a persistent kernel of their own: the divider's
+// register demand would otherwise set the register allocation, and so lower
+// the occupancy, of the kernel that runs every other circuit.
+struct BatchSplit {
+  uint32_t n_main = 0;  // chunks [0, n_main): add/sub/mul kernel
+  uint32_t n_div = 0;   // chunks [n_main, n_main + n_div): division kernel
+  unsigned grid_main = 0, grid_div = 0;
+};
 
-// Enqueue counter reset + persistent kernel on `s`.
-hipError_t batch_launch(const BatchTask* d_tasks, const BatchChunk* d_chunks, uint32_t nchunks, uint32_t* d_counter,
-                        unsigned grid, hipStream_t s);
+// Blocks of the persistent kernel (division kernel if div) that fit on the
+// current device at once; 0 on error.
+int batch_resident_blocks(bool div);
+
+// Split of sorted chunks with grids capped at the resident block counts.
+BatchSplit batch_split(const std::vector<BatchTask>& tasks, const std::vector<BatchChunk>& chunks, int cap_main,
+                       int cap_div);
+
+// Enqueue the counter reset and the persistent kernels that have chunks on
+// `s`.  d_counter holds two counters.
+hipError_t batch_launch(const BatchTask* d_tasks, const BatchChunk* d_chunks, const BatchSplit& split,
+                        uint32_t* d_counter, hipStream_t s);
 
 }  // namespace bfp

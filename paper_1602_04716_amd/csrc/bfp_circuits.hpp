@@ -6,6 +6,7 @@
 // Table 1 (Section 4):
 //   add/sub: sign, alignment shift, add, normalise, round
 //   mul:     sign, exponent add, significand multiply, normalise, round
+//   div:     sign, exponent subtract, significand divide, normalise, round
 // with a logarithmic (barrel) shifter for alignment and normalisation
 // (Section 4) and gate count, not depth, as the cost to minimise, which is
 // also the cost on a SIMT machine where every lane runs every gate.
@@ -323,6 +324,177 @@ BFP_FN void fp_add(const W* a, const W* b, W negb, W* out) {
 }
 
 // ---------------------------------------------------------------------------
+// Shared by Mul and Div
+// ---------------------------------------------------------------------------
+
+// Two's complement width holding every value in [lo, hi] and also -lo (the
+// underflow shift amount).
+constexpr int exp_width(int lo, int hi) {
+  int w = 2;
+  while (!(-(1 << (w - 1)) <= lo && hi < (1 << (w - 1)) && -lo < (1 << (w - 1)))) ++w;
+  return w;
+}
+
+// x[0, N) -= y[0, NY) (y zero-extended), modulo 2^N: x + ~y + 1.
+template <int N, int NY, class W>
+BFP_FN void sub_zext(W* x, const W* y) {
+  W c = WordTraits<W>::zero();
+#pragma unroll
+  for (int i = 0; i < N; ++i) {
+    const W xi = x[i];
+    if (i == 0) {  // carry-in 1: sum = x ^ y, carry = x | ~y
+      x[0] = g_xor(xi, y[0]);
+      c = g_orn(xi, y[0]);
+    } else if (i < NY) {
+      x[i] = g3<IMM_XNOR3>(xi, y[i], c);
+      if (i + 1 < N) c = g3<IMM_MAJ_NB>(xi, y[i], c);
+    } else {  // ~y = 1 above its width: x + 1 + c
+      x[i] = g_xnor(xi, c);
+      if (i + 1 < N) c = g_or(xi, c);
+    }
+  }
+}
+
+// x[0, N) += y[0, NY) (y zero-extended), modulo 2^N.
+template <int N, int NY, class W>
+BFP_FN void add_zext(W* x, const W* y) {
+  W c = WordTraits<W>::zero();
+#pragma unroll
+  for (int i = 0; i < N; ++i) {
+    const W xi = x[i];
+    if (i == 0) {
+      x[0] = g_xor(xi, y[0]);
+      c = g_and(xi, y[0]);
+    } else if (i < NY) {
+      x[i] = g_xor3(xi, y[i], c);
+      if (i + 1 < N) c = g_maj(xi, y[i], c);
+    } else {
+      x[i] = g_xor(xi, c);
+      if (i + 1 < N) c = g_and(xi, c);
+    }
+  }
+}
+
+// x[0, N) += K (a constant), modulo 2^N: a constant addend folds to at most
+// one gate per bit for the sum and one for the carry.
+template <int N, class W>
+BFP_FN void add_const(W* x, unsigned K) {
+  W c = WordTraits<W>::zero();
+  bool c_is_zero = true;
+#pragma unroll
+  for (int i = 0; i < N; ++i) {
+    const bool k = (K >> i) & 1u;
+    const W xi = x[i];
+    if (c_is_zero) {
+      if (k) {  // x + 1, carry-in 0
+        x[i] = g_not(xi);
+        c = xi;
+        c_is_zero = false;
+      }
+    } else if (k) {  // x + 1 + c: sum = ~(x ^ c), carry = x | c
+      x[i] = g_xnor(xi, c);
+      c = g_or(xi, c);
+    } else {         // x + 0 + c
+      x[i] = g_xor(xi, c);
+      c = g_and(xi, c);
+    }
+  }
+}
+
+// Pre-normalise the P = M + 1 bit significand of x (hidden bit hid): shift it
+// left by its leading-zero count, found greedily by descending powers of two;
+// lz[0, LP) receives the count.  A normal significand is left unchanged.
+template <int M, int LP, class W>
+BFP_FN void prenormalise(const W* x, W hid, W* S, W* lz) {
+  constexpr int P = M + 1;
+#pragma unroll
+  for (int k = 0; k < M; ++k) S[k] = x[k];
+  S[M] = hid;
+#pragma unroll
+  for (int j = LP - 1; j >= 0; --j) {
+    const int sh = 1 << j;
+    W z = S[P - 1];
+#pragma unroll
+    for (int i = P - 2; i >= P - sh; --i) z = g_or(z, S[i]);
+    z = g_not(z);
+#pragma unroll
+    for (int i = P - 1; i >= sh; --i) S[i] = g_mux(z, S[i - sh], S[i]);
+#pragma unroll
+    for (int i = 0; i < sh; ++i) S[i] = g_andn(S[i], z);
+    lz[j] = z;
+  }
+}
+
+// Normalised significand v[0, M + 3) (0 sticky, 1 guard, 2 .. M+2 the
+// significand, hidden bit on top) and D = E_f - 1 in EW two's complement bits
+// -> rounded result.  Underflow (E_f <= 0, i.e. D < 0) shifts right by -D with
+// sticky and gives exponent field 0; overflow is E_f >= 2^e - 1.  Then the
+// special results: sp forces the all-ones exponent (Inf, or NaN when nan_o),
+// zero_o a signed zero.
+template <int E, int M, bool RZ, int EW, class W>
+BFP_FN void finish_muldiv(W* v, W* D, W s, W nan_o, W sp, W zero_o, W* out) {
+  constexpr int F = E + M, P = M + 1, NV = P + 2;
+  const W zero = WordTraits<W>::zero();
+  const W neg = D[EW - 1];
+  W sh[EW];
+  {
+    // -D = ~D + 1, masked to zero unless D < 0
+#pragma unroll
+    for (int i = 0; i < EW; ++i) sh[i] = g_not(D[i]);
+    increment<EW>(sh, WordTraits<W>::ones());
+#pragma unroll
+    for (int i = 0; i < EW; ++i) sh[i] = g_and(sh[i], neg);
+  }
+  shift_right_sticky<NV, EW - 1>(v, sh);
+  W ovf;
+  {
+    W hi_bits = (EW - 1 > E) ? or_range<E, cmax(EW - 1, E + 1)>(D) : zero;
+    W top = (E >= 2) ? and_range<1, cmax(E, 2)>(D) : D[0];
+    ovf = g3<imm8((TA | TB) & ~TC)>(hi_bits, top, neg);
+  }
+
+  // step 5 (round): X = (D + hidden) << m | mantissa, then + round-up; the
+  // hidden bit carries D + 1 = E_f into the field for normal results, and D
+  // is masked to 0 for subnormal ones
+  W x[F];
+#pragma unroll
+  for (int k = 0; k < M; ++k) x[k] = v[2 + k];
+#pragma unroll
+  for (int i = 0; i < E; ++i) x[M + i] = g_andn(D[i], neg);
+  {
+    W c = v[P + 1];  // hidden bit
+#pragma unroll
+    for (int i = 0; i < E; ++i) {
+      W t = g_xor(x[M + i], c);
+      if (i + 1 < E) c = g_and(x[M + i], c);
+      x[M + i] = t;
+    }
+  }
+  if constexpr (!RZ) {
+    const W up = g3<IMM_AND_OR>(v[1], v[2], v[0]);  // g & (lsb | s)
+    increment<F>(x, up);
+#pragma unroll
+    for (int i = 0; i < E; ++i) x[M + i] = g_or(x[M + i], ovf);
+#pragma unroll
+    for (int k = 0; k < M; ++k) x[k] = g_andn(x[k], ovf);
+  } else {
+#pragma unroll
+    for (int i = 1; i < E; ++i) x[M + i] = g_or(x[M + i], ovf);
+    x[M] = g_andn(x[M], ovf);
+#pragma unroll
+    for (int k = 0; k < M; ++k) x[k] = g_or(x[k], ovf);
+  }
+
+  // zero operands, then specials
+  out[F] = g_andn(s, nan_o);
+#pragma unroll
+  for (int i = 0; i < E; ++i) out[M + i] = g3<IMM_ANDN_OR>(x[M + i], zero_o, sp);
+#pragma unroll
+  for (int k = 0; k < M - 1; ++k) out[k] = g3<imm8(TA & ~(TB | TC))>(x[k], zero_o, sp);
+  out[M - 1] = g3<imm8((TA & ~TB) | TC)>(g_andn(x[M - 1], zero_o), sp, nan_o);
+}
+
+// ---------------------------------------------------------------------------
 // Table 1, Mul.
 // ---------------------------------------------------------------------------
 template <int E, int M>
@@ -334,14 +506,7 @@ struct MulWidths {
   // [2 - 2(P-1) - bias - 1, 2(2^E - 2) - bias]
   static constexpr int LO = 2 - 2 * (P - 1) - BIAS - 1;
   static constexpr int HI = 2 * ((1 << E) - 2) - BIAS;
-  // two's complement width holding every value in [lo, hi] and also -lo
-  // (the underflow shift amount)
-  static constexpr int need(int lo, int hi) {
-    int w = 2;
-    while (!(-(1 << (w - 1)) <= lo && hi < (1 << (w - 1)) && -lo < (1 << (w - 1)))) ++w;
-    return w;
-  }
-  static constexpr int EW = cmax(need(LO, HI), E + 2);  // signed width of the exponent datapath
+  static constexpr int EW = cmax(exp_width(LO, HI), E + 2);  // signed width of the exponent datapath
 };
 
 template <int E, int M, bool RZ, class W>
@@ -365,40 +530,10 @@ BFP_FN void fp_mul(const W* a, const W* b, W* out) {
   const W sp = g_or(emax_a, emax_b);
   const W zero_o = g_not(g_and(nz_a, nz_b));
 
-  // pre-normalise subnormal significands: shift left by the leading-zero
-  // count, found greedily by descending powers of two
+  // pre-normalise subnormal significands
   W A[P], Bs[P], lza[LP], lzb[LP];
-#pragma unroll
-  for (int k = 0; k < M; ++k) {
-    A[k] = a[k];
-    Bs[k] = b[k];
-  }
-  A[M] = hid_a;
-  Bs[M] = hid_b;
-#pragma unroll
-  for (int j = LP - 1; j >= 0; --j) {
-    const int sh = 1 << j;
-    W za = A[P - 1], zb = Bs[P - 1];
-#pragma unroll
-    for (int i = P - 2; i >= P - sh; --i) {
-      za = g_or(za, A[i]);
-      zb = g_or(zb, Bs[i]);
-    }
-    za = g_not(za);
-    zb = g_not(zb);
-#pragma unroll
-    for (int i = P - 1; i >= sh; --i) {
-      A[i] = g_mux(za, A[i - sh], A[i]);
-      Bs[i] = g_mux(zb, Bs[i - sh], Bs[i]);
-    }
-#pragma unroll
-    for (int i = 0; i < sh; ++i) {
-      A[i] = g_andn(A[i], za);
-      Bs[i] = g_andn(Bs[i], zb);
-    }
-    lza[j] = za;
-    lzb[j] = zb;
-  }
+  prenormalise<M, LP>(a, hid_a, A, lza);
+  prenormalise<M, LP>(b, hid_b, Bs, lzb);
 
   // step 2 (exponent add), merged into one datapath of EW signed bits:
   // D = E'a + E'b + (-bias - 1) - (lza + lzb), and + cout after the multiply
@@ -425,32 +560,8 @@ BFP_FN void fp_mul(const W* a, const W* b, W* out) {
       }
       D[E] = c;
     }
-    // + K, K = (-bias - 1) mod 2^EW: a constant addend folds to one gate per bit
-    {
-      constexpr unsigned K = (unsigned)(-(MW::BIAS + 1)) & ((1u << EW) - 1u);
-      W c = zero;
-      bool c_is_zero = true;
-#pragma unroll
-      for (int i = 0; i < EW; ++i) {
-        const bool k = (K >> i) & 1u;
-        if (c_is_zero) {
-          if (k) {  // x + 1, carry-in 0
-            const W x = D[i];
-            D[i] = g_not(x);
-            c = x;
-            c_is_zero = false;
-          }
-        } else if (k) {  // x + 1 + c: sum = ~(x ^ c), carry = x | c
-          const W x = D[i];
-          D[i] = g_xnor(x, c);
-          c = g_or(x, c);
-        } else {         // x + 0 + c
-          const W x = D[i];
-          D[i] = g_xor(x, c);
-          c = g_and(x, c);
-        }
-      }
-    }
+    // + (-bias - 1) mod 2^EW
+    add_const<EW>(D, (unsigned)(-(MW::BIAS + 1)) & ((1u << EW) - 1u));
     // - (lza + lzb) = + ~(lza + lzb) + 1
     W lz[LP + 1];
     if constexpr (LP == 1) {
@@ -528,66 +639,129 @@ BFP_FN void fp_mul(const W* a, const W* b, W* out) {
 #pragma unroll
   for (int i = 2; i < NV; ++i) v[i] = g_mux(cout, acc[i - 1], acc[i - 2]);
   increment<EW>(D, cout);  // D = E_f - 1
+  finish_muldiv<E, M, RZ, EW, W>(v, D, s, nan_o, sp, zero_o, out);
+}
 
-  // underflow (E_f <= 0, i.e. D < 0): shift right by -D with sticky, exponent
-  // field 0.  Overflow: E_f >= 2^e - 1.
-  const W neg = D[EW - 1];
-  W sh[EW];
-  {
-    // -D = ~D + 1, masked to zero unless D < 0
-#pragma unroll
-    for (int i = 0; i < EW; ++i) sh[i] = g_not(D[i]);
-    increment<EW>(sh, WordTraits<W>::ones());
-#pragma unroll
-    for (int i = 0; i < EW; ++i) sh[i] = g_and(sh[i], neg);
-  }
-  shift_right_sticky<NV, EW - 1>(v, sh);
-  W ovf;
-  {
-    W hi_bits = (EW - 1 > E) ? or_range<E, cmax(EW - 1, E + 1)>(D) : zero;
-    W top = (E >= 2) ? and_range<1, cmax(E, 2)>(D) : D[0];
-    ovf = g3<imm8((TA | TB) & ~TC)>(hi_bits, top, neg);
-  }
+// ---------------------------------------------------------------------------
+// Table 1, Div.
+// ---------------------------------------------------------------------------
+template <int E, int M>
+struct DivWidths {
+  static constexpr int P = M + 1;
+  static constexpr int LP = ceil_log2(P);
+  static constexpr int BIAS = (1 << (E - 1)) - 1;
+  // E_f - 1 = E'a - lza - E'b + lzb + bias - 2 + q0 spans
+  // [2 - 2^E - P + bias, 2^E + P + bias - 5]
+  static constexpr int LO = 2 - (1 << E) - P + BIAS;
+  static constexpr int HI = (1 << E) + P + BIAS - 5;
+  static constexpr int EW = cmax(exp_width(LO, HI), E + 2);
+};
 
-  // step 5 (round): X = (D + hidden) << m | mantissa, then + round-up; the
-  // hidden bit carries D + 1 = E_f into the field for normal results, and D
-  // is masked to 0 for subnormal ones
-  W x[F];
-#pragma unroll
-  for (int k = 0; k < M; ++k) x[k] = v[2 + k];
-#pragma unroll
-  for (int i = 0; i < E; ++i) x[M + i] = g_andn(D[i], neg);
+// c = a / b.  After pre-normalisation both significands A', B' lie in
+// [2^(P-1), 2^P), so the quotient A'/B' lies in (1/2, 2).  Restoring division
+// produces its bits q_0, q_-1, ..., q_-(P+1), one per step (compare the
+// doubled partial remainder with B', subtract when not below), and the final
+// remainder's OR is the sticky bit; a quotient below 1 (q_0 = 0) shifts left
+// by one and lowers the exponent.
+template <int E, int M, bool RZ, class W>
+BFP_FN void fp_div(const W* a, const W* b, W* out) {
+  using DW = DivWidths<E, M>;
+  constexpr int F = E + M, P = DW::P, LP = DW::LP, EW = DW::EW;
+  constexpr int NV = P + 2;  // 0 sticky, 1 guard, 2.. significand
+  const W zero = WordTraits<W>::zero();
+
+  // step 1 (sign)
+  const W s = g_xor(a[F], b[F]);
+
+  // classification and special results
+  const W hid_a = or_range<M, F>(a), hid_b = or_range<M, F>(b);
+  const W emax_a = and_range<M, F>(a), emax_b = and_range<M, F>(b);
+  const W mnz_a = or_range<0, M>(a), mnz_b = or_range<0, M>(b);
+  const W nz_a = g_or(hid_a, mnz_a), nz_b = g_or(hid_b, mnz_b);
+  const W inf_a = g_andn(emax_a, mnz_a), inf_b = g_andn(emax_b, mnz_b);
+  // NaN: a NaN operand, 0/0 or Inf/Inf
+  const W nan_o = g_or(g_or3(g_and(emax_a, mnz_a), g_and(emax_b, mnz_b), g_and(inf_a, inf_b)),
+                       g3<imm8(~(TA | TB))>(nz_a, nz_b, nz_b));
+  // Inf: Inf / finite, or nonzero / 0; zero: 0 / nonzero, or finite / Inf
+  const W inf_o = g3<imm8((TA | ~TB) & ~TC)>(inf_a, nz_b, nan_o);
+  const W zero_o = g3<imm8((~TA | TB) & ~TC)>(nz_a, inf_b, nan_o);
+  const W sp = g_or(nan_o, inf_o);
+
+  // pre-normalise subnormal significands
+  W A[P], Bs[P], lza[LP], lzb[LP];
+  prenormalise<M, LP>(a, hid_a, A, lza);
+  prenormalise<M, LP>(b, hid_b, Bs, lzb);
+
+  // step 2 (exponent subtract): D = E'a - E'b + lzb - lza + bias - 2, then + q_0
+  W D[EW];
   {
-    W c = v[P + 1];  // hidden bit
+    W eb[E];
+    D[0] = g_orn(a[M], hid_a);  // E' = max(E, 1)
+    eb[0] = g_orn(b[M], hid_b);
 #pragma unroll
-    for (int i = 0; i < E; ++i) {
-      W t = g_xor(x[M + i], c);
-      if (i + 1 < E) c = g_and(x[M + i], c);
-      x[M + i] = t;
+    for (int i = 1; i < E; ++i) {
+      D[i] = a[M + i];
+      eb[i] = b[M + i];
     }
-  }
-  if constexpr (!RZ) {
-    const W up = g3<IMM_AND_OR>(v[1], v[2], v[0]);  // g & (lsb | s)
-    increment<F>(x, up);
 #pragma unroll
-    for (int i = 0; i < E; ++i) x[M + i] = g_or(x[M + i], ovf);
-#pragma unroll
-    for (int k = 0; k < M; ++k) x[k] = g_andn(x[k], ovf);
-  } else {
-#pragma unroll
-    for (int i = 1; i < E; ++i) x[M + i] = g_or(x[M + i], ovf);
-    x[M] = g_andn(x[M], ovf);
-#pragma unroll
-    for (int k = 0; k < M; ++k) x[k] = g_or(x[k], ovf);
+    for (int i = E; i < EW; ++i) D[i] = zero;
+    sub_zext<EW, E>(D, eb);
+    add_zext<EW, LP>(D, lzb);
+    sub_zext<EW, LP>(D, lza);
+    add_const<EW>(D, (unsigned)(DW::BIAS - 2) & ((1u << EW) - 1u));
   }
 
-  // zero operands, then specials
-  out[F] = g_andn(s, nan_o);
+  // step 3 (significand divide).  Q[t] is quotient bit q_-t.  R holds the
+  // partial remainder, always below B' < 2^P.
+  W Q[P + 2], R[P];
+  W nq0;  // ~q_0
+  {
+    // q_0: A' - B'; the borrow out is A' < B'
+    W d[P];
+    W bw = g_andn(Bs[0], A[0]);
+    d[0] = g_xor(A[0], Bs[0]);
 #pragma unroll
-  for (int i = 0; i < E; ++i) out[M + i] = g3<IMM_ANDN_OR>(x[M + i], zero_o, sp);
+    for (int i = 1; i < P; ++i) {
+      d[i] = g_xor3(A[i], Bs[i], bw);
+      bw = g3<IMM_MAJ_NA>(A[i], Bs[i], bw);
+    }
+    nq0 = bw;
+    Q[0] = g_not(bw);
 #pragma unroll
-  for (int k = 0; k < M - 1; ++k) out[k] = g3<imm8(TA & ~(TB | TC))>(x[k], zero_o, sp);
-  out[M - 1] = g3<imm8((TA & ~TB) | TC)>(g_andn(x[M - 1], zero_o), sp, nan_o);
+    for (int i = 0; i < P; ++i) R[i] = g_mux(bw, A[i], d[i]);
+  }
+#pragma unroll
+  for (int t = 1; t <= P + 1; ++t) {
+    // 2R (P + 1 bits, low bit 0) - B': bit 0 of the difference is B'[0] with
+    // borrow B'[0]; the top bit of 2R is R[P-1] against a zero bit of B'
+    W d[P];
+    W bw = Bs[0];
+    d[0] = Bs[0];
+#pragma unroll
+    for (int i = 1; i < P; ++i) {
+      d[i] = g_xor3(R[i - 1], Bs[i], bw);
+      bw = g3<IMM_MAJ_NA>(R[i - 1], Bs[i], bw);
+    }
+    const W q = g_orn(R[P - 1], bw);  // 2R >= B'
+    Q[t] = q;
+    W Rn[P];
+    Rn[0] = g_and(q, d[0]);
+#pragma unroll
+    for (int i = 1; i < P; ++i) Rn[i] = g_mux(q, d[i], R[i - 1]);
+#pragma unroll
+    for (int i = 0; i < P; ++i) R[i] = Rn[i];
+  }
+  const W rem = or_range<0, P>(R);
+
+  // step 4 (normalise): q_0 = 1 keeps q_0 .. q_-(P-1), guard q_-P and sticky
+  // q_-(P+1) | rem; q_0 = 0 takes q_-1 .. q_-P, guard q_-(P+1), sticky rem
+  W v[NV];
+  v[0] = g3<imm8(TA | (~TB & TC))>(rem, nq0, Q[P + 1]);
+#pragma unroll
+  for (int i = 1; i < NV; ++i) v[i] = g_mux(nq0, Q[P + 2 - i], Q[P + 1 - i]);
+  increment<EW>(D, Q[0]);  // D = E_f - 1
+
+  finish_muldiv<E, M, RZ, EW, W>(v, D, s, nan_o, sp, zero_o, out);
 }
 
 }  // namespace bfp

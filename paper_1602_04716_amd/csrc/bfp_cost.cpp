@@ -14,6 +14,8 @@ long count(int op) {
   CountW::counter() = 0;
   if (op == BFP_MUL)
     bfp::fp_mul<E, M, RZ, CountW>(x, y, z);
+  else if (op == BFP_DIV)
+    bfp::fp_div<E, M, RZ, CountW>(x, y, z);
   else
     bfp::fp_add<E, M, RZ, CountW>(x, y, CountW{}, z);
   return (long)CountW::counter();
@@ -21,7 +23,7 @@ long count(int op) {
 }  // namespace
 
 extern "C" long bfp_gate_count(int op, bfp_format f) {
-  if (op != BFP_ADD && op != BFP_SUB && op != BFP_MUL) return -1;
+  if (op < BFP_ADD || op > BFP_DIV) return -1;
   if (f.round > 1 || f.pad != 0) return -1;
 #define BFP_COUNT_CASE(EE, MM) \
   if (f.e == EE && f.m == MM) return f.round ? count<EE, MM, true>(op) : count<EE, MM, false>(op);

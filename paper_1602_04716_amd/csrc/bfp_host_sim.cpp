@@ -32,6 +32,8 @@ void run(int op, const uint32_t* a, const uint32_t* b, uint32_t* c, uint64_t n) 
     }
     if (op == 2)
       bfp::fp_mul<E, M, RZ, W>(x, y, z);
+    else if (op == 3)
+      bfp::fp_div<E, M, RZ, W>(x, y, z);
     else
       bfp::fp_add<E, M, RZ, W>(x, y, negb, z);
     for (int j = 0; j < WB && base + j < n; ++j) {
@@ -50,6 +52,8 @@ unsigned long gates(int op) {
   CountW::counter() = 0;
   if (op == 2)
     bfp::fp_mul<E, M, RZ, CountW>(x, y, z);
+  else if (op == 3)
+    bfp::fp_div<E, M, RZ, CountW>(x, y, z);
   else
     bfp::fp_add<E, M, RZ, CountW>(x, y, CountW{}, z);
   return CountW::counter();
@@ -59,7 +63,7 @@ unsigned long gates(int op) {
 
 extern "C" {
 
-// op: 0 add, 1 sub, 2 mul; mode: 0 nearest-even, 1 toward zero; wbits 32/64.
+// op: 0 add, 1 sub, 2 mul, 3 div; mode: 0 nearest-even, 1 toward zero; wbits 32/64.
 // Returns 0, or -1 for a format that is not compiled.
 int bfpsim_binop(int op, int e, int m, int mode, int wbits, const uint32_t* a, const uint32_t* b,
                  uint32_t* c, uint64_t n) {

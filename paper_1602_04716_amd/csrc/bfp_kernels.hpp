@@ -17,6 +17,7 @@
 #include <hip/hip_runtime.h>
 
 #include "bfp_circuits.hpp"
+#include "bfp_ops.hpp"
 #include "bfp_transpose.hpp"
 
 namespace bfp {
@@ -63,8 +64,7 @@ __device__ __forceinline__ void st_words(uint32_t* p, const WordR<R>& v) {
   }
 }
 
-// One circuit instance on R words per plane.  OPC 0: add/sub (negb all ones
-// subtracts), 1: mul.
+// One circuit instance on R words per plane.
 template <int E, int M, bool RZ, int OPC, int R>
 __device__ __forceinline__ void circuit(const WordR<R>* x, const WordR<R>* y, uint32_t negb, WordR<R>* z) {
   if constexpr (OPC == 0) {
@@ -72,15 +72,45 @@ __device__ __forceinline__ void circuit(const WordR<R>* x, const WordR<R>* y, ui
 #pragma unroll
     for (int i = 0; i < R; ++i) nb.w[i] = negb;
     fp_add<E, M, RZ, WordR<R>>(x, y, nb, z);
-  } else {
+  } else if constexpr (OPC == 1) {
     fp_mul<E, M, RZ, WordR<R>>(x, y, z);
+  } else {
+    fp_div<E, M, RZ, WordR<R>>(x, y, z);
   }
 }
 
-// c = a op b on resident bitslice vectors: every word of every plane.
+// Lane mask of R words starting at word `off` of a vector of n elements:
+// set for elements below n.  Division maps the zero padding to 0/0 = NaN, so
+// its outputs are masked to keep the padding of c zero; the other circuits
+// map zero operands to +0 and need no mask.
+template <int R>
+__device__ __forceinline__ void valid_mask(uint64_t off, uint64_t n, uint32_t* mask) {
+  const uint64_t full = n >> 5;
+  const uint32_t part = (uint32_t)(n & 31u);
+#pragma unroll
+  for (int r = 0; r < R; ++r) {
+    const uint64_t w = off + r;
+    mask[r] = w < full ? 0xFFFFFFFFu : (w == full ? (1u << part) - 1u : 0u);
+  }
+}
+
+template <int OPC, int R, int B>
+__device__ __forceinline__ void mask_padding(WordR<R>* z, uint64_t off, uint64_t n) {
+  if constexpr (OPC == 2) {
+    uint32_t mk[R];
+    valid_mask<R>(off, n, mk);
+#pragma unroll
+    for (int k = 0; k < B; ++k)
+#pragma unroll
+      for (int r = 0; r < R; ++r) z[k].w[r] &= mk[r];
+  }
+}
+
+// c = a op b on resident bitslice vectors of n elements: every word of every
+// plane (padding words of c are zero).
 template <int E, int M, bool RZ, int OPC, int R>
 __global__ void __launch_bounds__(512) k_binop(const uint32_t* a, const uint32_t* b, uint32_t* c,
-                                               uint64_t gpad, uint32_t negb) {
+                                               uint64_t gpad, uint64_t n, uint32_t negb) {
   constexpr int B = 1 + E + M;
   const uint64_t nt = gpad / R;
   const uint64_t stride = (uint64_t)gridDim.x * blockDim.x;
@@ -93,6 +123,7 @@ __global__ void __launch_bounds__(512) k_binop(const uint32_t* a, const uint32_t
       y[k] = ld_words<R>(b + (uint64_t)k * gpad + off);
     }
     circuit<E, M, RZ, OPC, R>(x, y, negb, z);
+    mask_padding<OPC, R, B>(z, off, n);
 #pragma unroll
     for (int k = 0; k < B; ++k) st_words<R>(c + (uint64_t)k * gpad + off, z[k]);
   }
@@ -317,7 +348,7 @@ __global__ void __launch_bounds__(512) k_binop_std(const uint8_t* a, const uint8
 // ---------------------------------------------------------------------------
 // Launchers and the registry of compiled variants
 // ---------------------------------------------------------------------------
-using BinopLauncher = hipError_t (*)(const void* a, const void* b, void* c, uint64_t gpad, uint32_t negb,
+using BinopLauncher = hipError_t (*)(const void* a, const void* b, void* c, uint64_t gpad, uint64_t n, uint32_t negb,
                                      unsigned grid, unsigned block, hipStream_t s);
 using StdLauncher = hipError_t (*)(const void* a, const void* b, void* c, uint64_t n, uint32_t negb,
                                    unsigned grid, unsigned block, hipStream_t s);
@@ -326,17 +357,17 @@ constexpr int kMaxWordsPerLane = 2;  // R in {1, 2}
 
 struct Registry {
   // [e][m][opclass][rz][R-1]
-  BinopLauncher binop[9][24][2][2][kMaxWordsPerLane] = {};
-  StdLauncher std_op[9][24][2][2] = {};
+  BinopLauncher binop[9][24][kOpClasses][2][kMaxWordsPerLane] = {};
+  StdLauncher std_op[9][24][kOpClasses][2] = {};
 };
 Registry& registry();
 
 template <int E, int M, bool RZ, int OPC, int R>
-hipError_t launch_binop(const void* a, const void* b, void* c, uint64_t gpad, uint32_t negb, unsigned grid,
+hipError_t launch_binop(const void* a, const void* b, void* c, uint64_t gpad, uint64_t n, uint32_t negb, unsigned grid,
                         unsigned block, hipStream_t s) {
   hipLaunchKernelGGL((k_binop<E, M, RZ, OPC, R>), dim3(grid), dim3(block), 0, s,
                      static_cast<const uint32_t*>(a), static_cast<const uint32_t*>(b),
-                     static_cast<uint32_t*>(c), gpad, negb);
+                     static_cast<uint32_t*>(c), gpad, n, negb);
   return hipGetLastError();
 }
 
@@ -364,6 +395,12 @@ void register_format() {
   r.std_op[E][M][0][1] = launch_binop_std<E, M, true, 0>;
   r.std_op[E][M][1][0] = launch_binop_std<E, M, false, 1>;
   r.std_op[E][M][1][1] = launch_binop_std<E, M, true, 1>;
+  r.binop[E][M][2][0][0] = launch_binop<E, M, false, 2, 1>;
+  r.binop[E][M][2][1][0] = launch_binop<E, M, true, 2, 1>;
+  r.binop[E][M][2][0][1] = launch_binop<E, M, false, 2, 2>;
+  r.binop[E][M][2][1][1] = launch_binop<E, M, true, 2, 2>;
+  r.std_op[E][M][2][0] = launch_binop_std<E, M, false, 2>;
+  r.std_op[E][M][2][1] = launch_binop_std<E, M, true, 2>;
 }
 
 }  // namespace bfp

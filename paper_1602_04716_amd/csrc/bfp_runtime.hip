@@ -70,7 +70,7 @@ unsigned grid_for(uint64_t items, int block, int blocks_per_cu) {
 
 // Launch configuration table: [opclass][e][m][round]
 std::mutex g_cfg_mu;
-bfp_launch g_cfg[2][9][24][2];
+bfp_launch g_cfg[kOpClasses][9][24][2];
 bool g_cfg_init = false;
 
 // Defaults before tuning (measured on MI355X at 2^26 elements): circuits
@@ -79,13 +79,13 @@ bool g_cfg_init = false;
 // blocks of 128; circuits with many gates per bit (VALU-bound) with 32.
 void cfg_init_locked() {
   if (g_cfg_init) return;
-  for (int o = 0; o < 2; ++o)
+  for (int o = 0; o < kOpClasses; ++o)
     for (int e = 0; e < 9; ++e)
       for (int m = 0; m < 24; ++m)
         for (int r = 0; r < 2; ++r) {
           bfp_launch& c = g_cfg[o][e][m][r];
           const int B = 1 + e + m;
-          const bool valu_heavy = o == 1 && m >= 15;
+          const bool valu_heavy = (o == 1 && m >= 15) || (o == 2 && m >= 10);
           c.words_per_lane = (B <= 8 || valu_heavy) ? 1 : 2;
           c.block = B <= 8 ? 128 : 256;
           c.blocks_per_cu = 0;
@@ -129,7 +129,7 @@ hipError_t launch_unpack(const void* src, void* dst, uint64_t n, uint64_t gpad, 
   return hipGetLastError();
 }
 
-bfp_status check_op(int op) { return (op == BFP_ADD || op == BFP_SUB || op == BFP_MUL) ? BFP_OK : BFP_E_OP; }
+bfp_status check_op(int op) { return op_valid(op) ? BFP_OK : BFP_E_OP; }
 
 }  // namespace
 }  // namespace bfp
@@ -210,13 +210,13 @@ bfp_status bfp_binop(int op, bfp_format f, const void* a, const void* b, void* c
   const uint64_t gpad = gpad_of(n);
   const size_t bytes = (size_t)bits_of(f) * gpad * 4;
   if ((c != a && overlap(c, bytes, a, bytes)) || (c != b && overlap(c, bytes, b, bytes))) return BFP_E_ALIAS;
-  const int opc = op == BFP_MUL ? 1 : 0;
+  const int opc = opclass_of(op);
   const bfp_launch cfg = cfg_get(opc, f);
   BinopLauncher L = registry().binop[f.e][f.m][opc][f.round][cfg.words_per_lane - 1];
   if (!L) return BFP_E_FORMAT;
   const unsigned grid = grid_for(gpad / cfg.words_per_lane, cfg.block, cfg.blocks_per_cu);
   const uint32_t negb = op == BFP_SUB ? 0xFFFFFFFFu : 0u;
-  return hip_status(L(a, b, c, gpad, negb, grid, (unsigned)cfg.block, (hipStream_t)stream));
+  return hip_status(L(a, b, c, gpad, n, negb, grid, (unsigned)cfg.block, (hipStream_t)stream));
 }
 
 bfp_status bfp_add(bfp_format f, const void* a, const void* b, void* c, uint64_t n, void* stream) {
@@ -227,6 +227,9 @@ bfp_status bfp_sub(bfp_format f, const void* a, const void* b, void* c, uint64_t
 }
 bfp_status bfp_mul(bfp_format f, const void* a, const void* b, void* c, uint64_t n, void* stream) {
   return bfp_binop(BFP_MUL, f, a, b, c, n, stream);
+}
+bfp_status bfp_div(bfp_format f, const void* a, const void* b, void* c, uint64_t n, void* stream) {
+  return bfp_binop(BFP_DIV, f, a, b, c, n, stream);
 }
 
 bfp_status bfp_binop_std(int op, bfp_format f, const void* a, const void* b, void* c, uint64_t n,
@@ -240,8 +243,7 @@ bfp_status bfp_binop_std(int op, bfp_format f, const void* a, const void* b, voi
   if (!aligned16(a) || !aligned16(b) || !aligned16(c)) return BFP_E_ALIGN;
   const size_t bytes = (size_t)n * cbytes_of(f);
   if ((c != a && overlap(c, bytes, a, bytes)) || (c != b && overlap(c, bytes, b, bytes))) return BFP_E_ALIAS;
-  const int opc = op == BFP_MUL ? 1 : 0;
-  StdLauncher L = registry().std_op[f.e][f.m][opc][f.round];
+  StdLauncher L = registry().std_op[f.e][f.m][opclass_of(op)][f.round];
   if (!L) return BFP_E_FORMAT;
   const int block = 256;
   const unsigned grid = grid_for((n + 31) / 32, block, 0);
@@ -254,7 +256,7 @@ bfp_status bfp_launch_get(int op, bfp_format f, bfp_launch* out) {
   if (st != BFP_OK) return st;
   if (!format_ok(f)) return BFP_E_FORMAT;
   if (!out) return BFP_E_NULL;
-  *out = cfg_get(op == BFP_MUL ? 1 : 0, f);
+  *out = cfg_get(opclass_of(op), f);
   return BFP_OK;
 }
 
@@ -266,7 +268,7 @@ bfp_status bfp_launch_set(int op, bfp_format f, const bfp_launch* cfg) {
   if (!cfg_valid(*cfg)) return BFP_E_ARG;
   std::lock_guard<std::mutex> lk(g_cfg_mu);
   cfg_init_locked();
-  g_cfg[op == BFP_MUL ? 1 : 0][f.e][f.m][f.round] = *cfg;
+  g_cfg[opclass_of(op)][f.e][f.m][f.round] = *cfg;
   return BFP_OK;
 }
 
@@ -312,13 +314,14 @@ bfp_status bfp_launch_save(const char* path) {
   {
     std::lock_guard<std::mutex> lk(g_cfg_mu);
     cfg_init_locked();
-    for (int o = 0; o < 2; ++o)
+    for (int o = 0; o < kOpClasses; ++o)
       for (int e = 0; e < 9; ++e)
         for (int m = 0; m < 24; ++m)
           for (int r = 0; r < 2; ++r) {
             if (!registry().binop[e][m][0][0][0]) continue;
             const bfp_launch& c = g_cfg[o][e][m][r];
-            fprintf(fp, "%d %d %d %d %d %d %d\n", o == 1 ? BFP_MUL : BFP_ADD, e, m, r, c.words_per_lane, c.block,
+            const int op = o == 1 ? BFP_MUL : (o == 2 ? BFP_DIV : BFP_ADD);
+            fprintf(fp, "%d %d %d %d %d %d %d\n", op, e, m, r, c.words_per_lane, c.block,
                     c.blocks_per_cu);
           }
   }

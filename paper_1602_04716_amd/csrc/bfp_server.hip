@@ -21,6 +21,7 @@
 
 #include "bfp.h"
 #include "bfp_batch.hpp"
+#include "bfp_ops.hpp"
 #include "bfp_sched.hpp"
 
 namespace bfp {
@@ -42,7 +43,7 @@ struct HipExecutor {
     std::vector<SchedRequest> reqs;
   };
   uint8_t* base = nullptr;  // arena base (device)
-  int grid_cap = 0;
+  int cap_main = 0, cap_div = 0;  // resident blocks of the two persistent kernels
   Slot slot[kStreams];
   uint64_t seq = 0;
   std::vector<BatchTask> tasks;
@@ -77,8 +78,9 @@ struct HipExecutor {
   }
 
   bool init() {
-    grid_cap = batch_resident_blocks();
-    if (grid_cap <= 0) return false;
+    cap_main = batch_resident_blocks(false);
+    cap_div = batch_resident_blocks(true);
+    if (cap_main <= 0 || cap_div <= 0) return false;
     for (Slot& s : slot) {
       if (hipStreamCreateWithFlags(&s.stream, hipStreamNonBlocking) != hipSuccess) return false;
       if (hipEventCreateWithFlags(&s.done, hipEventDisableTiming) != hipSuccess) return false;
@@ -130,10 +132,8 @@ struct HipExecutor {
         hipMemcpyAsync(s->d_chunks, s->h_chunks, chunks.size() * sizeof(BatchChunk), hipMemcpyHostToDevice,
                        s->stream) != hipSuccess)
       return BFP_E_HIP;
-    const unsigned grid = (unsigned)std::min<size_t>((size_t)grid_cap, chunks.size());
-    if (batch_launch(s->d_tasks, s->d_chunks, (uint32_t)chunks.size(), s->d_counter, grid, s->stream) !=
-        hipSuccess)
-      return BFP_E_HIP;
+    const BatchSplit split = batch_split(tasks, chunks, cap_main, cap_div);
+    if (batch_launch(s->d_tasks, s->d_chunks, split, s->d_counter, s->stream) != hipSuccess) return BFP_E_HIP;
     if (hipEventRecord(s->done, s->stream) != hipSuccess) return BFP_E_HIP;
     s->busy = true;
     s->seq = ++seq;
@@ -266,7 +266,7 @@ bfp_status bfp_server_put(bfp_server* s, bfp_format f, const void* std_dev, uint
 bfp_status bfp_server_submit(bfp_server* s, int op, bfp_format f, uint32_t a, uint32_t b, uint64_t n,
                              uint64_t* req_id) {
   if (!s || !req_id) return BFP_E_NULL;
-  if (op != BFP_ADD && op != BFP_SUB && op != BFP_MUL) return BFP_E_OP;
+  if (!op_valid(op)) return BFP_E_OP;
   if (!bfp_format_supported(f)) return BFP_E_FORMAT;
   {
     std::lock_guard<std::mutex> lk(s->sched->mutex());
@@ -308,7 +308,7 @@ bfp_status bfp_server_replay(bfp_server* s, const bfp_request* reqs, uint32_t co
   // check everything first so a bad entry cannot leave a half-submitted schedule
   for (uint32_t i = 0; i < count; ++i) {
     const bfp_request& r = reqs[i];
-    if (r.op != BFP_ADD && r.op != BFP_SUB && r.op != BFP_MUL) return BFP_E_OP;
+    if (!op_valid(r.op)) return BFP_E_OP;
     if (!bfp_format_supported(r.f)) return BFP_E_FORMAT;
     if (r.arrival_ns < 0 || (i && r.arrival_ns < reqs[i - 1].arrival_ns)) return BFP_E_ARG;
   }

@@ -57,7 +57,7 @@ using namespace bfp;
 
 extern "C" bfp_status bfp_autotune(int op, bfp_format f, uint64_t n_probe, int words_per_lane_mask, int reps,
                                    void* stream, bfp_launch* best_out, double* best_us_out) {
-  if (op != BFP_ADD && op != BFP_SUB && op != BFP_MUL) return BFP_E_OP;
+  if (!op_valid(op)) return BFP_E_OP;
   if (!bfp_format_supported(f)) return BFP_E_FORMAT;
   if (n_probe == 0 || n_probe > (1ull << 30)) return BFP_E_ARG;
   if ((words_per_lane_mask & 3) == 0) return BFP_E_ARG;

@@ -22,7 +22,7 @@ import sqlite3
 
 PKG = os.path.dirname(os.path.abspath(__file__))
 KERNEL_SOURCES = ["bfp_word.hpp", "bfp_circuits.hpp", "bfp_transpose.hpp", "bfp_kernels.hpp",
-                  "bfp_runtime.hip", "bfp_batch.hip"]
+                  "bfp_ops.hpp", "bfp_runtime.hip", "bfp_batch.hip"]
 CALIB_BYTES = 256 * 1024 * 1024  # read and written by the calibration kernel
 CALIB_PATTERN = "direct_copy_kernel"
 

@@ -15,7 +15,8 @@ import numpy as np
 
 from . import bfp, inputs
 
-OPS = ("add", "sub", "mul")
+OPS = ("add", "sub", "mul")           # the request mix of the serving measurement
+ALL_OPS = ("add", "sub", "mul", "div")
 
 
 _LIVE = set()
@@ -102,15 +103,16 @@ def build_pool(server: Server, formats, n: int, seed: int, device, sample_log2: 
     return pool
 
 
-def request_stream(count: int, formats, seed: int, nmin_log2: float = 10, nmax_log2: float = 22, nmax=None):
+def request_stream(count: int, formats, seed: int, nmin_log2: float = 10, nmax_log2: float = 22, nmax=None,
+                   ops=OPS):
     """(op, (e, m), n) with n = floor(2^U(nmin_log2, nmax_log2)), uniform format and op."""
     rng = np.random.default_rng(seed)
     ns = np.floor(np.exp2(rng.uniform(nmin_log2, nmax_log2, count))).astype(np.int64)
     if nmax is not None:
         ns = np.minimum(ns, nmax)
     fi = rng.integers(0, len(formats), count)
-    oi = rng.integers(0, 3, count)
-    return [(OPS[oi[i]], formats[fi[i]], int(max(1, ns[i]))) for i in range(count)]
+    oi = rng.integers(0, len(ops), count)
+    return [(ops[oi[i]], formats[fi[i]], int(max(1, ns[i]))) for i in range(count)]
 
 
 def run(server: Server, pool, reqs, rate=None, rnd: int = 0, seed: int = 0, keep_results: bool = False,

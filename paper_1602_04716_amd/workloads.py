@@ -13,7 +13,8 @@ import numpy as np
 
 from . import bfp, inputs
 
-OPS = ("add", "sub", "mul")
+OPS = ("add", "sub", "mul")           # the op mix of the batched measurement
+ALL_OPS = ("add", "sub", "mul", "div")
 
 
 class Batch:

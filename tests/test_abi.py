@@ -70,7 +70,8 @@ def test_argument_errors_before_any_device_work():
     assert L.bfp_pack(f, 17, 4096, 10, None) == -3                       # alignment
     assert L.bfp_pack(f, 4096, 4096, 10, None) == -7                     # overlap
     assert L.bfp_pack(f, 0, 0, 0, None) == 0                             # n == 0
-    assert L.bfp_binop(3, f, 16, 32, 48, 1, None) == -4                  # op
+    assert L.bfp_binop(4, f, 16, 32, 48, 1, None) == -4                  # op
+    assert L.bfp_binop(-1, f, 16, 32, 48, 1, None) == -4
     assert L.bfp_binop(0, f, 16, 32, 0, 1, None) == -2
     assert L.bfp_binop(0, f, 4096, 1 << 20, 4096 + 16, 100, None) == -7  # partial overlap
     assert L.bfp_binop(0, f, 4096, 1 << 20, 0, 0, None) == 0
@@ -92,6 +93,18 @@ def test_launch_table_roundtrip(tmp_path):
     bfp.bfp_launch_load(p)
     assert bfp.bfp_launch_get("mul", f).block == 128
     bfp.bfp_launch_set("mul", f, old.words_per_lane, old.block, old.blocks_per_cu)
+    # division has a table entry of its own
+    old_d = bfp.bfp_launch_get("div", f)
+    bfp.bfp_launch_set("div", f, 1, 512, 8)
+    bfp.bfp_launch_save(p)
+    bfp.bfp_launch_set("div", f, old_d.words_per_lane, old_d.block, old_d.blocks_per_cu)
+    cm = bfp.bfp_launch_get("mul", f)
+    assert (cm.words_per_lane, cm.block, cm.blocks_per_cu) == (old.words_per_lane, old.block, old.blocks_per_cu)
+    bfp.bfp_launch_load(p)
+    c = bfp.bfp_launch_get("div", f)
+    assert (c.words_per_lane, c.block, c.blocks_per_cu) == (1, 512, 8)
+    bfp.bfp_launch_set("div", f, old_d.words_per_lane, old_d.block, old_d.blocks_per_cu)
+    bfp.bfp_launch_set("mul", f, old.words_per_lane, old.block, old.blocks_per_cu)
     with pytest.raises(bfp.BfpError):
         bfp.bfp_launch_set("add", f, 3, 256, 0)
     with pytest.raises(bfp.BfpError):
@@ -99,7 +112,8 @@ def test_launch_table_roundtrip(tmp_path):
 
 
 def test_gate_counts_positive():
-    for op in ("add", "sub", "mul"):
+    for op in ("add", "sub", "mul", "div"):
         assert bfp.bfp_gate_count(op, bfp.fmt(5, 10)) > 100
+    assert bfp.bfp_gate_count(4, bfp.fmt(5, 10)) == -1
     assert bfp.bfp_gate_count("add", bfp.fmt(5, 10)) == bfp.bfp_gate_count("sub", bfp.fmt(5, 10))
     assert bfp.bfp_gate_count("add", bfp.fmt(7, 3)) == -1

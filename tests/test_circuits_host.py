@@ -44,7 +44,7 @@ SMALL = [(e, m) for (e, m) in FORMATS if 1 + e + m <= 8]
 def test_exhaustive_small(sim, oracle_lib, e, m):
     B = 1 + e + m
     a, b = inputs.exhaustive_pairs(B)
-    for op in (0, 1, 2):
+    for op in (0, 1, 2, 3):
         for mode in (0, 1):
             assert np.array_equal(_run(sim, op, e, m, mode, a, b), oracle_lib.binop(op, e, m, mode, a, b))
 
@@ -61,12 +61,17 @@ def test_random_and_edges(sim, oracle_lib, e, m):
     q = n // 4
     b[:q] = (((a[:q].astype(np.uint64) + rng.integers(0, 3, q).astype(np.uint64)) % (1 << B))
              ^ (1 << (e + m))).astype(np.uint32)
+    # subnormal or lowest-binade dividends (and divisors): the quotient's
+    # fewest bits below the rounding point, and the pre-normalisation shifts
+    low = (1 << (m + 2)) - 1 | (1 << (e + m))
+    a[q:2 * q] &= low
+    b[2 * q:3 * q] &= low
     pos = edge_patterns(f)
     pats = pos + [p | f.sign_bit for p in pos]
     ea = np.array([x for x in pats for _ in pats], dtype=np.uint32)
     eb = np.array([y for _ in pats for y in pats], dtype=np.uint32)
     a, b = np.concatenate([a, ea]), np.concatenate([b, eb])
-    for op in (0, 1, 2):
+    for op in (0, 1, 2, 3):
         for mode in (0, 1):
             want = oracle_lib.binop(op, e, m, mode, a, b, nthreads=4)
             got32 = _run(sim, op, e, m, mode, a, b, 32)
@@ -91,10 +96,12 @@ def test_figure2_adder(sim):
 
 def test_table1_cost_growth(sim):
     """Table 1: add costs O(n log n) in the significand width (alignment and
-    normalisation shifters), mul O(n^2) (the significand multiply).  Least
-    squares over p = m + 1 at fixed e = 8: mul's p^2 coefficient is the
-    array multiplier's ~3 gates per cell; add has no quadratic term but a
-    positive term in p times the number of log-shifter stages."""
+    normalisation shifters), mul and div O(n^2) (the significand multiply,
+    the digit-by-digit divide).  Least squares over p = m + 1 at fixed e = 8:
+    the p^2 coefficients are ~3 gates per cell (array multiplier: and, sum,
+    carry; restoring divider: difference, borrow, restore); add has no
+    quadratic term but a positive term in p times the number of log-shifter
+    stages."""
     ms = [1, 2, 3, 5, 7, 10, 15, 23]
     p = np.array([m + 1 for m in ms], dtype=float)
     for mode in (0, 1):
@@ -103,6 +110,9 @@ def test_table1_cost_growth(sim):
         A = np.stack([np.ones_like(p), p, p ** 2], axis=1)
         c_mul = np.linalg.lstsq(A, mul, rcond=None)[0]
         assert 2.5 < c_mul[2] < 3.5, c_mul
+        div = np.array([sim.bfpsim_gate_count(3, 8, m, mode) for m in ms], dtype=float)
+        c_div = np.linalg.lstsq(A, div, rcond=None)[0]
+        assert 2.5 < c_div[2] < 3.5, c_div
         c_add_q = np.linalg.lstsq(A, add, rcond=None)[0]
         assert abs(c_add_q[2]) < 0.1 * c_mul[2], c_add_q
         stages = np.ceil(np.log2(p + 3))  # barrel-shifter stages over the aligned width
@@ -116,7 +126,7 @@ def test_table1_cost_growth(sim):
 def test_round_toward_zero_is_cheaper(sim):
     """Section 5.2: toward-zero rounding needs fewer gates than nearest-even."""
     for (e, m) in FORMATS:
-        for op in (0, 2):
+        for op in (0, 2, 3):
             assert sim.bfpsim_gate_count(op, e, m, 1) < sim.bfpsim_gate_count(op, e, m, 0)
 
 

@@ -29,11 +29,11 @@ def _mixed_specs(count, seed):
     for i in range(count):
         n = edge_n[i] if i < len(edge_n) else int(np.exp(rng.uniform(0, np.log(120000))))
         e, m = fmts[int(rng.integers(0, len(fmts)))] if i >= len(edge_n) else fmts[i % len(fmts)]
-        op = workloads.OPS[int(rng.integers(0, 3))]
+        op = workloads.ALL_OPS[int(rng.integers(0, len(workloads.ALL_OPS)))]
         specs.append((max(1, n), e, m, op, int(rng.integers(0, 2))))
     # every format x op x mode at least once
     for k, (e, m) in enumerate(fmts):
-        for op in workloads.OPS:
+        for op in workloads.ALL_OPS:
             for r in (0, 1):
                 specs.append((1000 + 37 * k, e, m, op, r))
     return specs

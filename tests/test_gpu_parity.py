@@ -15,7 +15,7 @@ from paper_1602_04716_amd import bfp, inputs
 pytestmark = pytest.mark.gpu
 
 FORMATS = inputs.sweep_formats()
-OPS = ["add", "sub", "mul"]
+OPS = ["add", "sub", "mul", "div"]
 NPAR = 70000 + 13  # 2188 words per plane: several blocks and a ragged last word
 
 
@@ -167,6 +167,10 @@ def test_in_place_and_zero_length():
     bfp.bfp_mul(f, pa, pb, pa, 5000)  # c == a
     assert np.array_equal(_host(bfp.unpack(f, pa, 5000)).astype(np.uint32), want)
     bfp.bfp_add(f, pa, pb, pa, 0)  # no-op
+    pa = bfp.pack(f, _dev(a))
+    bfp.bfp_div(f, pa, pb, pb, 5000)  # c == b
+    assert np.array_equal(_host(bfp.unpack(f, pb, 5000)).astype(np.uint32), oracle.binop("div", e, m, 0, a, b))
+    pb = bfp.pack(f, _dev(b))
     da = _dev(a)
     bfp.bfp_binop_std("sub", f, da, _dev(b), da, 5000)  # c == a, fused path
     assert np.array_equal(_host(da).astype(np.uint32), oracle.binop("sub", e, m, 0, a, b))
@@ -199,7 +203,7 @@ def test_full_size_2_26(e, m):
             ha, hb = ta.view(torch.float16), tb.view(torch.float16)
         else:
             ha, hb = ta.view(torch.bfloat16).float(), tb.view(torch.bfloat16).float()
-        r = {"add": ha + hb, "sub": ha - hb, "mul": ha * hb}[op]
+        r = {"add": ha + hb, "sub": ha - hb, "mul": ha * hb, "div": ha / hb}[op]
         if (e, m) == (8, 7):
             r = r.to(torch.bfloat16)
         nat = r.view(torch.int16).cpu().numpy().view(np.uint16).astype(np.uint32)

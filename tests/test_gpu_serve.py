@@ -47,7 +47,7 @@ def test_mix_matches_oracle_and_alone():
     srv = serving.Server(2 << 30, 256)
     pool = serving.build_pool(srv, FMTS, N0, seed=5, device="cuda")
     host = _pool_host(srv, pool, FMTS)
-    reqs = serving.request_stream(400, FMTS, seed=6, nmin_log2=0, nmax_log2=16, nmax=N0)
+    reqs = serving.request_stream(400, FMTS, seed=6, nmin_log2=0, nmax_log2=16, nmax=N0, ops=serving.ALL_OPS)
     res = serving.run(srv, pool, reqs, rate=None, rnd=0, keep_results=True)
     assert res["errors"] == 0
     st = srv.stats()
@@ -87,7 +87,7 @@ def test_budget_defers_and_never_exceeds():
     budget = pool_bytes + 3 * biggest + 4096
     srv = serving.Server(budget, 64)
     pool = serving.build_pool(srv, f_list, N0, seed=7, device="cuda")
-    reqs = [(op, fm, N0 - 3 * k) for k, (op, fm) in enumerate([(o, f) for o in serving.OPS for f in f_list] * 10)]
+    reqs = [(op, fm, N0 - 3 * k) for k, (op, fm) in enumerate([(o, f) for o in serving.ALL_OPS for f in f_list] * 10)]
     res = serving.run(srv, pool, reqs, rate=None)
     st = srv.stats()
     assert res["errors"] == 0 and st["completed"] == len(reqs)

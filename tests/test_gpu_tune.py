@@ -19,7 +19,7 @@ def gpu():
     oracle.build()
 
 
-@pytest.mark.parametrize("e,m,op", [(5, 10, "add"), (8, 23, "mul"), (3, 1, "sub")])
+@pytest.mark.parametrize("e,m,op", [(5, 10, "add"), (8, 23, "mul"), (3, 1, "sub"), (5, 10, "div")])
 def test_autotune_installs_measured_best(e, m, op):
     f = bfp.fmt(e, m)
     old = bfp.bfp_launch_get(op, f)
@@ -39,19 +39,20 @@ def test_every_candidate_configuration_is_exact():
     n = 300000 + 5
     a = inputs.sweep_operands(e, m, n, 1)
     b = inputs.sweep_operands(e, m, n, 2)
-    want = oracle.binop("mul", e, m, 0, a, b, nthreads=8)
     f = bfp.fmt(e, m)
     pa, pb = bfp.pack(f, torch.from_numpy(a).cuda()), bfp.pack(f, torch.from_numpy(b).cuda())
-    old = bfp.bfp_launch_get("mul", f)
-    for wpl in (1, 2):
-        for blk in (64, 128, 256, 512):
-            for bpc in (0, 4, 8):
-                bfp.bfp_launch_set("mul", f, wpl, blk, bpc)
-                pc = bfp.empty_bitslice(f, n)
-                bfp.bfp_mul(f, pa, pb, pc, n)
-                got = bfp.unpack(f, pc, n).cpu().numpy().astype(np.uint32)
-                assert np.array_equal(got, want), (wpl, blk, bpc)
-    bfp.bfp_launch_set("mul", f, old.words_per_lane, old.block, old.blocks_per_cu)
+    for op in ("mul", "div"):
+        want = oracle.binop(op, e, m, 0, a, b, nthreads=8)
+        old = bfp.bfp_launch_get(op, f)
+        for wpl in (1, 2):
+            for blk in (64, 128, 256, 512):
+                for bpc in (0, 4, 8):
+                    bfp.bfp_launch_set(op, f, wpl, blk, bpc)
+                    pc = bfp.empty_bitslice(f, n)
+                    bfp.bfp_binop(op, f, pa, pb, pc, n)
+                    got = bfp.unpack(f, pc, n).cpu().numpy().astype(np.uint32)
+                    assert np.array_equal(got, want), (op, wpl, blk, bpc)
+        bfp.bfp_launch_set(op, f, old.words_per_lane, old.block, old.blocks_per_cu)
 
 
 def test_autotune_errors():
