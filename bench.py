@@ -17,6 +17,9 @@ Also printed in the same JSON line:
   kernels       every kernel's mean duration and rates, measured the same way;
   batched       (with --batched) 4096 mixed vectors: one persistent launch vs
                 one launch per vector;
+  div           division (Table 1, Div) on resident bitslice vectors of the
+                same size and formats, the launch table's configuration:
+                elements/s and its bitwise VALU rate against peak;
   cpu_baseline  the oracle timed on this host on a bounded sample.
 """
 from __future__ import annotations
@@ -50,6 +53,8 @@ def parse():
                          "written) so hardware byte counters can be scaled against a kernel of known traffic")
     ap.add_argument("--batched-reps", type=int, default=10)
     ap.add_argument("--no-serving", action="store_true")
+    ap.add_argument("--no-div", action="store_true")
+    ap.add_argument("--div-reps", type=int, default=10)
     ap.add_argument("--serving-requests", type=int, default=20000)
     return ap.parse_args()
 
@@ -123,6 +128,43 @@ def bench_serving(torch, bfp, dev, n_req):
     return out
 
 
+def bench_div(torch, bfp, dev, n, reps):
+    """Division on resident bitslice vectors of n elements per bench format,
+    round to nearest even, launch configuration from the tuned table; the
+    event pair brackets `reps` back-to-back launches on the launch stream."""
+    from paper_1602_04716_amd import inputs
+    s = torch.cuda.current_stream()
+    out = {}
+    for (e, m) in FORMATS:
+        f = bfp.fmt(e, m)
+        B = 1 + e + m
+        a = torch.from_numpy(inputs.scaled_normal(e, m, n, 2)).to(dev)
+        b = torch.from_numpy(inputs.scaled_normal(e, m, n, 3)).to(dev)
+        pa, pb = bfp.pack(f, a), bfp.pack(f, b)
+        pc = bfp.empty_bitslice(f, n, dev)
+        del a, b
+        for _ in range(2):
+            bfp.bfp_div(f, pa, pb, pc, n, s)
+        ev0, ev1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+        ev0.record(s)
+        for _ in range(reps):
+            bfp.bfp_div(f, pa, pb, pc, n, s)
+        ev1.record(s)
+        torch.cuda.synchronize()
+        us = ev0.elapsed_time(ev1) * 1e3 / reps
+        G = bfp.bfp_gate_count("div", f)
+        cfg = bfp.bfp_launch_get("div", f)
+        ops_s = G * n / 32 / (us * 1e-6)
+        bytes_s = 3 * B / 8 * n / (us * 1e-6)
+        out["(%d,%d)" % (e, m)] = {
+            "us": us, "elements_per_s": n / (us * 1e-6), "gates": G, "Tops/s": ops_s / 1e12,
+            "valu_frac": ops_s / VALU_PEAK, "GB/s": bytes_s / 1e9, "hbm_frac": bytes_s / HBM_PEAK,
+            "device_kernel": "bfp::k_binop<%d, %d, false, 2, %d>" % (e, m, cfg.words_per_lane),
+            "block": cfg.block, "blocks_per_cu": cfg.blocks_per_cu}
+        del pa, pb, pc
+    return out
+
+
 def device_kernel(label):
     """Device kernel that a bench label ("unpack(8,7)", "mul(5,10)") launches
     with the bench's configuration (64-element lane words, nearest-even)."""
@@ -134,7 +176,7 @@ def device_kernel(label):
         return "bfp::k_pack<%d>" % C
     if kind == "unpack":
         return "bfp::k_unpack<%d>" % C
-    return "bfp::k_binop<%d, %d, false, %d, 2>" % (e, m, 1 if kind == "mul" else 0)
+    return "bfp::k_binop<%d, %d, false, %d, 2>" % (e, m, {"add": 0, "sub": 0, "mul": 1, "div": 2}[kind])
 
 
 def committed_traffic(kernel):
@@ -323,6 +365,8 @@ def main():
         res["batched"] = bench_batched(torch, bfp, dev, args.batched_reps)
     if not args.no_serving:
         res["serving"] = bench_serving(torch, bfp, dev, args.serving_requests)
+    if not args.no_div:
+        res["div"] = bench_div(torch, bfp, dev, n, args.div_reps)
     if not args.no_cpu_baseline:
         res["cpu_baseline"] = cpu_baseline()
     print(json.dumps(res), flush=True)

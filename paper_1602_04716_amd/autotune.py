@@ -3,7 +3,7 @@
     python -m paper_1602_04716_amd.autotune [--n-log2 24] [--reps 7] [--out tuning/gfx950.txt]
 
 For each format of the sweep (e in {3,4,5,6,8} x m in {1,2,3,5,7,10,15,23}),
-each op class (add, mul) and each rounding mode, ``bfp_autotune`` times the
+each op class (add, mul, div) and each rounding mode, ``bfp_autotune`` times the
 launch variants on a 2^24-element probe with the last-level cache swept clean
 before every run and installs the fastest; the table is saved for
 ``bfp.lib()`` to load.  The printed JSON lines are the format-sweep
@@ -24,7 +24,7 @@ HBM_PEAK = 8.0e12
 VALU_PEAK = 256 * 4 * 16 * 2.4e9
 
 
-def tune(formats, ops=("add", "mul"), modes=(0, 1), n=1 << 24, reps=7, mask=3, log=print):
+def tune(formats, ops=("add", "mul", "div"), modes=(0, 1), n=1 << 24, reps=7, mask=3, log=print):
     out = []
     for (e, m) in formats:
         for op in ops:
@@ -52,6 +52,7 @@ def main(argv=None):
     ap.add_argument("--reps", type=int, default=7)
     ap.add_argument("--out", default=bfp.TUNE_TABLE)
     ap.add_argument("--formats", default="", help="comma list like 5:10,8:7; default all 40")
+    ap.add_argument("--ops", default="add,mul,div", help="op classes to tune (sub shares add's entry)")
     a = ap.parse_args(argv)
     import torch
     assert torch.cuda.is_available()
@@ -60,7 +61,7 @@ def main(argv=None):
     fmts = inputs.sweep_formats()
     if a.formats:
         fmts = [tuple(int(x) for x in s.split(":")) for s in a.formats.split(",")]
-    tune(fmts, n=1 << a.n_log2, reps=a.reps, log=lambda s: print(s, flush=True))
+    tune(fmts, ops=tuple(a.ops.split(",")), n=1 << a.n_log2, reps=a.reps, log=lambda s: print(s, flush=True))
     if a.out:
         os.makedirs(os.path.dirname(a.out), exist_ok=True)
         bfp.bfp_launch_save(a.out)
