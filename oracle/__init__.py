@@ -87,6 +87,20 @@ def binop(op, e: int, m: int, mode: int, a, b, nthreads: int = 1) -> np.ndarray:
     return c
 
 
+def chain2(op1, op2, e: int, m: int, mode: int, a, b, c, nthreads: int = 1) -> np.ndarray:
+    """(a op1 b) op2 c, each op rounded on its own: the definition of a
+    two-op chain is the composition of the two elementwise ops."""
+    t = binop(op1, e, m, mode, a, b, nthreads)
+    return binop(op2, e, m, mode, t, c, nthreads)
+
+
+def axpy(e: int, m: int, mode: int, alpha: int, x, y, nthreads: int = 1) -> np.ndarray:
+    """alpha * x + y with the pattern alpha broadcast (bits above 1+e+m ignored)."""
+    xs = np.asarray(x)
+    al = np.full(xs.shape, int(alpha) & ((1 << (1 + e + m)) - 1), dtype=np.uint32)
+    return chain2("mul", "add", e, m, mode, al, xs, y, nthreads)
+
+
 def from_double(e: int, m: int, mode: int, v: float) -> int:
     return int(lib().oracle_from_double(e, m, mode, float(v)))
 

@@ -67,3 +67,32 @@ void f16_binop_rz(int op, const uint16_t *a, const uint16_t *b, uint16_t *c, siz
     }
     _mm_setcsr(csr);
 }
+
+/* d = (a op1 b) op2 c in binary32, each op rounded (the intermediate is
+ * stored to a volatile float, so no fused multiply-add can form). */
+void f32_chain2(int op1, int op2, int mode, const uint32_t *a, const uint32_t *b, const uint32_t *c,
+                uint32_t *d, size_t n) {
+    unsigned csr = clear_ftz_daz();
+    int old = fegetround();
+    fesetround(mode == 0 ? FE_TONEAREST : FE_TOWARDZERO);
+    for (size_t i = 0; i < n; i++) {
+        volatile float x, y, z, t, r;
+        float tx, ty, tz;
+        memcpy(&tx, &a[i], 4);
+        memcpy(&ty, &b[i], 4);
+        memcpy(&tz, &c[i], 4);
+        x = tx;
+        y = ty;
+        z = tz;
+        if (op1 == 0) t = x + y;
+        else if (op1 == 1) t = x - y;
+        else t = x * y;
+        if (op2 == 0) r = t + z;
+        else if (op2 == 1) r = t - z;
+        else r = t * z;
+        float tr = r;
+        memcpy(&d[i], &tr, 4);
+    }
+    fesetround(old);
+    _mm_setcsr(csr);
+}

@@ -29,6 +29,7 @@ def native():
     vp, i32, sz = ctypes.c_void_p, ctypes.c_int, ctypes.c_size_t
     L.f32_binop.argtypes = [i32, i32, vp, vp, vp, sz]
     L.f16_binop_rz.argtypes = [i32, vp, vp, vp, sz]
+    L.f32_chain2.argtypes = [i32, i32, i32, vp, vp, vp, vp, sz]
     return L
 
 
@@ -200,3 +201,32 @@ def test_from_double_matches_native_conversions(oracle_lib):
         assert oracle_lib.from_double(5, 10, 0, v) == int(h[i]), v
         assert oracle_lib.from_double(8, 23, 0, v) == int(f[i]), v
     assert oracle_lib.from_double(5, 10, 0, float("nan")) == 0x7E00
+
+
+@pytest.mark.parametrize("mode", [0, 1])
+def test_chain2_binary32(oracle_lib, native, mode):
+    """Two-op chains: the oracle's composition against binary32 arithmetic
+    with the intermediate rounded to float (every op pair of add/sub/mul)."""
+    rng = np.random.default_rng(70 + mode)
+    a, b = _operands(rng, 8, 23, 60000)
+    c, _ = _operands(rng, 8, 23, 60000)
+    ops = ["add", "sub", "mul"]
+    for i1, op1 in enumerate(ops):
+        for i2, op2 in enumerate(ops):
+            want = np.empty_like(a)
+            native.f32_chain2(i1, i2, mode, a.ctypes.data, b.ctypes.data, c.ctypes.data, want.ctypes.data, a.size)
+            got = oracle_lib.chain2(op1, op2, 8, 23, mode, a, b, c, nthreads=4)
+            _compare(8, 23, got, want, a, b, ("f32 chain", op1, op2, mode))
+
+
+def test_axpy_binary16_numpy(oracle_lib):
+    """alpha * x + y in binary16 (numpy float16: each op rounded to nearest)."""
+    rng = np.random.default_rng(71)
+    x, y = _operands(rng, 5, 10, 100000)
+    for alpha in (0x3C00, 0xC100, 0x0001, 0x7BFF, 0x8000, 0x7C00, 0x3555):
+        hx, hy = x.astype(np.uint16).view(np.float16), y.astype(np.uint16).view(np.float16)
+        ha = np.float16(np.uint16(alpha).view(np.float16))
+        with np.errstate(all="ignore"):
+            want = (ha * hx + hy).view(np.uint16).astype(np.uint32)
+        got = oracle_lib.axpy(5, 10, 0, alpha, x, y, nthreads=4)
+        _compare(5, 10, got, want, x, y, ("f16 axpy", hex(alpha)))
