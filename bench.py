@@ -20,6 +20,9 @@ Also printed in the same JSON line:
   div           division (Table 1, Div) on resident bitslice vectors of the
                 same size and formats, the launch table's configuration:
                 elements/s and its bitwise VALU rate against peak;
+  chain         d = a*b + c on the same vectors: one two-op chain kernel
+                (intermediate in registers, 4 vectors through HBM) against
+                the two separate launches (6 vectors);
   cpu_baseline  the oracle timed on this host on a bounded sample.
 """
 from __future__ import annotations
@@ -54,6 +57,7 @@ def parse():
     ap.add_argument("--batched-reps", type=int, default=10)
     ap.add_argument("--no-serving", action="store_true")
     ap.add_argument("--no-div", action="store_true")
+    ap.add_argument("--no-chain", action="store_true")
     ap.add_argument("--div-reps", type=int, default=10)
     ap.add_argument("--serving-requests", type=int, default=20000)
     return ap.parse_args()
@@ -162,6 +166,49 @@ def bench_div(torch, bfp, dev, n, reps):
             "device_kernel": "bfp::k_binop<%d, %d, false, 2, %d>" % (e, m, cfg.words_per_lane),
             "block": cfg.block, "blocks_per_cu": cfg.blocks_per_cu}
         del pa, pb, pc
+    return out
+
+
+def bench_chain(torch, bfp, dev, n, reps):
+    """d = a*b + c per bench format, nearest-even: the fused chain kernel vs
+    bfp_mul + bfp_add into a temporary, each timed over `reps` back-to-back
+    repetitions between two events on the launch stream."""
+    from paper_1602_04716_amd import inputs
+    s = torch.cuda.current_stream()
+    out = {}
+    for (e, m) in FORMATS:
+        f = bfp.fmt(e, m)
+        B = 1 + e + m
+        pa, pb, pc = (bfp.pack(f, torch.from_numpy(inputs.scaled_normal(e, m, n, k)).to(dev)) for k in (2, 3, 4))
+        pd, pt = bfp.empty_bitslice(f, n, dev), bfp.empty_bitslice(f, n, dev)
+
+        def fused():
+            bfp.bfp_chain2("mul", "add", f, pa, pb, pc, pd, n, s)
+
+        def separate():
+            bfp.bfp_mul(f, pa, pb, pt, n, s)
+            bfp.bfp_add(f, pt, pc, pd, n, s)
+
+        res = {}
+        for name, fn in (("fused", fused), ("separate", separate)):
+            for _ in range(2):
+                fn()
+            ev0, ev1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+            ev0.record(s)
+            for _ in range(reps):
+                fn()
+            ev1.record(s)
+            torch.cuda.synchronize()
+            res[name] = ev0.elapsed_time(ev1) * 1e3 / reps
+        G = bfp.bfp_gate_count("mul", f) + bfp.bfp_gate_count("add", f)
+        us = res["fused"]
+        out["(%d,%d)" % (e, m)] = {
+            "fused_us": us, "separate_us": res["separate"], "speedup": res["separate"] / us,
+            "elements_per_s": n / (us * 1e-6), "GB/s": 4 * B / 8 * n / (us * 1e-6) / 1e9,
+            "hbm_frac": 4 * B / 8 * n / (us * 1e-6) / HBM_PEAK,
+            "valu_frac": G * n / 32 / (us * 1e-6) / VALU_PEAK,
+            "device_kernel": "bfp::k_chain2<%d, %d, false, 1, 0, 1>" % (e, m)}
+        del pa, pb, pc, pd, pt
     return out
 
 
@@ -367,6 +414,8 @@ def main():
         res["serving"] = bench_serving(torch, bfp, dev, args.serving_requests)
     if not args.no_div:
         res["div"] = bench_div(torch, bfp, dev, n, args.div_reps)
+    if not args.no_chain:
+        res["chain"] = bench_chain(torch, bfp, dev, n, args.div_reps)
     if not args.no_cpu_baseline:
         res["cpu_baseline"] = cpu_baseline()
     print(json.dumps(res), flush=True)

@@ -140,6 +140,25 @@ bfp_status bfp_sub(bfp_format f, const void* a, const void* b, void* c, uint64_t
 bfp_status bfp_mul(bfp_format f, const void* a, const void* b, void* c, uint64_t n, void* stream);
 bfp_status bfp_div(bfp_format f, const void* a, const void* b, void* c, uint64_t n, void* stream);
 
+/* ---- two-op chains on resident bitslice vectors ---------------------------- */
+/* d = (a op1 b) op2 c elementwise in one kernel, op1, op2 in {BFP_ADD,
+ * BFP_SUB, BFP_MUL} (BFP_E_OP otherwise).  Each op rounds on its own in
+ * format f, so d equals bfp_binop(op1, ...) into a temporary followed by
+ * bfp_binop(op2, ...) bit for bit; the temporary stays in registers, so 4
+ * vectors cross HBM instead of 6.  (Section 4 merges the steps of one
+ * operation to avoid storing intermediate results; this applies the same
+ * idea across operations.)  a, b, c, d: device bitslice vectors of n
+ * elements in format f; d may be the same buffer as a, b or c; partial
+ * overlaps are not allowed; bits of elements at and above n in d are zero. */
+bfp_status bfp_chain2(int op1, int op2, bfp_format f, const void* a, const void* b, const void* c, void* d,
+                      uint64_t n, void* stream);
+
+/* d = alpha * x + y (multiply, then add, each rounded), alpha one standard
+ * pattern of format f broadcast to every element (bits above 1+e+m are
+ * ignored).  x, y, d as for bfp_chain2. */
+bfp_status bfp_axpy(bfp_format f, uint32_t alpha, const void* x, const void* y, void* d, uint64_t n,
+                    void* stream);
+
 /* Fused standard-in / standard-out op: pack both operands in registers, run
  * the circuit, unpack, in one kernel with no bitslice round trip to memory.
  * a, b, c: device, n containers each (bfp_container_bytes).  c may equal a

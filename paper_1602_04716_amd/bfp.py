@@ -94,6 +94,10 @@ _SIGS = {
                                ctypes.c_void_p]),
     "bfp_div": (ctypes.c_int, [bfp_format, ctypes.c_void_p, ctypes.c_void_p, ctypes.c_void_p, ctypes.c_uint64,
                                ctypes.c_void_p]),
+    "bfp_chain2": (ctypes.c_int, [ctypes.c_int, ctypes.c_int, bfp_format, ctypes.c_void_p, ctypes.c_void_p,
+                                  ctypes.c_void_p, ctypes.c_void_p, ctypes.c_uint64, ctypes.c_void_p]),
+    "bfp_axpy": (ctypes.c_int, [bfp_format, ctypes.c_uint32, ctypes.c_void_p, ctypes.c_void_p, ctypes.c_void_p,
+                                ctypes.c_uint64, ctypes.c_void_p]),
     "bfp_binop_std": (ctypes.c_int, [ctypes.c_int, bfp_format, ctypes.c_void_p, ctypes.c_void_p,
                                      ctypes.c_void_p, ctypes.c_uint64, ctypes.c_void_p]),
     "bfp_launch_get": (ctypes.c_int, [ctypes.c_int, bfp_format, ctypes.POINTER(bfp_launch)]),
@@ -239,6 +243,15 @@ def bfp_mul(f, a, b, c, n: int, stream=None):
 
 def bfp_div(f, a, b, c, n: int, stream=None):
     _check(lib().bfp_div(f, _ptr(a), _ptr(b), _ptr(c), n, _stream(stream)), "bfp_div")
+
+
+def bfp_chain2(op1, op2, f, a, b, c, d, n: int, stream=None):
+    _check(lib().bfp_chain2(_op(op1), _op(op2), f, _ptr(a), _ptr(b), _ptr(c), _ptr(d), n, _stream(stream)),
+           "bfp_chain2")
+
+
+def bfp_axpy(f, alpha: int, x, y, d, n: int, stream=None):
+    _check(lib().bfp_axpy(f, int(alpha), _ptr(x), _ptr(y), _ptr(d), n, _stream(stream)), "bfp_axpy")
 
 
 def bfp_binop_std(op, f, a, b, c, n: int, stream=None):

@@ -353,12 +353,19 @@ using BinopLauncher = hipError_t (*)(const void* a, const void* b, void* c, uint
 using StdLauncher = hipError_t (*)(const void* a, const void* b, void* c, uint64_t n, uint32_t negb,
                                    unsigned grid, unsigned block, hipStream_t s);
 
+using ChainLauncher = hipError_t (*)(const void* a, uint32_t alpha, const void* b, const void* c, void* d,
+                                     uint64_t gpad, uint64_t n, uint32_t negb1, uint32_t negb2, unsigned grid,
+                                     unsigned block, hipStream_t s);
+
 constexpr int kMaxWordsPerLane = 2;  // R in {1, 2}
 
 struct Registry {
   // [e][m][opclass][rz][R-1]
   BinopLauncher binop[9][24][kOpClasses][2][kMaxWordsPerLane] = {};
   StdLauncher std_op[9][24][kOpClasses][2] = {};
+  // two-op chains: [e][m][opclass of op1][opclass of op2][rz], op classes
+  // 0 (add/sub) and 1 (mul)
+  ChainLauncher chain[9][24][2][2][2] = {};
 };
 Registry& registry();
 

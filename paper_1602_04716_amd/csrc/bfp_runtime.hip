@@ -131,6 +131,32 @@ hipError_t launch_unpack(const void* src, void* dst, uint64_t n, uint64_t gpad, 
 
 bfp_status check_op(int op) { return op_valid(op) ? BFP_OK : BFP_E_OP; }
 
+// Ops a two-op chain accepts: add, sub, mul (division is not chained).
+bool chain_op_ok(int op) { return op == BFP_ADD || op == BFP_SUB || op == BFP_MUL; }
+
+// d = (a op1 b) op2 c; a == nullptr broadcasts the pattern alpha.
+bfp_status chain_impl(int op1, int op2, bfp_format f, const void* a, uint32_t alpha, const void* b, const void* c,
+                      void* d, uint64_t n, void* stream) {
+  if (!chain_op_ok(op1) || !chain_op_ok(op2)) return BFP_E_OP;
+  if (!format_ok(f)) return BFP_E_FORMAT;
+  if (n == 0) return BFP_OK;
+  if (n > kMaxN) return BFP_E_ARG;
+  if (!b || !c || !d) return BFP_E_NULL;
+  if ((a && !aligned16(a)) || !aligned16(b) || !aligned16(c) || !aligned16(d)) return BFP_E_ALIGN;
+  const uint64_t gpad = gpad_of(n);
+  const size_t bytes = (size_t)bits_of(f) * gpad * 4;
+  const void* in[3] = {a, b, c};
+  for (const void* p : in)
+    if (p && p != d && overlap(d, bytes, p, bytes)) return BFP_E_ALIAS;
+  ChainLauncher L = registry().chain[f.e][f.m][opclass_of(op1)][opclass_of(op2)][f.round];
+  if (!L) return BFP_E_FORMAT;
+  const unsigned block = 256;
+  const unsigned grid = grid_for(gpad, (int)block, 0);
+  const uint32_t alpha_b = alpha & (uint32_t)((1ull << bits_of(f)) - 1u);
+  const uint32_t negb1 = op1 == BFP_SUB ? 0xFFFFFFFFu : 0u, negb2 = op2 == BFP_SUB ? 0xFFFFFFFFu : 0u;
+  return hip_status(L(a, alpha_b, b, c, d, gpad, n, negb1, negb2, grid, block, (hipStream_t)stream));
+}
+
 }  // namespace
 }  // namespace bfp
 
@@ -230,6 +256,17 @@ bfp_status bfp_mul(bfp_format f, const void* a, const void* b, void* c, uint64_t
 }
 bfp_status bfp_div(bfp_format f, const void* a, const void* b, void* c, uint64_t n, void* stream) {
   return bfp_binop(BFP_DIV, f, a, b, c, n, stream);
+}
+
+bfp_status bfp_chain2(int op1, int op2, bfp_format f, const void* a, const void* b, const void* c, void* d,
+                      uint64_t n, void* stream) {
+  if (!a && n > 0) return BFP_E_NULL;
+  return chain_impl(op1, op2, f, a, 0u, b, c, d, n, stream);
+}
+
+bfp_status bfp_axpy(bfp_format f, uint32_t alpha, const void* x, const void* y, void* d, uint64_t n,
+                    void* stream) {
+  return chain_impl(BFP_MUL, BFP_ADD, f, nullptr, alpha, x, y, d, n, stream);
 }
 
 bfp_status bfp_binop_std(int op, bfp_format f, const void* a, const void* b, void* c, uint64_t n,

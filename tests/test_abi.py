@@ -77,6 +77,14 @@ def test_argument_errors_before_any_device_work():
     assert L.bfp_binop(0, f, 4096, 1 << 20, 0, 0, None) == 0
     assert L.bfp_binop_std(2, bfp.fmt(5, 10, 3), 16, 32, 48, 1, None) == -1
     assert L.bfp_unpack(f, 16, 32, 1 << 40, None) == -6                  # too long
+    assert L.bfp_chain2(3, 0, f, 16, 32, 48, 64, 1, None) == -4           # division is not chained
+    assert L.bfp_chain2(0, 4, f, 16, 32, 48, 64, 1, None) == -4
+    assert L.bfp_chain2(2, 0, f, 0, 32, 48, 64, 1, None) == -2
+    assert L.bfp_chain2(2, 0, f, 16, 32, 48, 72, 1, None) == -3
+    assert L.bfp_chain2(2, 0, f, 4096, 1 << 20, 1 << 21, 4096 + 16, 100, None) == -7
+    assert L.bfp_chain2(2, 0, f, 0, 0, 0, 0, 0, None) == 0
+    assert L.bfp_axpy(f, 0x3C00, 0, 32, 48, 1, None) == -2
+    assert L.bfp_axpy(bfp.fmt(7, 4), 0x3C00, 16, 32, 48, 1, None) == -1
     assert bfp.bfp_status_string(-5).startswith("HIP")
 
 
