@@ -7,7 +7,9 @@ GPU library and its Python binding never import it.
 The arithmetic lives in ``bfp_oracle.c`` (plain C, exact integers): decode to
 (sign, integer significand, exponent), compute the exact sum, product or
 quotient, round once to nearest-even or toward zero (Section 4 of the paper
-fixes the two modes; Table 1 the operations).  This module only marshals numpy arrays.
+fixes the two modes; Table 1 the operations).  k-bit integer vectors
+(Section 3, Figure 2) take the exact result modulo 2^k or clamped to the
+unsigned / signed range.  This module only marshals numpy arrays.
 """
 from __future__ import annotations
 
@@ -57,6 +59,8 @@ def lib():
         L.oracle_pack.argtypes = [i32, i32, vp, vp, u64, u64]
         L.oracle_unpack.restype = i32
         L.oracle_unpack.argtypes = [i32, i32, vp, vp, u64, u64]
+        L.oracle_int_binop.restype = i32
+        L.oracle_int_binop.argtypes = [i32, i32, i32, vp, vp, vp, u64]
         _lib = L
     return _lib
 
@@ -99,6 +103,28 @@ def axpy(e: int, m: int, mode: int, alpha: int, x, y, nthreads: int = 1) -> np.n
     xs = np.asarray(x)
     al = np.full(xs.shape, int(alpha) & ((1 << (1 + e + m)) - 1), dtype=np.uint32)
     return chain2("mul", "add", e, m, mode, al, xs, y, nthreads)
+
+
+INT_WRAP, INT_SAT_U, INT_SAT_S = 0, 1, 2
+INT_KINDS = {"wrap": INT_WRAP, "satu": INT_SAT_U, "sats": INT_SAT_S}
+
+
+def int_binop(op, k: int, kind, a, b) -> np.ndarray:
+    """Elementwise a op b on k-bit integer patterns (1 <= k <= 32): wrap
+    modulo 2^k, or saturate as unsigned / signed (see bfp_oracle.c)."""
+    a32 = np.ascontiguousarray(np.asarray(a).astype(np.uint32))
+    b32 = np.ascontiguousarray(np.asarray(b).astype(np.uint32))
+    if a32.shape != b32.shape:
+        raise ValueError("shape mismatch")
+    kd = INT_KINDS[kind] if isinstance(kind, str) else int(kind)
+    c = np.empty_like(a32)
+    if lib().oracle_int_binop(_op(op), k, kd, a32.ctypes.data, b32.ctypes.data, c.ctypes.data, a32.size) != 0:
+        raise ValueError("invalid oracle arguments")
+    return c
+
+
+def int_container_bytes(k: int) -> int:
+    return 1 if k <= 8 else (2 if k <= 16 else 4)
 
 
 def from_double(e: int, m: int, mode: int, v: float) -> int:

@@ -412,3 +412,48 @@ int oracle_unpack(int B, int cbytes, const uint32_t *planes, void *x, uint64_t n
     }
     return 0;
 }
+
+/* ---- bitslice integer vectors (Section 3, Figure 2; Section 6) ------------
+ * An element is a k-bit pattern, 1 <= k <= 32, read as an unsigned value
+ * (the pattern) or a signed one (two's complement).  The exact sum,
+ * difference or product of the two values is formed in 128-bit integers and
+ * mapped to k bits by the kind:
+ *   0 wrap: the exact result modulo 2^k (what the ripple adder of Figure 2
+ *     gives when its last carry is dropped; the same bits whether the
+ *     operands are read signed or unsigned);
+ *   1 unsigned saturation: operands unsigned, result clamped to [0, 2^k - 1];
+ *   2 signed saturation: operands signed, result clamped to
+ *     [-2^(k-1), 2^(k-1) - 1].
+ * Bits of a and b above bit k-1 are ignored. */
+static __int128 int_value(uint32_t x, int k, int is_signed) {
+    uint64_t p = (uint64_t)x & ((1ull << k) - 1);
+    if (is_signed && (p >> (k - 1)) & 1) return (__int128)p - ((__int128)1 << k);
+    return (__int128)p;
+}
+
+static uint32_t int_op(int op, int k, int kind, uint32_t a, uint32_t b) {
+    const int is_signed = kind == 2;
+    const __int128 x = int_value(a, k, is_signed), y = int_value(b, k, is_signed);
+    __int128 v = op == ORACLE_ADD ? x + y : (op == ORACLE_SUB ? x - y : x * y);
+    if (kind == 1) {
+        const __int128 hi = ((__int128)1 << k) - 1;
+        if (v < 0) v = 0;
+        if (v > hi) v = hi;
+    } else if (kind == 2) {
+        const __int128 lo = -((__int128)1 << (k - 1)), hi = ((__int128)1 << (k - 1)) - 1;
+        if (v < lo) v = lo;
+        if (v > hi) v = hi;
+    }
+    const __int128 mod = (__int128)1 << k;
+    __int128 r = v % mod;
+    if (r < 0) r += mod;
+    return (uint32_t)r;
+}
+
+/* c[i] = a[i] op b[i] for k-bit integers.  op: 0 add, 1 sub, 2 mul; kind as
+ * above.  Returns 0, or -1 for an invalid argument. */
+int oracle_int_binop(int op, int k, int kind, const uint32_t *a, const uint32_t *b, uint32_t *c, uint64_t n) {
+    if (k < 1 || k > 32 || op < 0 || op > 2 || kind < 0 || kind > 2) return -1;
+    for (uint64_t i = 0; i < n; i++) c[i] = int_op(op, k, kind, a[i], b[i]);
+    return 0;
+}

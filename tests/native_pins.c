@@ -96,3 +96,41 @@ void f32_chain2(int op1, int op2, int mode, const uint32_t *a, const uint32_t *b
     fesetround(old);
     _mm_setcsr(csr);
 }
+
+/* Saturating and wrapping 8- and 16-bit integer arithmetic with SSE2/SSE4.1
+ * instructions: add/sub by the saturating adds/subs instructions; products
+ * formed exactly in a wider lane and narrowed by the saturating packs
+ * (signed) or an unsigned minimum (unsigned).  op: 0 add, 1 sub, 2 mul;
+ * kind: 1 unsigned saturation, 2 signed saturation.  Inputs and outputs are
+ * held in uint32 arrays (low k bits). */
+void int_sat_sse(int op, int k, int kind, const uint32_t *a, const uint32_t *b, uint32_t *c, size_t n) {
+    for (size_t i = 0; i < n; i++) {
+        uint32_t r = 0;
+        if (k == 8) {
+            __m128i x = _mm_cvtsi32_si128((int)(a[i] & 0xFF)), y = _mm_cvtsi32_si128((int)(b[i] & 0xFF)), z;
+            if (op == 0) z = kind == 1 ? _mm_adds_epu8(x, y) : _mm_adds_epi8(x, y);
+            else if (op == 1) z = kind == 1 ? _mm_subs_epu8(x, y) : _mm_subs_epi8(x, y);
+            else if (kind == 1) {
+                __m128i p = _mm_mullo_epi16(_mm_cvtepu8_epi16(x), _mm_cvtepu8_epi16(y));
+                z = _mm_min_epu16(p, _mm_set1_epi16(0xFF));
+            } else {
+                __m128i p = _mm_mullo_epi16(_mm_cvtepi8_epi16(x), _mm_cvtepi8_epi16(y));
+                z = _mm_packs_epi16(p, p);
+            }
+            r = (uint32_t)_mm_cvtsi128_si32(z) & 0xFF;
+        } else {
+            __m128i x = _mm_cvtsi32_si128((int)(a[i] & 0xFFFF)), y = _mm_cvtsi32_si128((int)(b[i] & 0xFFFF)), z;
+            if (op == 0) z = kind == 1 ? _mm_adds_epu16(x, y) : _mm_adds_epi16(x, y);
+            else if (op == 1) z = kind == 1 ? _mm_subs_epu16(x, y) : _mm_subs_epi16(x, y);
+            else if (kind == 1) {
+                __m128i p = _mm_mullo_epi32(_mm_cvtepu16_epi32(x), _mm_cvtepu16_epi32(y));
+                z = _mm_min_epu32(p, _mm_set1_epi32(0xFFFF));
+            } else {
+                __m128i p = _mm_mullo_epi32(_mm_cvtepi16_epi32(x), _mm_cvtepi16_epi32(y));
+                z = _mm_packs_epi32(p, p);
+            }
+            r = (uint32_t)_mm_cvtsi128_si32(z) & 0xFFFF;
+        }
+        c[i] = r;
+    }
+}

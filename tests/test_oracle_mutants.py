@@ -118,3 +118,45 @@ def test_unmutated_copy_agrees(tmp_path):
     """The same harness finds no disagreement for the committed oracle."""
     L = _build(tmp_path, open(SRC).read(), "clean")
     assert not _disagrees(L)
+
+
+INT_MUTANTS = [
+    ("signed read as unsigned", "if (is_signed && (p >> (k - 1)) & 1)", "if (0 && (p >> (k - 1)) & 1)"),
+    ("unsigned floor not clamped", "if (v < 0) v = 0;", ""),
+    ("signed max off by one", "hi = ((__int128)1 << (k - 1)) - 1;", "hi = ((__int128)1 << (k - 1));"),
+    ("signed min off by one", "const __int128 lo = -((__int128)1 << (k - 1)),", "const __int128 lo = 1 - ((__int128)1 << (k - 1)),"),
+    ("negative remainder not lifted", "if (r < 0) r += mod;", ""),
+    ("sub as add", "(op == ORACLE_SUB ? x - y : x * y)", "(op == ORACLE_SUB ? x + y : x * y)"),
+    ("unsigned ceiling off by one", "const __int128 hi = ((__int128)1 << k) - 1;", "const __int128 hi = ((__int128)1 << k) - 2;"),
+]
+
+
+def _int_disagrees(L):
+    from tests.test_oracle_int import _table_search
+    L.oracle_int_binop.restype = ctypes.c_int
+    L.oracle_int_binop.argtypes = [ctypes.c_int] * 3 + [ctypes.c_void_p] * 3 + [ctypes.c_uint64]
+    for k in (1, 3, 4):
+        n = 1 << k
+        a = np.repeat(np.arange(n, dtype=np.uint32), n)
+        b = np.tile(np.arange(n, dtype=np.uint32), n)
+        c = np.empty_like(a)
+        for opi, op in enumerate(("add", "sub", "mul")):
+            for kd, kind in enumerate(("wrap", "satu", "sats")):
+                L.oracle_int_binop(opi, k, kd, a.ctypes.data, b.ctypes.data, c.ctypes.data, a.size)
+                for i in range(a.size):
+                    if int(c[i]) != _table_search(k, kind, op, int(a[i]), int(b[i])):
+                        return True
+    return False
+
+
+@pytest.mark.parametrize("name,old,new", INT_MUTANTS, ids=[m[0] for m in INT_MUTANTS])
+def test_int_mutant_is_caught(tmp_path, name, old, new):
+    text = open(SRC).read()
+    assert text.count(old) == 1, "mutation site not found: " + name
+    L = _build(tmp_path, text.replace(old, new), "mutant")
+    assert _int_disagrees(L), "planted mistake survived the pins: " + name
+
+
+def test_int_unmutated_copy_agrees(tmp_path):
+    L = _build(tmp_path, open(SRC).read(), "clean")
+    assert not _int_disagrees(L)
