@@ -20,6 +20,8 @@ Also printed in the same JSON line:
   div           division (Table 1, Div) on resident bitslice vectors of the
                 same size and formats, the launch table's configuration:
                 elements/s and its bitwise VALU rate against peak;
+  int           k-bit integer vectors (k = 5, 9, 13), 2^26 elements: wrapping
+                add and mul, signed-saturating mul;
   chain         d = a*b + c on the same vectors: one two-op chain kernel
                 (intermediate in registers, 4 vectors through HBM) against
                 the two separate launches (6 vectors);
@@ -58,6 +60,7 @@ def parse():
     ap.add_argument("--no-serving", action="store_true")
     ap.add_argument("--no-div", action="store_true")
     ap.add_argument("--no-chain", action="store_true")
+    ap.add_argument("--no-int", action="store_true")
     ap.add_argument("--div-reps", type=int, default=10)
     ap.add_argument("--serving-requests", type=int, default=20000)
     return ap.parse_args()
@@ -209,6 +212,36 @@ def bench_chain(torch, bfp, dev, n, reps):
             "valu_frac": G * n / 32 / (us * 1e-6) / VALU_PEAK,
             "device_kernel": "bfp::k_chain2<%d, %d, false, 1, 0, 1>" % (e, m)}
         del pa, pb, pc, pd, pt
+    return out
+
+
+def bench_int(torch, bfp, dev, n, reps):
+    """k-bit integer ops on resident bitslice vectors of n elements, timed
+    over `reps` back-to-back launches between two events."""
+    import numpy as np
+    s = torch.cuda.current_stream()
+    out = {}
+    for k in (5, 9, 13):
+        rng = np.random.default_rng(k)
+        dt = np.uint8 if k <= 8 else np.uint16
+        pa, pb = (bfp.int_pack(k, torch.from_numpy(rng.integers(0, 1 << k, n, dtype=np.uint64).astype(dt)).to(dev))
+                  for _ in range(2))
+        pc = bfp.int_empty_bitslice(k, n, dev)
+        for op, kind in (("add", "wrap"), ("mul", "wrap"), ("mul", "sats")):
+            for _ in range(2):
+                bfp.bfp_int_binop(op, k, kind, pa, pb, pc, n, s)
+            ev0, ev1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+            ev0.record(s)
+            for _ in range(reps):
+                bfp.bfp_int_binop(op, k, kind, pa, pb, pc, n, s)
+            ev1.record(s)
+            torch.cuda.synchronize()
+            us = ev0.elapsed_time(ev1) * 1e3 / reps
+            nbytes = 3 * k / 8 * n
+            out["%s_%s_k%d" % (op, kind, k)] = {
+                "us": us, "elements_per_s": n / (us * 1e-6), "GB/s": nbytes / (us * 1e-6) / 1e9,
+                "hbm_frac": nbytes / (us * 1e-6) / HBM_PEAK}
+        del pa, pb, pc
     return out
 
 
@@ -416,6 +449,8 @@ def main():
         res["div"] = bench_div(torch, bfp, dev, n, args.div_reps)
     if not args.no_chain:
         res["chain"] = bench_chain(torch, bfp, dev, n, args.div_reps)
+    if not args.no_int:
+        res["int"] = bench_int(torch, bfp, dev, n, args.div_reps)
     if not args.no_cpu_baseline:
         res["cpu_baseline"] = cpu_baseline()
     print(json.dumps(res), flush=True)

@@ -166,6 +166,32 @@ bfp_status bfp_axpy(bfp_format f, uint32_t alpha, const void* x, const void* y, 
 bfp_status bfp_binop_std(int op, bfp_format f, const void* a, const void* b, void* c, uint64_t n,
                          void* stream);
 
+/* ---- k-bit integer vectors (Section 3, Figure 2) ------------------------------ */
+/* Vectors of k-bit integers, 1 <= k <= 32, in the same plane-major bitslice
+ * layout with k planes (plane i = bit i).  Standard containers are
+ * bfp_int_container_bytes(k) = 1, 2 or 4 bytes holding the k-bit pattern:
+ * bits above k-1 are ignored on input and zero on output (a signed value is
+ * its k-bit two's complement pattern).  Kinds: */
+#define BFP_INT_WRAP 0  /* result modulo 2^k (same bits signed or unsigned) */
+#define BFP_INT_SAT_U 1 /* unsigned operands, result clamped to [0, 2^k - 1] */
+#define BFP_INT_SAT_S 2 /* signed operands, result clamped to [-2^(k-1), 2^(k-1) - 1] */
+
+/* 1, 2 or 4; 0 if k is not compiled. */
+size_t bfp_int_container_bytes(int k);
+/* k * G_pad * 4; 0 if k is not compiled. */
+size_t bfp_int_bitslice_bytes(int k, uint64_t n);
+/* Standard <-> bitslice, with the rules of bfp_pack / bfp_unpack. */
+bfp_status bfp_int_pack(int k, const void* std_in, void* bs_out, uint64_t n, void* stream);
+bfp_status bfp_int_unpack(int k, const void* bs_in, void* std_out, uint64_t n, void* stream);
+/* c = a op b elementwise on k-bit bitslice vectors, op in {BFP_ADD, BFP_SUB,
+ * BFP_MUL} (the exact sum, difference or product mapped to k bits by the
+ * kind).  a, b, c: device bitslice vectors of n elements (same G_pad); c may
+ * be the same buffer as a or b; partial overlaps are not allowed; padding
+ * bits of c are zero.  Errors: BFP_E_OP, BFP_E_FORMAT (k or kind), as
+ * bfp_binop otherwise. */
+bfp_status bfp_int_binop(int op, int k, int kind, const void* a, const void* b, void* c, uint64_t n,
+                         void* stream);
+
 /* ---- launch configuration (autotuning) ------------------------------------ */
 
 /* One kernel variant: words per lane per plane (1: W = 32 elements,

@@ -98,6 +98,14 @@ _SIGS = {
                                   ctypes.c_void_p, ctypes.c_void_p, ctypes.c_uint64, ctypes.c_void_p]),
     "bfp_axpy": (ctypes.c_int, [bfp_format, ctypes.c_uint32, ctypes.c_void_p, ctypes.c_void_p, ctypes.c_void_p,
                                 ctypes.c_uint64, ctypes.c_void_p]),
+    "bfp_int_container_bytes": (ctypes.c_size_t, [ctypes.c_int]),
+    "bfp_int_bitslice_bytes": (ctypes.c_size_t, [ctypes.c_int, ctypes.c_uint64]),
+    "bfp_int_pack": (ctypes.c_int, [ctypes.c_int, ctypes.c_void_p, ctypes.c_void_p, ctypes.c_uint64,
+                                    ctypes.c_void_p]),
+    "bfp_int_unpack": (ctypes.c_int, [ctypes.c_int, ctypes.c_void_p, ctypes.c_void_p, ctypes.c_uint64,
+                                      ctypes.c_void_p]),
+    "bfp_int_binop": (ctypes.c_int, [ctypes.c_int, ctypes.c_int, ctypes.c_int, ctypes.c_void_p, ctypes.c_void_p,
+                                     ctypes.c_void_p, ctypes.c_uint64, ctypes.c_void_p]),
     "bfp_binop_std": (ctypes.c_int, [ctypes.c_int, bfp_format, ctypes.c_void_p, ctypes.c_void_p,
                                      ctypes.c_void_p, ctypes.c_uint64, ctypes.c_void_p]),
     "bfp_launch_get": (ctypes.c_int, [ctypes.c_int, bfp_format, ctypes.POINTER(bfp_launch)]),
@@ -252,6 +260,58 @@ def bfp_chain2(op1, op2, f, a, b, c, d, n: int, stream=None):
 
 def bfp_axpy(f, alpha: int, x, y, d, n: int, stream=None):
     _check(lib().bfp_axpy(f, int(alpha), _ptr(x), _ptr(y), _ptr(d), n, _stream(stream)), "bfp_axpy")
+
+
+INT_KINDS = {"wrap": 0, "satu": 1, "sats": 2}
+
+
+def _kind(kind) -> int:
+    return INT_KINDS[kind] if isinstance(kind, str) else int(kind)
+
+
+def bfp_int_container_bytes(k: int) -> int:
+    return int(lib().bfp_int_container_bytes(k))
+
+
+def bfp_int_bitslice_bytes(k: int, n: int) -> int:
+    return int(lib().bfp_int_bitslice_bytes(k, n))
+
+
+def bfp_int_pack(k: int, std, bs, n: int, stream=None):
+    _check(lib().bfp_int_pack(k, _ptr(std), _ptr(bs), n, _stream(stream)), "bfp_int_pack")
+
+
+def bfp_int_unpack(k: int, bs, std, n: int, stream=None):
+    _check(lib().bfp_int_unpack(k, _ptr(bs), _ptr(std), n, _stream(stream)), "bfp_int_unpack")
+
+
+def bfp_int_binop(op, k: int, kind, a, b, c, n: int, stream=None):
+    _check(lib().bfp_int_binop(_op(op), k, _kind(kind), _ptr(a), _ptr(b), _ptr(c), n, _stream(stream)),
+           "bfp_int_binop")
+
+
+def int_container_dtype(k: int):
+    import torch
+    return {1: torch.uint8, 2: torch.uint16, 4: torch.uint32}[1 if k <= 8 else (2 if k <= 16 else 4)]
+
+
+def int_empty_bitslice(k: int, n: int, device="cuda"):
+    """Uninitialised k-bit integer bitslice vector: (k, G_pad) uint32 planes."""
+    import torch
+    return torch.empty((k, bfp_plane_stride_words(n)), dtype=torch.uint32, device=device)
+
+
+def int_pack(k: int, std, stream=None):
+    out = int_empty_bitslice(k, std.numel(), std.device)
+    bfp_int_pack(k, std, out, std.numel(), stream)
+    return out
+
+
+def int_unpack(k: int, bs, n: int, stream=None):
+    import torch
+    out = torch.empty(n, dtype=int_container_dtype(k), device=bs.device)
+    bfp_int_unpack(k, bs, out, n, stream)
+    return out
 
 
 def bfp_binop_std(op, f, a, b, c, n: int, stream=None):

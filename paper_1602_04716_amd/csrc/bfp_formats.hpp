@@ -12,6 +12,14 @@
 #define BFP_FOR_EACH_FORMAT(X) \
   BFP_FOR_EACH_M(X, 3) BFP_FOR_EACH_M(X, 4) BFP_FOR_EACH_M(X, 5) BFP_FOR_EACH_M(X, 6) BFP_FOR_EACH_M(X, 8)
 
+// X(k) for every integer width of the bitslice integer vectors, 1 <= k <= 32
+#define BFP_FOR_EACH_INT_K_1_8(X) X(1) X(2) X(3) X(4) X(5) X(6) X(7) X(8)
+#define BFP_FOR_EACH_INT_K_9_16(X) X(9) X(10) X(11) X(12) X(13) X(14) X(15) X(16)
+#define BFP_FOR_EACH_INT_K_17_24(X) X(17) X(18) X(19) X(20) X(21) X(22) X(23) X(24)
+#define BFP_FOR_EACH_INT_K_25_32(X) X(25) X(26) X(27) X(28) X(29) X(30) X(31) X(32)
+#define BFP_FOR_EACH_INT_K(X) \
+  BFP_FOR_EACH_INT_K_1_8(X) BFP_FOR_EACH_INT_K_9_16(X) BFP_FOR_EACH_INT_K_17_24(X) BFP_FOR_EACH_INT_K_25_32(X)
+
 namespace bfp {
 constexpr int kMaxE = 8;
 constexpr int kMaxM = 23;

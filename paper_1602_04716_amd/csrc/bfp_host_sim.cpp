@@ -100,6 +100,81 @@ void bfpsim_ripple_add13(const uint32_t* a, const uint32_t* b, uint32_t* r) {
 
 }  // extern "C"
 
+#include "bfp_int_circuits.hpp"
+
+namespace {
+template <int K, int OP, int KIND, class W>
+void run_int(const uint32_t* a, const uint32_t* b, uint32_t* c, uint64_t n) {
+  constexpr int WB = kBits<W>;
+  for (uint64_t base = 0; base < n; base += WB) {
+    W x[K], y[K], z[K];
+    for (int k = 0; k < K; ++k) {
+      W wx = 0, wy = 0;
+      for (int j = 0; j < WB && base + j < n; ++j) {
+        wx |= (W)((a[base + j] >> k) & 1u) << j;
+        wy |= (W)((b[base + j] >> k) & 1u) << j;
+      }
+      x[k] = wx;
+      y[k] = wy;
+    }
+    bfp::int_circuit<K, OP, KIND, W>(x, y, z);
+    for (int j = 0; j < WB && base + j < n; ++j) {
+      uint32_t v = 0;
+      for (int k = 0; k < K; ++k) v |= (uint32_t)((z[k] >> j) & 1u) << k;
+      c[base + j] = v;
+    }
+  }
+}
+
+template <int K, int OP, int KIND>
+long int_gates() {
+  bfp::CountW x[K], y[K], z[K];
+  bfp::CountW::counter() = 0;
+  bfp::int_circuit<K, OP, KIND, bfp::CountW>(x, y, z);
+  return (long)bfp::CountW::counter();
+}
+}  // namespace
+
+extern "C" {
+// k-bit integer op (0 add, 1 sub, 2 mul), kind 0 wrap / 1 unsigned / 2 signed
+// saturation, on 32- or 64-bit host words.  Returns 0, or -1 for bad k/op/kind.
+int bfpsim_int_binop(int op, int k, int kind, int wbits, const uint32_t* a, const uint32_t* b, uint32_t* c,
+                     uint64_t n) {
+  if (op < 0 || op > 2 || kind < 0 || kind > 2) return -1;
+#define BFP_SIM_INT_OPK(KK, OP, KD)                                      \
+  if (op == OP && kind == KD) {                                          \
+    if (wbits == 64) run_int<KK, OP, KD, uint64_t>(a, b, c, n);          \
+    else run_int<KK, OP, KD, uint32_t>(a, b, c, n);                      \
+    return 0;                                                            \
+  }
+#define BFP_SIM_INT_CASE(KK)                                                                          \
+  if (k == KK) {                                                                                      \
+    BFP_SIM_INT_OPK(KK, 0, 0) BFP_SIM_INT_OPK(KK, 0, 1) BFP_SIM_INT_OPK(KK, 0, 2)                    \
+    BFP_SIM_INT_OPK(KK, 1, 0) BFP_SIM_INT_OPK(KK, 1, 1) BFP_SIM_INT_OPK(KK, 1, 2)                    \
+    BFP_SIM_INT_OPK(KK, 2, 0) BFP_SIM_INT_OPK(KK, 2, 1) BFP_SIM_INT_OPK(KK, 2, 2)                    \
+  }
+  BFP_FOR_EACH_INT_K(BFP_SIM_INT_CASE)
+#undef BFP_SIM_INT_CASE
+#undef BFP_SIM_INT_OPK
+  return -1;
+}
+
+long bfpsim_int_gate_count(int op, int k, int kind) {
+#define BFP_GC_INT_OPK(KK, OP, KD) \
+  if (op == OP && kind == KD) return int_gates<KK, OP, KD>();
+#define BFP_GC_INT_CASE(KK)                                                                 \
+  if (k == KK) {                                                                            \
+    BFP_GC_INT_OPK(KK, 0, 0) BFP_GC_INT_OPK(KK, 0, 1) BFP_GC_INT_OPK(KK, 0, 2)             \
+    BFP_GC_INT_OPK(KK, 1, 0) BFP_GC_INT_OPK(KK, 1, 1) BFP_GC_INT_OPK(KK, 1, 2)             \
+    BFP_GC_INT_OPK(KK, 2, 0) BFP_GC_INT_OPK(KK, 2, 1) BFP_GC_INT_OPK(KK, 2, 2)             \
+  }
+  BFP_FOR_EACH_INT_K(BFP_GC_INT_CASE)
+#undef BFP_GC_INT_CASE
+#undef BFP_GC_INT_OPK
+  return -1;
+}
+}  // extern "C"
+
 #include "bfp_transpose.hpp"
 
 extern "C" {

@@ -8,6 +8,7 @@
 
 #include "bfp.h"
 #include "bfp_formats.hpp"
+#include "bfp_int_kernels.hpp"
 #include "bfp_kernels.hpp"
 
 namespace bfp {
@@ -194,13 +195,20 @@ size_t bfp_bitslice_bytes(bfp_format f, uint64_t n) {
   return (size_t)bits_of(f) * gpad_of(n) * 4u;
 }
 
-bfp_status bfp_pack(bfp_format f, const void* std_in, void* bs_out, uint64_t n, void* stream) {
-  if (!format_ok(f)) return BFP_E_FORMAT;
+}  // extern "C"
+
+namespace bfp {
+namespace {
+
+int cbytes_of_bits(int B) { return B <= 8 ? 1 : (B <= 16 ? 2 : 4); }
+
+// Standard containers <-> B planes, 1 <= B <= 32 (format checked by the caller).
+bfp_status pack_impl(int B, const void* std_in, void* bs_out, uint64_t n, void* stream) {
   if (n == 0) return BFP_OK;
   if (n > kMaxN) return BFP_E_ARG;
   if (!std_in || !bs_out) return BFP_E_NULL;
   if (!aligned16(std_in) || !aligned16(bs_out)) return BFP_E_ALIGN;
-  const int C = cbytes_of(f), B = bits_of(f);
+  const int C = cbytes_of_bits(B);
   const uint64_t gpad = gpad_of(n);
   if (overlap(std_in, n * C, bs_out, (size_t)B * gpad * 4)) return BFP_E_ALIAS;
   const int block = 256;
@@ -209,13 +217,12 @@ bfp_status bfp_pack(bfp_format f, const void* std_in, void* bs_out, uint64_t n, 
   return hip_status(L(std_in, bs_out, n, gpad, B, grid, block, (hipStream_t)stream));
 }
 
-bfp_status bfp_unpack(bfp_format f, const void* bs_in, void* std_out, uint64_t n, void* stream) {
-  if (!format_ok(f)) return BFP_E_FORMAT;
+bfp_status unpack_impl(int B, const void* bs_in, void* std_out, uint64_t n, void* stream) {
   if (n == 0) return BFP_OK;
   if (n > kMaxN) return BFP_E_ARG;
   if (!bs_in || !std_out) return BFP_E_NULL;
   if (!aligned16(bs_in) || !aligned16(std_out)) return BFP_E_ALIGN;
-  const int C = cbytes_of(f), B = bits_of(f);
+  const int C = cbytes_of_bits(B);
   const uint64_t gpad = gpad_of(n);
   if (overlap(std_out, n * C, bs_in, (size_t)B * gpad * 4)) return BFP_E_ALIAS;
   const int block = 256;
@@ -223,6 +230,59 @@ bfp_status bfp_unpack(bfp_format f, const void* bs_in, void* std_out, uint64_t n
   const unsigned grid = grid_for(tiles * 64, block, 0);
   PackLauncher L = C == 1 ? launch_unpack<1> : (C == 2 ? launch_unpack<2> : launch_unpack<4>);
   return hip_status(L(bs_in, std_out, n, gpad, B, grid, block, (hipStream_t)stream));
+}
+
+bool int_bits_ok(int k) { return k >= 1 && k <= kMaxIntBits && int_registry().op[k][0][0] != nullptr; }
+
+}  // namespace
+
+IntRegistry& int_registry() {
+  static IntRegistry r;
+  return r;
+}
+
+}  // namespace bfp
+
+extern "C" {
+
+bfp_status bfp_pack(bfp_format f, const void* std_in, void* bs_out, uint64_t n, void* stream) {
+  if (!format_ok(f)) return BFP_E_FORMAT;
+  return pack_impl(bits_of(f), std_in, bs_out, n, stream);
+}
+
+bfp_status bfp_unpack(bfp_format f, const void* bs_in, void* std_out, uint64_t n, void* stream) {
+  if (!format_ok(f)) return BFP_E_FORMAT;
+  return unpack_impl(bits_of(f), bs_in, std_out, n, stream);
+}
+
+size_t bfp_int_container_bytes(int k) { return int_bits_ok(k) ? (size_t)cbytes_of_bits(k) : 0; }
+
+size_t bfp_int_bitslice_bytes(int k, uint64_t n) { return int_bits_ok(k) ? (size_t)k * gpad_of(n) * 4u : 0; }
+
+bfp_status bfp_int_pack(int k, const void* std_in, void* bs_out, uint64_t n, void* stream) {
+  if (!int_bits_ok(k)) return BFP_E_FORMAT;
+  return pack_impl(k, std_in, bs_out, n, stream);
+}
+
+bfp_status bfp_int_unpack(int k, const void* bs_in, void* std_out, uint64_t n, void* stream) {
+  if (!int_bits_ok(k)) return BFP_E_FORMAT;
+  return unpack_impl(k, bs_in, std_out, n, stream);
+}
+
+bfp_status bfp_int_binop(int op, int k, int kind, const void* a, const void* b, void* c, uint64_t n,
+                         void* stream) {
+  if (op != BFP_ADD && op != BFP_SUB && op != BFP_MUL) return BFP_E_OP;
+  if (!int_bits_ok(k) || kind < BFP_INT_WRAP || kind > BFP_INT_SAT_S) return BFP_E_FORMAT;
+  if (n == 0) return BFP_OK;
+  if (n > kMaxN) return BFP_E_ARG;
+  if (!a || !b || !c) return BFP_E_NULL;
+  if (!aligned16(a) || !aligned16(b) || !aligned16(c)) return BFP_E_ALIGN;
+  const uint64_t gpad = gpad_of(n);
+  const size_t bytes = (size_t)k * gpad * 4;
+  if ((c != a && overlap(c, bytes, a, bytes)) || (c != b && overlap(c, bytes, b, bytes))) return BFP_E_ALIAS;
+  IntLauncher L = int_registry().op[k][op][kind];
+  if (!L) return BFP_E_FORMAT;
+  return hip_status(L(a, b, c, gpad, 256u, (hipStream_t)stream));
 }
 
 bfp_status bfp_binop(int op, bfp_format f, const void* a, const void* b, void* c, uint64_t n, void* stream) {

@@ -85,6 +85,18 @@ def test_argument_errors_before_any_device_work():
     assert L.bfp_chain2(2, 0, f, 0, 0, 0, 0, 0, None) == 0
     assert L.bfp_axpy(f, 0x3C00, 0, 32, 48, 1, None) == -2
     assert L.bfp_axpy(bfp.fmt(7, 4), 0x3C00, 16, 32, 48, 1, None) == -1
+    assert L.bfp_int_binop(3, 8, 0, 16, 32, 48, 1, None) == -4             # no integer division
+    assert L.bfp_int_binop(0, 0, 0, 16, 32, 48, 1, None) == -1             # k
+    assert L.bfp_int_binop(0, 33, 0, 16, 32, 48, 1, None) == -1
+    assert L.bfp_int_binop(0, 8, 3, 16, 32, 48, 1, None) == -1             # kind
+    assert L.bfp_int_binop(0, 8, 1, 16, 0, 48, 1, None) == -2
+    assert L.bfp_int_binop(0, 8, 1, 16, 40, 48, 1, None) == -3
+    assert L.bfp_int_binop(2, 8, 2, 4096, 1 << 20, 4096 + 16, 100, None) == -7
+    assert L.bfp_int_binop(2, 8, 2, 0, 0, 0, 0, None) == 0
+    assert L.bfp_int_pack(33, 16, 4096, 10, None) == -1
+    assert L.bfp_int_unpack(5, 16, 32, 1 << 40, None) == -6
+    assert bfp.bfp_int_container_bytes(9) == 2 and bfp.bfp_int_container_bytes(0) == 0
+    assert bfp.bfp_int_bitslice_bytes(13, 70000) == 13 * bfp.bfp_plane_stride_words(70000) * 4
     assert bfp.bfp_status_string(-5).startswith("HIP")
 
 

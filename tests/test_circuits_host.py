@@ -26,6 +26,9 @@ def sim():
     L.bfpsim_gate_count.argtypes = [ctypes.c_int] * 4
     L.bfpsim_ripple_add13.argtypes = [ctypes.c_void_p] * 3
     L.bfpsim_transpose.argtypes = [ctypes.c_int, ctypes.c_int, ctypes.c_void_p, ctypes.c_void_p]
+    L.bfpsim_int_binop.argtypes = [ctypes.c_int] * 4 + [ctypes.c_void_p] * 3 + [ctypes.c_uint64]
+    L.bfpsim_int_gate_count.restype = ctypes.c_long
+    L.bfpsim_int_gate_count.argtypes = [ctypes.c_int] * 3
     return L
 
 
@@ -145,3 +148,51 @@ def test_transposes(sim, C):
         back = np.zeros(8 * C, dtype=np.uint32)
         sim.bfpsim_transpose(C, 1, out.ctypes.data, back.ctypes.data)
         assert np.array_equal(back, inw)
+
+
+def _int_operands(k, n, seed):
+    rng = np.random.default_rng(seed)
+    if k <= 6:
+        a, b = inputs.exhaustive_pairs(k)
+        return a.astype(np.uint32), b.astype(np.uint32)
+    mask = np.uint64((1 << k) - 1)
+    a = rng.integers(0, 1 << k, n, dtype=np.uint64)
+    b = rng.integers(0, 1 << k, n, dtype=np.uint64)
+    q = n // 4
+    neg = rng.integers(0, 2, (2, q)).astype(np.uint64) * mask
+    a[:q] = rng.integers(0, 1 << (k // 2), q).astype(np.uint64) ^ neg[0]
+    b[:q] = rng.integers(0, 1 << (k // 2), q).astype(np.uint64) ^ neg[1]
+    return (a & mask).astype(np.uint32), (b & mask).astype(np.uint32)
+
+
+@pytest.mark.parametrize("k", list(range(1, 33)))
+def test_int_circuits(sim, oracle_lib, k):
+    """k-bit integer add/sub/mul, wrapping and both saturations, against the
+    oracle (all pairs for k <= 6), 32- and 64-bit words identical."""
+    a, b = _int_operands(k, 12000, k)
+    for op in range(3):
+        for kind in range(3):
+            want = oracle_lib.int_binop(op, k, kind, a, b)
+            for w in (32, 64):
+                c = np.empty_like(a)
+                assert sim.bfpsim_int_binop(op, k, kind, w, a.ctypes.data, b.ctypes.data, c.ctypes.data, a.size) == 0
+                bad = np.flatnonzero(c != want)
+                assert bad.size == 0, (op, kind, w, hex(a[bad[0]]), hex(b[bad[0]]), hex(c[bad[0]]), hex(want[bad[0]]))
+
+
+def test_int_gate_counts():
+    """Figure 2's adder costs one sum and one carry per bit: 2k - 1 gates
+    with 3-input gates (the listing spends five bitwise operations per bit);
+    the wrapping multiplier grows as ~1.5 k^2, the full-width (saturating)
+    ones as ~3 k^2."""
+    import ctypes as ct
+    L = ct.CDLL(build.HOSTSIM)
+    L.bfpsim_int_gate_count.restype = ct.c_long
+    L.bfpsim_int_gate_count.argtypes = [ct.c_int] * 3
+    for k in range(2, 33):
+        assert L.bfpsim_int_gate_count(0, k, 0) == 2 * k - 1
+    ks = np.arange(4, 33, dtype=float)
+    for kind, lo, hi in ((0, 1.2, 1.8), (1, 2.5, 3.5), (2, 2.5, 3.5)):
+        g = np.array([L.bfpsim_int_gate_count(2, int(k), kind) for k in ks], dtype=float)
+        c = np.linalg.lstsq(np.stack([np.ones_like(ks), ks, ks ** 2], axis=1), g, rcond=None)[0]
+        assert lo < c[2] < hi, (kind, c)
