@@ -51,10 +51,12 @@ def lib():
         vp = ctypes.c_void_p
         L.oracle_op1.restype = u32
         L.oracle_op1.argtypes = [i32, i32, i32, i32, u32, u32]
-        L.oracle_from_double.restype = u32
+        L.oracle_op1_64.restype = u64
+        L.oracle_op1_64.argtypes = [i32, i32, i32, i32, u64, u64]
+        L.oracle_from_double.restype = u64
         L.oracle_from_double.argtypes = [i32, i32, i32, ctypes.c_double]
-        L.oracle_binop.restype = i32
-        L.oracle_binop.argtypes = [i32, i32, i32, i32, vp, vp, vp, u64, i32]
+        L.oracle_binop64.restype = i32
+        L.oracle_binop64.argtypes = [i32, i32, i32, i32, vp, vp, vp, u64, i32]
         L.oracle_pack.restype = i32
         L.oracle_pack.argtypes = [i32, i32, vp, vp, u64, u64]
         L.oracle_unpack.restype = i32
@@ -71,24 +73,25 @@ def _op(op) -> int:
 
 def op1(op, e: int, m: int, mode: int, a: int, b: int) -> int:
     """One element: pattern of a op b."""
-    r = lib().oracle_op1(_op(op), e, m, mode, a, b)
-    if r == 0xFFFFFFFF:
+    r = lib().oracle_op1_64(_op(op), e, m, mode, a, b)
+    if r == 0xFFFFFFFFFFFFFFFF:
         raise ValueError("invalid oracle arguments")
     return int(r)
 
 
 def binop(op, e: int, m: int, mode: int, a, b, nthreads: int = 1) -> np.ndarray:
-    """Elementwise a op b over arrays of patterns (any unsigned container)."""
-    a32 = np.ascontiguousarray(np.asarray(a).astype(np.uint32))
-    b32 = np.ascontiguousarray(np.asarray(b).astype(np.uint32))
-    if a32.shape != b32.shape:
+    """Elementwise a op b over arrays of patterns (any unsigned container).
+    Returns uint32 patterns for formats of at most 32 bits, else uint64."""
+    a64 = np.ascontiguousarray(np.asarray(a).astype(np.uint64))
+    b64 = np.ascontiguousarray(np.asarray(b).astype(np.uint64))
+    if a64.shape != b64.shape:
         raise ValueError("shape mismatch")
-    c = np.empty_like(a32)
-    rc = lib().oracle_binop(_op(op), e, m, mode, a32.ctypes.data, b32.ctypes.data,
-                            c.ctypes.data, a32.size, nthreads)
+    c = np.empty_like(a64)
+    rc = lib().oracle_binop64(_op(op), e, m, mode, a64.ctypes.data, b64.ctypes.data,
+                              c.ctypes.data, a64.size, nthreads)
     if rc != 0:
         raise ValueError("invalid oracle arguments")
-    return c
+    return c.astype(np.uint32) if 1 + e + m <= 32 else c
 
 
 def chain2(op1, op2, e: int, m: int, mode: int, a, b, c, nthreads: int = 1) -> np.ndarray:
@@ -101,7 +104,7 @@ def chain2(op1, op2, e: int, m: int, mode: int, a, b, c, nthreads: int = 1) -> n
 def axpy(e: int, m: int, mode: int, alpha: int, x, y, nthreads: int = 1) -> np.ndarray:
     """alpha * x + y with the pattern alpha broadcast (bits above 1+e+m ignored)."""
     xs = np.asarray(x)
-    al = np.full(xs.shape, int(alpha) & ((1 << (1 + e + m)) - 1), dtype=np.uint32)
+    al = np.full(xs.shape, int(alpha) & ((1 << (1 + e + m)) - 1), dtype=np.uint64)
     return chain2("mul", "add", e, m, mode, al, xs, y, nthreads)
 
 
@@ -133,7 +136,7 @@ def from_double(e: int, m: int, mode: int, v: float) -> int:
 
 def container_bytes(e: int, m: int) -> int:
     B = 1 + e + m
-    return 1 if B <= 8 else (2 if B <= 16 else 4)
+    return 1 if B <= 8 else (2 if B <= 16 else (4 if B <= 32 else 8))
 
 
 def plane_stride_words(n: int) -> int:
@@ -146,7 +149,7 @@ def pack(e: int, m: int, x, gpad: int | None = None) -> np.ndarray:
     """Standard containers -> bitslice planes, shape (B, gpad) uint32."""
     B = 1 + e + m
     c = container_bytes(e, m)
-    dt = {1: np.uint8, 2: np.uint16, 4: np.uint32}[c]
+    dt = {1: np.uint8, 2: np.uint16, 4: np.uint32, 8: np.uint64}[c]
     xs = np.ascontiguousarray(np.asarray(x).astype(dt))
     n = xs.size
     gpad = plane_stride_words(n) if gpad is None else gpad
@@ -160,7 +163,7 @@ def unpack(e: int, m: int, planes, n: int) -> np.ndarray:
     """Bitslice planes (B, gpad) -> standard containers (uint8/16/32)."""
     B = 1 + e + m
     c = container_bytes(e, m)
-    dt = {1: np.uint8, 2: np.uint16, 4: np.uint32}[c]
+    dt = {1: np.uint8, 2: np.uint16, 4: np.uint32, 8: np.uint64}[c]
     p = np.ascontiguousarray(np.asarray(planes, dtype=np.uint32))
     if p.shape[0] != B:
         raise ValueError("plane count mismatch")

@@ -17,9 +17,11 @@
  * NaN output bits) follows IEEE 754-2008 binary interchange semantics
  * generalised to (e, m); each such reading is listed in the design notes.
  *
- * Wide integers: exact sums need at most 2^e - 3 + m + 2 <= 278 bits for
- * e <= 8, m <= 23, so a fixed 384-bit unsigned integer (six 64-bit limbs,
- * least significant first) is enough; products need at most 48 bits.
+ * Patterns are held in 64-bit words (1 + e + m <= 64, e <= 11, m <= 52).
+ * Wide integers: an exact sum needs at most 2^e - 3 + m + 2 <= 2100 bits
+ * (e <= 11, m <= 52), so a fixed 2304-bit unsigned integer (36 64-bit limbs,
+ * least significant first) is enough; products need at most 106 bits and
+ * the scaled quotient at most 164.
  */
 #include <stdint.h>
 #include <stdlib.h>
@@ -34,36 +36,51 @@
 #define ORACLE_DIV 3
 
 /* ------------------------------------------------------------------------ */
-/* 384-bit unsigned integers                                                 */
+/* 2304-bit unsigned integers                                                */
 /* ------------------------------------------------------------------------ */
-#define NLIMB 6
-typedef struct { uint64_t w[NLIMB]; } big;
+#define NLIMB 36
+/* Limbs [0, n) hold the value; limbs at and above n are zero by definition
+ * and are never read (limb() supplies the zeros), so small formats touch
+ * only the few limbs their values need. */
+typedef struct { int n; uint64_t w[NLIMB]; } big;
+
+static uint64_t limb(const big *a, int i) { return i < a->n ? a->w[i] : 0; }
+static int imax(int a, int b) { return a > b ? a : b; }
+static int imin(int a, int b) { return a < b ? a : b; }
 
 static big big_from_u64(uint64_t v) {
     big r;
-    memset(&r, 0, sizeof r);
+    r.n = 1;
     r.w[0] = v;
     return r;
 }
 
+static big big_from_u128(unsigned __int128 v) {
+    big r;
+    r.n = 2;
+    r.w[0] = (uint64_t)v;
+    r.w[1] = (uint64_t)(v >> 64);
+    return r;
+}
+
 static int big_cmp(const big *a, const big *b) {
-    for (int i = NLIMB - 1; i >= 0; i--) {
-        if (a->w[i] > b->w[i]) return 1;
-        if (a->w[i] < b->w[i]) return -1;
+    for (int i = imax(a->n, b->n) - 1; i >= 0; i--) {
+        uint64_t x = limb(a, i), y = limb(b, i);
+        if (x > y) return 1;
+        if (x < y) return -1;
     }
     return 0;
 }
 
-/* a << s, s < 384; the operands used here never overflow 384 bits. */
+/* a << s; the operands used here never overflow 2304 bits. */
 static big big_shl(const big *a, int s) {
     big r;
-    memset(&r, 0, sizeof r);
-    int limb = s / 64, bit = s % 64;
-    for (int i = NLIMB - 1; i >= 0; i--) {
-        int src = i - limb;
-        if (src < 0) continue;
-        uint64_t v = a->w[src] << bit;
-        if (bit && src - 1 >= 0) v |= a->w[src - 1] >> (64 - bit);
+    int lw = s / 64, bit = s % 64;
+    r.n = imin(NLIMB, a->n + lw + 1);
+    for (int i = 0; i < r.n; i++) {
+        int src = i - lw;
+        uint64_t v = src >= 0 ? limb(a, src) << bit : 0;
+        if (bit && src - 1 >= 0) v |= limb(a, src - 1) >> (64 - bit);
         r.w[i] = v;
     }
     return r;
@@ -72,13 +89,12 @@ static big big_shl(const big *a, int s) {
 /* a >> s */
 static big big_shr(const big *a, int s) {
     big r;
-    memset(&r, 0, sizeof r);
-    int limb = s / 64, bit = s % 64;
-    for (int i = 0; i < NLIMB; i++) {
-        int src = i + limb;
-        if (src >= NLIMB) continue;
-        uint64_t v = a->w[src] >> bit;
-        if (bit && src + 1 < NLIMB) v |= a->w[src + 1] << (64 - bit);
+    int lw = s / 64, bit = s % 64;
+    r.n = imax(1, a->n - lw);
+    for (int i = 0; i < r.n; i++) {
+        int src = i + lw;
+        uint64_t v = limb(a, src) >> bit;
+        if (bit) v |= limb(a, src + 1) << (64 - bit);
         r.w[i] = v;
     }
     return r;
@@ -87,9 +103,11 @@ static big big_shr(const big *a, int s) {
 static big big_add(const big *a, const big *b) {
     big r;
     uint64_t carry = 0;
-    for (int i = 0; i < NLIMB; i++) {
-        uint64_t s = a->w[i] + b->w[i];
-        uint64_t c1 = s < a->w[i];
+    r.n = imin(NLIMB, imax(a->n, b->n) + 1);
+    for (int i = 0; i < r.n; i++) {
+        uint64_t x = limb(a, i), y = limb(b, i);
+        uint64_t s = x + y;
+        uint64_t c1 = s < x;
         uint64_t t = s + carry;
         uint64_t c2 = t < s;
         r.w[i] = t;
@@ -102,9 +120,11 @@ static big big_add(const big *a, const big *b) {
 static big big_sub(const big *a, const big *b) {
     big r;
     uint64_t borrow = 0;
-    for (int i = 0; i < NLIMB; i++) {
-        uint64_t d = a->w[i] - b->w[i];
-        uint64_t b1 = a->w[i] < b->w[i];
+    r.n = imax(a->n, b->n);
+    for (int i = 0; i < r.n; i++) {
+        uint64_t x = limb(a, i), y = limb(b, i);
+        uint64_t d = x - y;
+        uint64_t b1 = x < y;
         uint64_t t = d - borrow;
         uint64_t b2 = d < borrow;
         r.w[i] = t;
@@ -113,9 +133,21 @@ static big big_sub(const big *a, const big *b) {
     return r;
 }
 
+/* x / d in place (d > 0, one limb: schoolbook division digit by digit, each
+ * step dividing a 128-bit partial remainder); returns the remainder. */
+static uint64_t big_divmod_u64(big *x, uint64_t d) {
+    unsigned __int128 rem = 0;
+    for (int i = x->n - 1; i >= 0; i--) {
+        unsigned __int128 cur = (rem << 64) | x->w[i];
+        x->w[i] = (uint64_t)(cur / d);
+        rem = cur % d;
+    }
+    return (uint64_t)rem;
+}
+
 /* number of significant bits; 0 for zero */
 static int big_bitlen(const big *a) {
-    for (int i = NLIMB - 1; i >= 0; i--) {
+    for (int i = a->n - 1; i >= 0; i--) {
         if (a->w[i]) {
             int n = 64;
             while (!((a->w[i] >> (n - 1)) & 1)) n--;
@@ -141,14 +173,14 @@ static int bias_of(int e) { return (1 << (e - 1)) - 1; }
 
 /* Field layout of a pattern x (low 1+e+m bits): mantissa in bits [0,m),
  * exponent in bits [m,m+e), sign in bit m+e. */
-static decoded decode(uint32_t x, int e, int m) {
+static decoded decode(uint64_t x, int e, int m) {
     decoded d;
-    uint32_t M = x & ((1u << m) - 1u);
-    uint32_t E = (x >> m) & ((1u << e) - 1u);
+    uint64_t M = x & ((1ull << m) - 1u);
+    uint64_t E = (x >> m) & ((1ull << e) - 1u);
     d.s = (int)((x >> (e + m)) & 1u);
     d.sig = 0;
     d.q = 0;
-    if (E == (1u << e) - 1u) {
+    if (E == (1ull << e) - 1u) {
         d.cls = M ? CLS_NAN : CLS_INF;
     } else if (E == 0) {
         d.sig = M;
@@ -162,20 +194,20 @@ static decoded decode(uint32_t x, int e, int m) {
     return d;
 }
 
-static uint32_t encode(int s, uint32_t E, uint32_t M, int e, int m) {
-    return ((uint32_t)s << (e + m)) | (E << m) | M;
+static uint64_t encode(int s, uint64_t E, uint64_t M, int e, int m) {
+    return ((uint64_t)s << (e + m)) | (E << m) | M;
 }
 
-static uint32_t canonical_nan(int e, int m) {
-    return encode(0, (1u << e) - 1u, 1u << (m - 1), e, m);
+static uint64_t canonical_nan(int e, int m) {
+    return encode(0, (1ull << e) - 1u, 1ull << (m - 1), e, m);
 }
 
-static uint32_t infinity(int s, int e, int m) {
-    return encode(s, (1u << e) - 1u, 0, e, m);
+static uint64_t infinity(int s, int e, int m) {
+    return encode(s, (1ull << e) - 1u, 0, e, m);
 }
 
 /* Round (-1)^s * S * 2^q0 (S > 0) once to the format. */
-static uint32_t round_exact(int s, const big *S, int q0, int e, int m, int mode) {
+static uint64_t round_exact(int s, const big *S, int q0, int e, int m, int mode) {
     int bias = bias_of(e);
     int L = big_bitlen(S);
     /* ulp exponent of the result: normal ulp, clamped at the subnormal ulp */
@@ -184,11 +216,11 @@ static uint32_t round_exact(int s, const big *S, int q0, int e, int m, int mode)
     uint64_t sig;
     if (qt <= q0) {
         big t = big_shl(S, q0 - qt); /* exact, fits in m+1 bits */
-        sig = t.w[0];
+        sig = limb(&t, 0);
     } else {
         int sh = qt - q0;
         big t = big_shr(S, sh);
-        sig = t.w[0];
+        sig = limb(&t, 0);
         big back = big_shl(&t, sh);
         big rem = big_sub(S, &back);
         big one = big_from_u64(1);
@@ -202,18 +234,18 @@ static uint32_t round_exact(int s, const big *S, int q0, int e, int m, int mode)
         sig >>= 1;
         qt += 1;
     }
-    uint32_t E, M;
+    uint64_t E, M;
     if (sig < (1ull << m)) { /* subnormal (or zero), qt is the subnormal ulp */
         E = 0;
-        M = (uint32_t)sig;
+        M = sig;
     } else {
         long Ev = (long)qt + m + bias;
         if (Ev >= (1L << e) - 1) { /* overflow */
             if (mode == ORACLE_RNE) return infinity(s, e, m);
-            return encode(s, (1u << e) - 2u, (1u << m) - 1u, e, m);
+            return encode(s, (1ull << e) - 2u, (1ull << m) - 1u, e, m);
         }
-        E = (uint32_t)Ev;
-        M = (uint32_t)(sig - (1ull << m));
+        E = (uint64_t)Ev;
+        M = sig - (1ull << m);
     }
     return encode(s, E, M, e, m);
 }
@@ -221,7 +253,7 @@ static uint32_t round_exact(int s, const big *S, int q0, int e, int m, int mode)
 /* ------------------------------------------------------------------------ */
 /* Operations                                                                */
 /* ------------------------------------------------------------------------ */
-static uint32_t op_add(uint32_t a, uint32_t b, int e, int m, int mode) {
+static uint64_t op_add(uint64_t a, uint64_t b, int e, int m, int mode) {
     decoded x = decode(a, e, m), y = decode(b, e, m);
     if (x.cls == CLS_NAN || y.cls == CLS_NAN) return canonical_nan(e, m);
     if (x.cls == CLS_INF && y.cls == CLS_INF)
@@ -253,7 +285,7 @@ static uint32_t op_add(uint32_t a, uint32_t b, int e, int m, int mode) {
     return round_exact(s, &S, q0, e, m, mode);
 }
 
-static uint32_t op_mul(uint32_t a, uint32_t b, int e, int m, int mode) {
+static uint64_t op_mul(uint64_t a, uint64_t b, int e, int m, int mode) {
     decoded x = decode(a, e, m), y = decode(b, e, m);
     int s = x.s ^ y.s;
     if (x.cls == CLS_NAN || y.cls == CLS_NAN) return canonical_nan(e, m);
@@ -262,7 +294,7 @@ static uint32_t op_mul(uint32_t a, uint32_t b, int e, int m, int mode) {
         return infinity(s, e, m);
     }
     if (x.cls == CLS_ZERO || y.cls == CLS_ZERO) return encode(s, 0, 0, e, m);
-    big S = big_from_u64(x.sig * y.sig); /* < 2^48 */
+    big S = big_from_u128((unsigned __int128)x.sig * y.sig); /* < 2^106 */
     return round_exact(s, &S, x.q + y.q, e, m, mode);
 }
 
@@ -273,7 +305,7 @@ static uint32_t op_mul(uint32_t a, uint32_t b, int e, int m, int mode) {
  * quotient and S * 2^(qa-qb-k-1) (both lie in the same open interval between
  * consecutive multiples of 2^(qa-qb-k), and every boundary is a multiple of
  * that unit), so rounding S rounds the exact quotient. */
-static uint32_t op_div(uint32_t a, uint32_t b, int e, int m, int mode) {
+static uint64_t op_div(uint64_t a, uint64_t b, int e, int m, int mode) {
     decoded x = decode(a, e, m), y = decode(b, e, m);
     int s = x.s ^ y.s; /* sign of the quotient */
     if (x.cls == CLS_NAN || y.cls == CLS_NAN) return canonical_nan(e, m);
@@ -284,37 +316,45 @@ static uint32_t op_div(uint32_t a, uint32_t b, int e, int m, int mode) {
     if (y.cls == CLS_ZERO) return infinity(s, e, m); /* finite nonzero / 0 */
     if (x.cls == CLS_ZERO) return encode(s, 0, 0, e, m);
     const int k = 2 * m + 6; /* sig_a * 2^k / sig_b >= 2^k / 2^(m+1) = 2^(m+5) */
-    unsigned __int128 num = (unsigned __int128)x.sig << k; /* < 2^(3m+7) <= 2^76 */
-    unsigned __int128 quo = num / y.sig;
-    unsigned __int128 rem = num % y.sig;
-    unsigned __int128 s2 = 2 * quo + (rem != 0); /* < 2^77 */
-    big S = big_from_u64((uint64_t)s2);
-    S.w[1] = (uint64_t)(s2 >> 64);
+    big A0 = big_from_u64(x.sig);
+    big S = big_shl(&A0, k); /* < 2^(3m+7) <= 2^163 */
+    const uint64_t rem = big_divmod_u64(&S, y.sig);
+    S = big_shl(&S, 1);
+    S.w[0] |= (rem != 0);
     return round_exact(s, &S, x.q - y.q - k - 1, e, m, mode);
 }
 
-static int format_ok(int e, int m) { return e >= 2 && e <= 8 && m >= 1 && m <= 23; }
+static int format_ok(int e, int m) { return e >= 2 && e <= 11 && m >= 1 && m <= 52 && 1 + e + m <= 64; }
 
 /* One element.  op: 0 add, 1 sub, 2 mul, 3 div.  mode: 0 RNE, 1 RZ.
- * Returns the result pattern, or 0xFFFFFFFF for an invalid argument. */
-uint32_t oracle_op1(int op, int e, int m, int mode, uint32_t a, uint32_t b) {
-    if (!format_ok(e, m) || (mode != ORACLE_RNE && mode != ORACLE_RZ)) return 0xFFFFFFFFu;
-    uint32_t mask = (uint32_t)((1ull << (1 + e + m)) - 1u);
+ * Returns the result pattern, or all ones (never a result: NaN results have
+ * sign 0) for an invalid argument.  Bits above 1+e+m of a and b are ignored. */
+uint64_t oracle_op1_64(int op, int e, int m, int mode, uint64_t a, uint64_t b) {
+    if (!format_ok(e, m) || (mode != ORACLE_RNE && mode != ORACLE_RZ)) return ~0ull;
+    const int B = 1 + e + m;
+    const uint64_t mask = B == 64 ? ~0ull : ((1ull << B) - 1u);
     a &= mask;
     b &= mask;
     switch (op) {
     case ORACLE_ADD: return op_add(a, b, e, m, mode);
-    case ORACLE_SUB: return op_add(a, b ^ (1u << (e + m)), e, m, mode); /* a + (-b) */
+    case ORACLE_SUB: return op_add(a, b ^ (1ull << (e + m)), e, m, mode); /* a + (-b) */
     case ORACLE_MUL: return op_mul(a, b, e, m, mode);
     case ORACLE_DIV: return op_div(a, b, e, m, mode);
-    default: return 0xFFFFFFFFu;
+    default: return ~0ull;
     }
 }
 
+/* The same for formats of at most 32 bits; 0xFFFFFFFF for an invalid argument. */
+uint32_t oracle_op1(int op, int e, int m, int mode, uint32_t a, uint32_t b) {
+    if (!format_ok(e, m) || 1 + e + m > 32) return 0xFFFFFFFFu;
+    const uint64_t r = oracle_op1_64(op, e, m, mode, a, b);
+    return r == ~0ull ? 0xFFFFFFFFu : (uint32_t)r;
+}
+
 /* Round a binary64 value once to the format (used to build expected values
- * for pins, never by the GPU path). */
-uint32_t oracle_from_double(int e, int m, int mode, double v) {
-    if (!format_ok(e, m)) return 0xFFFFFFFFu;
+ * for pins, never by the GPU path); all ones for an invalid format. */
+uint64_t oracle_from_double(int e, int m, int mode, double v) {
+    if (!format_ok(e, m)) return ~0ull;
     uint64_t bits;
     memcpy(&bits, &v, sizeof bits);
     int s = (int)(bits >> 63);
@@ -333,22 +373,22 @@ uint32_t oracle_from_double(int e, int m, int mode, double v) {
 /* ------------------------------------------------------------------------ */
 typedef struct {
     int op, e, m, mode;
-    const uint32_t *a, *b;
-    uint32_t *c;
+    const uint64_t *a, *b;
+    uint64_t *c;
     uint64_t lo, hi;
 } job;
 
 static void *run_job(void *p) {
     job *j = (job *)p;
     for (uint64_t i = j->lo; i < j->hi; i++)
-        j->c[i] = oracle_op1(j->op, j->e, j->m, j->mode, j->a[i], j->b[i]);
+        j->c[i] = oracle_op1_64(j->op, j->e, j->m, j->mode, j->a[i], j->b[i]);
     return NULL;
 }
 
-/* Elementwise c[i] = a[i] op b[i] on patterns held in uint32 words.
+/* Elementwise c[i] = a[i] op b[i] on patterns held in uint64 words.
  * Returns 0, or -1 for an invalid argument. */
-int oracle_binop(int op, int e, int m, int mode, const uint32_t *a, const uint32_t *b,
-                 uint32_t *c, uint64_t n, int nthreads) {
+int oracle_binop64(int op, int e, int m, int mode, const uint64_t *a, const uint64_t *b,
+                   uint64_t *c, uint64_t n, int nthreads) {
     if (!format_ok(e, m) || op < 0 || op > 3 || (mode != 0 && mode != 1)) return -1;
     if (nthreads < 1) nthreads = 1;
     if (nthreads > 256) nthreads = 256;
@@ -377,24 +417,29 @@ int oracle_binop(int op, int e, int m, int mode, const uint32_t *a, const uint32
 /* Bitslice layout: plane k (0 <= k < B) holds bit k of every element's
  * standard pattern; element i sits in word i / 32 of the plane at bit
  * i % 32.  Planes are gpad 32-bit words apart. */
-static uint32_t load_container(const void *x, int cbytes, uint64_t i) {
+static uint64_t load_container(const void *x, int cbytes, uint64_t i) {
     if (cbytes == 1) return ((const uint8_t *)x)[i];
     if (cbytes == 2) return ((const uint16_t *)x)[i];
-    return ((const uint32_t *)x)[i];
+    if (cbytes == 4) return ((const uint32_t *)x)[i];
+    return ((const uint64_t *)x)[i];
 }
 
-static void store_container(void *x, int cbytes, uint64_t i, uint32_t v) {
+static void store_container(void *x, int cbytes, uint64_t i, uint64_t v) {
     if (cbytes == 1) ((uint8_t *)x)[i] = (uint8_t)v;
     else if (cbytes == 2) ((uint16_t *)x)[i] = (uint16_t)v;
-    else ((uint32_t *)x)[i] = v;
+    else if (cbytes == 4) ((uint32_t *)x)[i] = (uint32_t)v;
+    else ((uint64_t *)x)[i] = v;
+}
+
+static int layout_ok(int B, int cbytes) {
+    return B >= 1 && B <= 64 && B <= 8 * cbytes && (cbytes == 1 || cbytes == 2 || cbytes == 4 || cbytes == 8);
 }
 
 int oracle_pack(int B, int cbytes, const void *x, uint32_t *planes, uint64_t n, uint64_t gpad) {
-    if (B < 1 || B > 32 || B > 8 * cbytes || (cbytes != 1 && cbytes != 2 && cbytes != 4)) return -1;
-    if (gpad * 32 < n) return -1;
+    if (!layout_ok(B, cbytes) || gpad * 32 < n) return -1;
     memset(planes, 0, (size_t)B * gpad * sizeof(uint32_t));
     for (uint64_t i = 0; i < n; i++) {
-        uint32_t v = load_container(x, cbytes, i);
+        uint64_t v = load_container(x, cbytes, i);
         for (int k = 0; k < B; k++)
             if ((v >> k) & 1u) planes[(uint64_t)k * gpad + i / 32] |= 1u << (i % 32);
     }
@@ -402,12 +447,11 @@ int oracle_pack(int B, int cbytes, const void *x, uint32_t *planes, uint64_t n, 
 }
 
 int oracle_unpack(int B, int cbytes, const uint32_t *planes, void *x, uint64_t n, uint64_t gpad) {
-    if (B < 1 || B > 32 || B > 8 * cbytes || (cbytes != 1 && cbytes != 2 && cbytes != 4)) return -1;
-    if (gpad * 32 < n) return -1;
+    if (!layout_ok(B, cbytes) || gpad * 32 < n) return -1;
     for (uint64_t i = 0; i < n; i++) {
-        uint32_t v = 0;
+        uint64_t v = 0;
         for (int k = 0; k < B; k++)
-            if ((planes[(uint64_t)k * gpad + i / 32] >> (i % 32)) & 1u) v |= 1u << k;
+            if ((planes[(uint64_t)k * gpad + i / 32] >> (i % 32)) & 1u) v |= 1ull << k;
         store_container(x, cbytes, i, v);
     }
     return 0;

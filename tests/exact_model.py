@@ -230,3 +230,9 @@ def edge_patterns(f: Fmt):
 
 def sweep_formats():
     return [(e, m) for e in (3, 4, 5, 6, 8) for m in (1, 2, 3, 5, 7, 10, 15, 23)]
+
+
+def wide_formats():
+    """Formats wider than the sweep: exponents up to 11 bits, patterns up to
+    64 bits (8-byte containers above 32 bits); (11,52) is binary64."""
+    return [(8, 31), (11, 20), (11, 40), (11, 52)]

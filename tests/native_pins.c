@@ -134,3 +134,27 @@ void int_sat_sse(int op, int k, int kind, const uint32_t *a, const uint32_t *b, 
         c[i] = r;
     }
 }
+
+/* binary64 under fesetround (nearest-even or toward zero), FTZ/DAZ cleared.
+ * op: 0 add, 1 sub, 2 mul, 3 div. */
+void f64_binop(int op, int mode, const uint64_t *a, const uint64_t *b, uint64_t *c, size_t n) {
+    unsigned csr = clear_ftz_daz();
+    int old = fegetround();
+    fesetround(mode == 0 ? FE_TONEAREST : FE_TOWARDZERO);
+    for (size_t i = 0; i < n; i++) {
+        volatile double x, y, r;
+        double tx, ty;
+        memcpy(&tx, &a[i], 8);
+        memcpy(&ty, &b[i], 8);
+        x = tx;
+        y = ty;
+        if (op == 0) r = x + y;
+        else if (op == 1) r = x - y;
+        else if (op == 2) r = x * y;
+        else r = x / y;
+        double tr = r;
+        memcpy(&c[i], &tr, 8);
+    }
+    fesetround(old);
+    _mm_setcsr(csr);
+}

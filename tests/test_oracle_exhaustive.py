@@ -11,7 +11,7 @@ import numpy as np
 import pytest
 
 from tests.exact_model import (Fmt, check_correctly_rounded, edge_patterns, sweep_formats,
-                               table_round, tables)
+                               table_round, tables, wide_formats)
 
 SMALL = [(e, m) for (e, m) in sweep_formats() if 1 + e + m <= 8]
 
@@ -74,27 +74,27 @@ def _neighbour_case(oracle_lib, e, m, a, b):
                 assert err is None, (e, m, op, mode, hex(a[k]), hex(b[k]), hex(got[k]), err)
 
 
-@pytest.mark.parametrize("e,m", sweep_formats())
+@pytest.mark.parametrize("e,m", sweep_formats() + wide_formats())
 def test_neighbour_random(oracle_lib, e, m):
     f = Fmt(e, m)
     rng = np.random.default_rng(1000 + 17 * e + m)
     n = 300
-    a = rng.integers(0, 1 << f.B, n, dtype=np.uint64).astype(np.uint32)
+    a = rng.integers(0, 1 << f.B, n, dtype=np.uint64)
     # half the b's near a in magnitude, to exercise cancellation and ties
-    b = rng.integers(0, 1 << f.B, n, dtype=np.uint64).astype(np.uint32)
-    near = (a.astype(np.int64) + rng.integers(-3, 4, n)) % (1 << f.B)
-    flip = rng.integers(0, 2, n).astype(np.uint32) << (e + m)
-    b[: n // 2] = (near[: n // 2].astype(np.uint32) ^ flip[: n // 2])
+    b = rng.integers(0, 1 << f.B, n, dtype=np.uint64)
+    near = np.array([(int(x) + int(d)) % (1 << f.B) for x, d in zip(a, rng.integers(-3, 4, n))], dtype=np.uint64)
+    flip = rng.integers(0, 2, n).astype(np.uint64) << np.uint64(e + m)
+    b[: n // 2] = near[: n // 2] ^ flip[: n // 2]
     _neighbour_case(oracle_lib, e, m, a, b)
 
 
-@pytest.mark.parametrize("e,m", sweep_formats())
+@pytest.mark.parametrize("e,m", sweep_formats() + wide_formats())
 def test_neighbour_edges(oracle_lib, e, m):
     f = Fmt(e, m)
     pos = edge_patterns(f)
     pats = pos + [p | f.sign_bit for p in pos]
-    a = np.array([x for x in pats for _ in pats], dtype=np.uint32)
-    b = np.array([y for _ in pats for y in pats], dtype=np.uint32)
+    a = np.array([x for x in pats for _ in pats], dtype=np.uint64)
+    b = np.array([y for _ in pats for y in pats], dtype=np.uint64)
     _neighbour_case(oracle_lib, e, m, a, b)
 
 
@@ -102,10 +102,10 @@ def test_pack_definition(oracle_lib):
     """Plane k, word i//32, bit i%32 holds bit k of element i (Section 2);
     checked with numpy bit ops, for each container size and a ragged n."""
     rng = np.random.default_rng(5)
-    for (e, m) in [(5, 2), (4, 3), (5, 10), (8, 7), (8, 23), (3, 1)]:
+    for (e, m) in [(5, 2), (4, 3), (5, 10), (8, 7), (8, 23), (3, 1), (8, 31), (11, 52)]:
         B = 1 + e + m
         for n in (1, 31, 33, 2048 + 17):
-            dt = {1: np.uint8, 2: np.uint16, 4: np.uint32}[oracle_lib.container_bytes(e, m)]
+            dt = {1: np.uint8, 2: np.uint16, 4: np.uint32, 8: np.uint64}[oracle_lib.container_bytes(e, m)]
             x = rng.integers(0, np.iinfo(dt).max, n, dtype=np.uint64, endpoint=True).astype(dt)
             planes = oracle_lib.pack(e, m, x)
             gpad = planes.shape[1]

@@ -28,13 +28,13 @@ MUTANTS = [
     ("RZ overflow gives Inf", "if (mode == ORACLE_RNE) return infinity(s, e, m);", "return infinity(s, e, m);"),
     ("carry renormalisation dropped", "sig >>= 1;\n        qt += 1;", "qt += 0;"),
     ("mul sign not xor", "int s = x.s ^ y.s;\n", "int s = x.s;\n"),
-    ("sub does not negate", "return op_add(a, b ^ (1u << (e + m)), e, m, mode);", "return op_add(a, b, e, m, mode);"),
+    ("sub does not negate", "return op_add(a, b ^ (1ull << (e + m)), e, m, mode);", "return op_add(a, b, e, m, mode);"),
     ("inf*0 not NaN", "if (x.cls == CLS_ZERO || y.cls == CLS_ZERO) return canonical_nan(e, m);", ""),
     ("wrong bias", "static int bias_of(int e) { return (1 << (e - 1)) - 1; }",
      "static int bias_of(int e) { return (1 << (e - 1)); }"),
     ("borrow dropped in sub", "borrow = b1 | b2;", "borrow = b1;"),
     ("min exponent alignment", "int q0 = x.q < y.q ? x.q : y.q;", "int q0 = x.q > y.q ? y.q : y.q + 1;"),
-    ("div sticky dropped", "2 * quo + (rem != 0);", "2 * quo;"),
+    ("div sticky dropped", "S.w[0] |= (rem != 0);", ""),
     ("div exponent off by one", "x.q - y.q - k - 1, e, m, mode", "x.q - y.q - k, e, m, mode"),
     ("div sign not xor", "int s = x.s ^ y.s; /* sign of the quotient */", "int s = x.s;"),
     ("x/0 gives NaN", "if (y.cls == CLS_ZERO) return infinity(s, e, m);",
@@ -43,6 +43,9 @@ MUTANTS = [
     ("x/Inf gives Inf", "if (y.cls == CLS_INF) return encode(s, 0, 0, e, m);",
      "if (y.cls == CLS_INF) return infinity(s, e, m);"),
     ("div guard bits too few", "const int k = 2 * m + 6;", "const int k = 1;"),
+    ("wide integers too narrow for binary64 alignment", "#define NLIMB 36", "#define NLIMB 6"),
+    ("binary64 product truncated to 64 bits", "big S = big_from_u128((unsigned __int128)x.sig * y.sig);",
+     "big S = big_from_u64(x.sig * y.sig);"),
 ]
 
 
@@ -52,8 +55,8 @@ def _build(tmp_path, src_text, name):
     so = tmp_path / (name + ".so")
     subprocess.check_call(["gcc", "-O1", "-fPIC", "-shared", "-pthread", "-w", str(c), "-o", str(so)])
     L = ctypes.CDLL(str(so))
-    L.oracle_binop.restype = ctypes.c_int
-    L.oracle_binop.argtypes = [ctypes.c_int] * 4 + [ctypes.c_void_p] * 3 + [ctypes.c_uint64, ctypes.c_int]
+    L.oracle_binop64.restype = ctypes.c_int
+    L.oracle_binop64.argtypes = [ctypes.c_int] * 4 + [ctypes.c_void_p] * 3 + [ctypes.c_uint64, ctypes.c_int]
     return L
 
 
@@ -68,25 +71,50 @@ def _wide_gap_pairs():
     return a.astype(np.uint32), b.astype(np.uint32)
 
 
+def _run(L, op, e, m, mode, a, b, nthreads=1):
+    a64 = np.ascontiguousarray(np.asarray(a, dtype=np.uint64))
+    b64 = np.ascontiguousarray(np.asarray(b, dtype=np.uint64))
+    c = np.empty_like(a64)
+    L.oracle_binop64(op, e, m, mode, a64.ctypes.data, b64.ctypes.data, c.ctypes.data, a64.size, nthreads)
+    return c
+
+
 def _small_dividend_quotients_disagree(L):
     """binary16 subnormal / lowest-binade quotients against numpy's float16
     division (round to nearest even): the fewest bits below the rounding point."""
     a = np.repeat(np.arange(1, 1024, dtype=np.uint32), 1024)
     b = np.tile(np.arange(1024, 2048, dtype=np.uint32), 1023)
-    c = np.empty_like(a)
-    L.oracle_binop(3, 5, 10, 0, a.ctypes.data, b.ctypes.data, c.ctypes.data, a.size, 8)
+    c = _run(L, 3, 5, 10, 0, a, b, 8)
     ha, hb = a.astype(np.uint16).view(np.float16), b.astype(np.uint16).view(np.float16)
-    return not np.array_equal(c, (ha / hb).view(np.uint16).astype(np.uint32))
+    return not np.array_equal(c, (ha / hb).view(np.uint16).astype(np.uint64))
+
+
+def _binary64_wide_gaps_disagree(L):
+    """binary64 sums and differences across exponent gaps of up to ~2000
+    binades (exact sums up to ~2100 bits wide), and products and quotients,
+    against numpy's float64 (round to nearest even)."""
+    rng = np.random.default_rng(8)
+    n = 4000
+    ea = rng.integers(1000, 2046, n).astype(np.uint64)
+    eb = np.maximum(ea.astype(np.int64) - rng.integers(0, 2000, n), 0).astype(np.uint64)
+    a = (ea << np.uint64(52)) | rng.integers(0, 1 << 52, n, dtype=np.uint64)
+    b = (eb << np.uint64(52)) | rng.integers(0, 1 << 52, n, dtype=np.uint64)
+    b[::2] |= np.uint64(1 << 63)
+    fa, fb = a.view(np.float64), b.view(np.float64)
+    with np.errstate(all="ignore"):
+        for op, r in ((0, fa + fb), (2, fa * fb), (3, fa / fb)):
+            if not np.array_equal(_run(L, op, 11, 52, 0, a, b, 8), r.view(np.uint64)):
+                return True
+    return False
 
 
 def _disagrees(L):
-    if _small_dividend_quotients_disagree(L):
+    if _small_dividend_quotients_disagree(L) or _binary64_wide_gaps_disagree(L):
         return True
     f = Fmt(8, 23)
     a, b = _wide_gap_pairs()
-    c = np.empty_like(a)
     for mode in (0, 1):
-        L.oracle_binop(0, 8, 23, mode, a.ctypes.data, b.ctypes.data, c.ctypes.data, a.size, 1)
+        c = _run(L, 0, 8, 23, mode, a, b)
         for i in range(a.size):
             if check_correctly_rounded(f, "add", mode, int(a[i]), int(b[i]), int(c[i])) is not None:
                 return True
@@ -96,10 +124,9 @@ def _disagrees(L):
         n = 1 << f.B
         a = np.repeat(np.arange(n, dtype=np.uint32), n)
         b = np.tile(np.arange(n, dtype=np.uint32), n)
-        c = np.empty_like(a)
         for opi, op in enumerate(("add", "sub", "mul", "div")):
             for mode in (0, 1):
-                L.oracle_binop(opi, e, m, mode, a.ctypes.data, b.ctypes.data, c.ctypes.data, a.size, 1)
+                c = _run(L, opi, e, m, mode, a, b)
                 for i in range(0, a.size, 5):
                     if int(c[i]) != table_round(f, ta, tm, op, mode, int(a[i]), int(b[i])):
                         return True

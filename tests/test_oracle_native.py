@@ -30,6 +30,7 @@ def native():
     L.f32_binop.argtypes = [i32, i32, vp, vp, vp, sz]
     L.f16_binop_rz.argtypes = [i32, vp, vp, vp, sz]
     L.f32_chain2.argtypes = [i32, i32, i32, vp, vp, vp, vp, sz]
+    L.f64_binop.argtypes = [i32, i32, vp, vp, vp, sz]
     return L
 
 
@@ -230,3 +231,52 @@ def test_axpy_binary16_numpy(oracle_lib):
             want = (ha * hx + hy).view(np.uint16).astype(np.uint32)
         got = oracle_lib.axpy(5, 10, 0, alpha, x, y, nthreads=4)
         _compare(5, 10, got, want, x, y, ("f16 axpy", hex(alpha)))
+
+
+def _operands64(rng, n):
+    """binary64 patterns: uniform, near-cancelling, subnormal-heavy, small
+    exponent gaps and gaps of up to 2000 binades."""
+    e, m = 11, 52
+    a = rng.integers(0, 1 << 64, n, dtype=np.uint64)
+    b = rng.integers(0, 1 << 64, n, dtype=np.uint64)
+    q = n // 5
+    sign = np.uint64(1 << 63)
+    b[:q] = (a[:q] + rng.integers(0, 5, q).astype(np.uint64)) ^ sign
+    mmask = np.uint64((1 << m) - 1)
+    a[q:2 * q] = (rng.integers(0, 3, q).astype(np.uint64) << np.uint64(m)) | (a[q:2 * q] & mmask) | \
+        (a[q:2 * q] & sign)
+    ea = ((a[2 * q:3 * q] >> np.uint64(m)) & np.uint64(0x7FF)).astype(np.int64)
+    eb = np.clip(ea - rng.integers(0, m + 5, q), 0, 0x7FE).astype(np.uint64)
+    b[2 * q:3 * q] = (b[2 * q:3 * q] & ~np.uint64(0x7FF << m)) | (eb << np.uint64(m))
+    ea = rng.integers(1000, 2046, q).astype(np.int64)
+    eb = np.clip(ea - rng.integers(0, 2000, q), 0, 0x7FE)
+    a[3 * q:4 * q] = (a[3 * q:4 * q] & (mmask | sign)) | (ea.astype(np.uint64) << np.uint64(m))
+    b[3 * q:4 * q] = (b[3 * q:4 * q] & (mmask | sign)) | (eb.astype(np.uint64) << np.uint64(m))
+    return a, b
+
+
+@pytest.mark.parametrize("mode", [0, 1])
+@pytest.mark.parametrize("op", [0, 1, 2, 3])
+def test_binary64(oracle_lib, native, op, mode):
+    """(11,52) is binary64: x86 double arithmetic under fesetround."""
+    rng = np.random.default_rng(640 + 4 * op + mode)
+    a, b = _operands64(rng, 200000)
+    from tests.exact_model import Fmt, edge_patterns
+    pos = edge_patterns(Fmt(11, 52))
+    pats = pos + [p | (1 << 63) for p in pos]
+    a = np.concatenate([a, np.array([x for x in pats for _ in pats], dtype=np.uint64)])
+    b = np.concatenate([b, np.array([y for _ in pats for y in pats], dtype=np.uint64)])
+    want = np.empty_like(a)
+    native.f64_binop(op, mode, a.ctypes.data, b.ctypes.data, want.ctypes.data, a.size)
+    got = oracle_lib.binop(op, 11, 52, mode, a, b, nthreads=8)
+    _compare(11, 52, got, want, a, b, ("f64", op, mode))
+
+
+def test_from_double_binary64_is_identity(oracle_lib):
+    rng = np.random.default_rng(9)
+    x = rng.integers(0, 1 << 64, 2000, dtype=np.uint64)
+    for v in x:
+        f = float(np.uint64(v).view(np.float64))
+        if f != f:
+            continue
+        assert oracle_lib.from_double(11, 52, 0, f) == int(v)
