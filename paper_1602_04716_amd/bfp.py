@@ -484,7 +484,7 @@ def bfp_server_destroy(server: int):
 # ---- conveniences over torch tensors ----------------------------------------
 def container_dtype(f: bfp_format):
     import torch
-    return {1: torch.uint8, 2: torch.uint16, 4: torch.uint32}[bfp_container_bytes(f)]
+    return {1: torch.uint8, 2: torch.uint16, 4: torch.uint32, 8: torch.uint64}[bfp_container_bytes(f)]
 
 
 def empty_bitslice(f: bfp_format, n: int, device="cuda"):

@@ -107,6 +107,8 @@ __global__ void __launch_bounds__(kBatchBlock) k_batch(const BatchTask* tasks, c
   }
 }
 
+bool batch_format_ok(const bfp_format& f) { return format_index(f.e, f.m) >= 0 && f.round <= 1; }
+
 bool batch_task(const void* a, uint64_t na, const void* b, uint64_t nb, void* c, uint64_t n, bfp_format f, int op,
                 BatchTask* out) {
   const int fi = format_index(f.e, f.m);

@@ -37,6 +37,9 @@ constexpr int kBatchBlock = 256;
 bool batch_task(const void* a, uint64_t na, const void* b, uint64_t nb, void* c, uint64_t n, bfp_format f, int op,
                 BatchTask* out);
 
+// Formats the persistent batch kernels compile (the 40 sweep formats).
+bool batch_format_ok(const bfp_format& f);
+
 // Cut tasks into chunks of at most kChunkWords words, sorted by circuit
 // variant and, within a variant, longest task first; chunks of the division
 // circuit come last.

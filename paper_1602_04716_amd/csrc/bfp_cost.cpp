@@ -28,6 +28,7 @@ extern "C" long bfp_gate_count(int op, bfp_format f) {
 #define BFP_COUNT_CASE(EE, MM) \
   if (f.e == EE && f.m == MM) return f.round ? count<EE, MM, true>(op) : count<EE, MM, false>(op);
   BFP_FOR_EACH_FORMAT(BFP_COUNT_CASE)
+  BFP_FOR_EACH_WIDE_FORMAT(BFP_COUNT_CASE)
 #undef BFP_COUNT_CASE
   return -1;
 }

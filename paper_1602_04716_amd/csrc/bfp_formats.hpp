@@ -4,7 +4,7 @@
 // rounding mode) configuration (Section 5.1); here every format of the sweep
 // e in {3,4,5,6,8} x m in {1,2,3,5,7,10,15,23} is instantiated once per
 // operation class and rounding mode, which covers FP8 (4,3), FP16 (5,10) and
-// FP32 (8,23) of Section 5.2 and bfloat16 (8,7).
+// FP32 (8,23) of Section 5.2 and bfloat16 (8,7); four wider formats follow.
 #pragma once
 
 // X(e, m) for every compiled format
@@ -20,7 +20,14 @@
 #define BFP_FOR_EACH_INT_K(X) \
   BFP_FOR_EACH_INT_K_1_8(X) BFP_FOR_EACH_INT_K_9_16(X) BFP_FOR_EACH_INT_K_17_24(X) BFP_FOR_EACH_INT_K_25_32(X)
 
+// Formats wider than the sweep (exponent up to 11 bits, patterns up to 64
+// bits in 8-byte containers above 32 bits); (11,52) is IEEE binary64.  They
+// have the elementwise ops with 32-element lane words and the fused standard
+// path, but no two-op chains and no batch or serving kernels, whose register
+// allocation they would set.
+#define BFP_FOR_EACH_WIDE_FORMAT(X) X(8, 31) X(11, 20) X(11, 40) X(11, 52)
+
 namespace bfp {
-constexpr int kMaxE = 8;
-constexpr int kMaxM = 23;
+constexpr int kMaxE = 11;
+constexpr int kMaxM = 52;
 }  // namespace bfp

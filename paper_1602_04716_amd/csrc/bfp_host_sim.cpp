@@ -13,9 +13,10 @@ namespace {
 template <class W>
 constexpr int kBits = sizeof(W) * 8;
 
-// Run one circuit over n standard patterns (low 1+e+m bits of uint32 words).
-template <int E, int M, bool RZ, class W>
-void run(int op, const uint32_t* a, const uint32_t* b, uint32_t* c, uint64_t n) {
+// Run one circuit over n standard patterns (low 1+e+m bits of uint32 or
+// uint64 words).
+template <int E, int M, bool RZ, class W, class P>
+void run(int op, const P* a, const P* b, P* c, uint64_t n) {
   constexpr int B = 1 + E + M;
   constexpr int WB = kBits<W>;
   const W negb = (op == 1) ? bfp::WordTraits<W>::ones() : bfp::WordTraits<W>::zero();
@@ -37,8 +38,8 @@ void run(int op, const uint32_t* a, const uint32_t* b, uint32_t* c, uint64_t n) 
     else
       bfp::fp_add<E, M, RZ, W>(x, y, negb, z);
     for (int j = 0; j < WB && base + j < n; ++j) {
-      uint32_t v = 0;
-      for (int k = 0; k < B; ++k) v |= (uint32_t)((z[k] >> j) & 1u) << k;
+      P v = 0;
+      for (int k = 0; k < B; ++k) v |= (P)((z[k] >> j) & 1u) << k;
       c[base + j] = v;
     }
   }
@@ -83,11 +84,31 @@ int bfpsim_binop(int op, int e, int m, int mode, int wbits, const uint32_t* a, c
   return -1;
 }
 
+// The wide formats on uint64 patterns.
+int bfpsim_binop64(int op, int e, int m, int mode, int wbits, const uint64_t* a, const uint64_t* b, uint64_t* c,
+                   uint64_t n) {
+#define BFP_SIM_CASE(EE, MM)                                                             \
+  if (e == EE && m == MM) {                                                              \
+    if (wbits == 64) {                                                                   \
+      if (mode) run<EE, MM, true, uint64_t>(op, a, b, c, n);                             \
+      else run<EE, MM, false, uint64_t>(op, a, b, c, n);                                 \
+    } else {                                                                             \
+      if (mode) run<EE, MM, true, uint32_t>(op, a, b, c, n);                             \
+      else run<EE, MM, false, uint32_t>(op, a, b, c, n);                                 \
+    }                                                                                    \
+    return 0;                                                                            \
+  }
+  BFP_FOR_EACH_WIDE_FORMAT(BFP_SIM_CASE)
+#undef BFP_SIM_CASE
+  return -1;
+}
+
 // Gates of one circuit instance (one word group), constants folded.
 long bfpsim_gate_count(int op, int e, int m, int mode) {
 #define BFP_GC_CASE(EE, MM) \
   if (e == EE && m == MM) return (long)(mode ? gates<EE, MM, true>(op) : gates<EE, MM, false>(op));
   BFP_FOR_EACH_FORMAT(BFP_GC_CASE)
+  BFP_FOR_EACH_WIDE_FORMAT(BFP_GC_CASE)
 #undef BFP_GC_CASE
   return -1;
 }

@@ -17,6 +17,7 @@
 #include <hip/hip_runtime.h>
 
 #include "bfp_circuits.hpp"
+#include "bfp_formats.hpp"
 #include "bfp_ops.hpp"
 #include "bfp_transpose.hpp"
 
@@ -192,7 +193,8 @@ __device__ __forceinline__ void store_std(uint8_t* dst, uint64_t e0, uint64_t n,
       if (idx < n) {
         if constexpr (C == 1) dst[idx] = (uint8_t)w;
         else if constexpr (C == 2) reinterpret_cast<uint16_t*>(dst)[idx] = (uint16_t)w;
-        else reinterpret_cast<uint32_t*>(dst)[idx] = w;
+        else if constexpr (C == 4) reinterpret_cast<uint32_t*>(dst)[idx] = w;
+        else reinterpret_cast<uint64_t*>(dst)[idx] = ((uint64_t)out[r][(byte >> 2) + 1] << 32) | w;
       }
     }
   }
@@ -319,7 +321,7 @@ template <int E, int M, bool RZ, int OPC>
 __global__ void __launch_bounds__(512) k_binop_std(const uint8_t* a, const uint8_t* b, uint8_t* c,
                                                    uint64_t n, uint32_t negb) {
   constexpr int B = 1 + E + M;
-  constexpr int C = B <= 8 ? 1 : (B <= 16 ? 2 : 4);
+  constexpr int C = B <= 8 ? 1 : (B <= 16 ? 2 : (B <= 32 ? 4 : 8));
   const uint64_t groups = (n + 31) / 32;
   const uint64_t stride = (uint64_t)gridDim.x * blockDim.x;
   for (uint64_t t = (uint64_t)blockIdx.x * blockDim.x + threadIdx.x; t < groups; t += stride) {
@@ -361,11 +363,11 @@ constexpr int kMaxWordsPerLane = 2;  // R in {1, 2}
 
 struct Registry {
   // [e][m][opclass][rz][R-1]
-  BinopLauncher binop[9][24][kOpClasses][2][kMaxWordsPerLane] = {};
-  StdLauncher std_op[9][24][kOpClasses][2] = {};
+  BinopLauncher binop[kMaxE + 1][kMaxM + 1][kOpClasses][2][kMaxWordsPerLane] = {};
+  StdLauncher std_op[kMaxE + 1][kMaxM + 1][kOpClasses][2] = {};
   // two-op chains: [e][m][opclass of op1][opclass of op2][rz], op classes
   // 0 (add/sub) and 1 (mul)
-  ChainLauncher chain[9][24][2][2][2] = {};
+  ChainLauncher chain[kMaxE + 1][kMaxM + 1][2][2][2] = {};
 };
 Registry& registry();
 
@@ -408,6 +410,22 @@ void register_format() {
   r.binop[E][M][2][1][1] = launch_binop<E, M, true, 2, 2>;
   r.std_op[E][M][2][0] = launch_binop_std<E, M, false, 2>;
   r.std_op[E][M][2][1] = launch_binop_std<E, M, true, 2>;
+}
+
+// Wide formats: one 32-element word per lane (two would double registers
+// that the 64-plane circuits already fill), every op class, both modes.
+template <int E, int M>
+void register_wide_format() {
+  Registry& r = registry();
+#define BFP_WIDE_REG(OPC)                                         \
+  r.binop[E][M][OPC][0][0] = launch_binop<E, M, false, OPC, 1>;  \
+  r.binop[E][M][OPC][1][0] = launch_binop<E, M, true, OPC, 1>;   \
+  r.std_op[E][M][OPC][0] = launch_binop_std<E, M, false, OPC>;   \
+  r.std_op[E][M][OPC][1] = launch_binop_std<E, M, true, OPC>;
+  BFP_WIDE_REG(0)
+  BFP_WIDE_REG(1)
+  BFP_WIDE_REG(2)
+#undef BFP_WIDE_REG
 }
 
 }  // namespace bfp

@@ -33,7 +33,7 @@ bool format_ok(const bfp_format& f) {
 int bits_of(const bfp_format& f) { return 1 + f.e + f.m; }
 int cbytes_of(const bfp_format& f) {
   const int B = bits_of(f);
-  return B <= 8 ? 1 : (B <= 16 ? 2 : 4);
+  return B <= 8 ? 1 : (B <= 16 ? 2 : (B <= 32 ? 4 : 8));
 }
 uint64_t gpad_of(uint64_t n) {
   const uint64_t g = (n + 31) / 32;
@@ -71,7 +71,7 @@ unsigned grid_for(uint64_t items, int block, int blocks_per_cu) {
 
 // Launch configuration table: [opclass][e][m][round]
 std::mutex g_cfg_mu;
-bfp_launch g_cfg[kOpClasses][9][24][2];
+bfp_launch g_cfg[kOpClasses][kMaxE + 1][kMaxM + 1][2];
 bool g_cfg_init = false;
 
 // Defaults before tuning (measured on MI355X at 2^26 elements): circuits
@@ -81,13 +81,14 @@ bool g_cfg_init = false;
 void cfg_init_locked() {
   if (g_cfg_init) return;
   for (int o = 0; o < kOpClasses; ++o)
-    for (int e = 0; e < 9; ++e)
-      for (int m = 0; m < 24; ++m)
+    for (int e = 0; e <= kMaxE; ++e)
+      for (int m = 0; m <= kMaxM; ++m)
         for (int r = 0; r < 2; ++r) {
           bfp_launch& c = g_cfg[o][e][m][r];
           const int B = 1 + e + m;
           const bool valu_heavy = (o == 1 && m >= 15) || (o == 2 && m >= 10);
-          c.words_per_lane = (B <= 8 || valu_heavy) ? 1 : 2;
+          const bool one_word_only = !registry().binop[e][m][o][r][1];
+          c.words_per_lane = (B <= 8 || valu_heavy || one_word_only) ? 1 : 2;
           c.block = B <= 8 ? 128 : 256;
           c.blocks_per_cu = 0;
           c.pad = 0;
@@ -140,6 +141,8 @@ bfp_status chain_impl(int op1, int op2, bfp_format f, const void* a, uint32_t al
                       void* d, uint64_t n, void* stream) {
   if (!chain_op_ok(op1) || !chain_op_ok(op2)) return BFP_E_OP;
   if (!format_ok(f)) return BFP_E_FORMAT;
+  ChainLauncher L = registry().chain[f.e][f.m][opclass_of(op1)][opclass_of(op2)][f.round];
+  if (!L) return BFP_E_FORMAT;  // the wide formats have no chain kernels
   if (n == 0) return BFP_OK;
   if (n > kMaxN) return BFP_E_ARG;
   if (!b || !c || !d) return BFP_E_NULL;
@@ -149,8 +152,6 @@ bfp_status chain_impl(int op1, int op2, bfp_format f, const void* a, uint32_t al
   const void* in[3] = {a, b, c};
   for (const void* p : in)
     if (p && p != d && overlap(d, bytes, p, bytes)) return BFP_E_ALIAS;
-  ChainLauncher L = registry().chain[f.e][f.m][opclass_of(op1)][opclass_of(op2)][f.round];
-  if (!L) return BFP_E_FORMAT;
   const unsigned block = 256;
   const unsigned grid = grid_for(gpad, (int)block, 0);
   const uint32_t alpha_b = alpha & (uint32_t)((1ull << bits_of(f)) - 1u);
@@ -200,7 +201,7 @@ size_t bfp_bitslice_bytes(bfp_format f, uint64_t n) {
 namespace bfp {
 namespace {
 
-int cbytes_of_bits(int B) { return B <= 8 ? 1 : (B <= 16 ? 2 : 4); }
+int cbytes_of_bits(int B) { return B <= 8 ? 1 : (B <= 16 ? 2 : (B <= 32 ? 4 : 8)); }
 
 // Standard containers <-> B planes, 1 <= B <= 32 (format checked by the caller).
 bfp_status pack_impl(int B, const void* std_in, void* bs_out, uint64_t n, void* stream) {
@@ -213,7 +214,7 @@ bfp_status pack_impl(int B, const void* std_in, void* bs_out, uint64_t n, void* 
   if (overlap(std_in, n * C, bs_out, (size_t)B * gpad * 4)) return BFP_E_ALIAS;
   const int block = 256;
   const unsigned grid = grid_for(gpad, block, 0);
-  PackLauncher L = C == 1 ? launch_pack<1> : (C == 2 ? launch_pack<2> : launch_pack<4>);
+  PackLauncher L = C == 1 ? launch_pack<1> : (C == 2 ? launch_pack<2> : (C == 4 ? launch_pack<4> : launch_pack<8>));
   return hip_status(L(std_in, bs_out, n, gpad, B, grid, block, (hipStream_t)stream));
 }
 
@@ -228,7 +229,8 @@ bfp_status unpack_impl(int B, const void* bs_in, void* std_out, uint64_t n, void
   const int block = 256;
   const uint64_t tiles = ((n + 31) / 32 + 63) / 64;  // 64 groups per wave tile
   const unsigned grid = grid_for(tiles * 64, block, 0);
-  PackLauncher L = C == 1 ? launch_unpack<1> : (C == 2 ? launch_unpack<2> : launch_unpack<4>);
+  PackLauncher L =
+      C == 1 ? launch_unpack<1> : (C == 2 ? launch_unpack<2> : (C == 4 ? launch_unpack<4> : launch_unpack<8>));
   return hip_status(L(bs_in, std_out, n, gpad, B, grid, block, (hipStream_t)stream));
 }
 
@@ -363,6 +365,8 @@ bfp_status bfp_launch_set(int op, bfp_format f, const bfp_launch* cfg) {
   if (!format_ok(f)) return BFP_E_FORMAT;
   if (!cfg) return BFP_E_NULL;
   if (!cfg_valid(*cfg)) return BFP_E_ARG;
+  // the wide formats have one-word kernels only
+  if (!registry().binop[f.e][f.m][opclass_of(op)][f.round][cfg->words_per_lane - 1]) return BFP_E_ARG;
   std::lock_guard<std::mutex> lk(g_cfg_mu);
   cfg_init_locked();
   g_cfg[opclass_of(op)][f.e][f.m][f.round] = *cfg;
@@ -412,8 +416,8 @@ bfp_status bfp_launch_save(const char* path) {
     std::lock_guard<std::mutex> lk(g_cfg_mu);
     cfg_init_locked();
     for (int o = 0; o < kOpClasses; ++o)
-      for (int e = 0; e < 9; ++e)
-        for (int m = 0; m < 24; ++m)
+      for (int e = 0; e <= kMaxE; ++e)
+        for (int m = 0; m <= kMaxM; ++m)
           for (int r = 0; r < 2; ++r) {
             if (!registry().binop[e][m][0][0][0]) continue;
             const bfp_launch& c = g_cfg[o][e][m][r];

@@ -267,7 +267,7 @@ bfp_status bfp_server_submit(bfp_server* s, int op, bfp_format f, uint32_t a, ui
                              uint64_t* req_id) {
   if (!s || !req_id) return BFP_E_NULL;
   if (!op_valid(op)) return BFP_E_OP;
-  if (!bfp_format_supported(f)) return BFP_E_FORMAT;
+  if (!bfp_format_supported(f) || !batch_format_ok(f)) return BFP_E_FORMAT;
   {
     std::lock_guard<std::mutex> lk(s->sched->mutex());
     const Resident* ra = s->sched->resident(a);
@@ -309,7 +309,7 @@ bfp_status bfp_server_replay(bfp_server* s, const bfp_request* reqs, uint32_t co
   for (uint32_t i = 0; i < count; ++i) {
     const bfp_request& r = reqs[i];
     if (!op_valid(r.op)) return BFP_E_OP;
-    if (!bfp_format_supported(r.f)) return BFP_E_FORMAT;
+    if (!bfp_format_supported(r.f) || !batch_format_ok(r.f)) return BFP_E_FORMAT;
     if (r.arrival_ns < 0 || (i && r.arrival_ns < reqs[i - 1].arrival_ns)) return BFP_E_ARG;
   }
   const int64_t t0 = now_ns();

@@ -89,8 +89,11 @@ extern "C" bfp_status bfp_autotune(int op, bfp_format f, uint64_t n_probe, int w
   double best = 1e30;
   bfp_launch best_cfg = saved;
   std::vector<float> ts;
+  bool any = false;
   for (int wpl = 1; wpl <= 2 && st == BFP_OK; ++wpl) {
     if (!(words_per_lane_mask & wpl)) continue;
+    if (!registry().binop[f.e][f.m][opclass_of(op)][f.round][wpl - 1]) continue;  // not compiled
+    any = true;
     for (int blk : blocks) {
       for (int bpc : bpcs) {
         bfp_launch cfg;
@@ -125,6 +128,7 @@ extern "C" bfp_status bfp_autotune(int op, bfp_format f, uint64_t n_probe, int w
   }
   (void)hipEventDestroy(e0);
   (void)hipEventDestroy(e1);
+  if (st == BFP_OK && !any) st = BFP_E_ARG;  // no allowed word width is compiled for f
   if (st != BFP_OK) {
     (void)bfp_launch_set(op, f, &saved);
     return st;

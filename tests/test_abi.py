@@ -52,6 +52,25 @@ def test_sizing():
     assert bfp.bfp_bitslice_bytes(bfp.fmt(7, 3), 10) == 0  # not compiled
 
 
+def test_wide_formats_sizing_and_table():
+    for (e, m), C in (((8, 31), 8), ((11, 20), 4), ((11, 40), 8), ((11, 52), 8)):
+        f = bfp.fmt(e, m)
+        assert bfp.bfp_format_supported(f)
+        assert bfp.bfp_container_bytes(f) == C
+        assert bfp.bfp_bitslice_bytes(f, 1000) == (1 + e + m) * 64 * 4
+        for op in ("add", "mul", "div"):
+            assert bfp.bfp_launch_get(op, f).words_per_lane == 1
+            assert bfp.bfp_gate_count(op, f) > 0
+    w = bfp.fmt(11, 52)
+    old = bfp.bfp_launch_get("mul", w)
+    with pytest.raises(bfp.BfpError):
+        bfp.bfp_launch_set("mul", w, 2, 256, 0)  # one-word kernels only
+    bfp.bfp_launch_set("mul", w, 1, 128, 4)
+    bfp.bfp_launch_set("mul", w, old.words_per_lane, old.block, old.blocks_per_cu)
+    assert not bfp.bfp_format_supported(bfp.fmt(11, 53))
+    assert not bfp.bfp_format_supported(bfp.fmt(12, 40))
+
+
 def test_supported_formats():
     from paper_1602_04716_amd import inputs
     for (e, m) in inputs.sweep_formats():
@@ -97,6 +116,10 @@ def test_argument_errors_before_any_device_work():
     assert L.bfp_int_unpack(5, 16, 32, 1 << 40, None) == -6
     assert bfp.bfp_int_container_bytes(9) == 2 and bfp.bfp_int_container_bytes(0) == 0
     assert bfp.bfp_int_bitslice_bytes(13, 70000) == 13 * bfp.bfp_plane_stride_words(70000) * 4
+    # wide formats: elementwise ops only (no chains, no batch or serving kernels)
+    w = bfp.fmt(11, 52)
+    assert L.bfp_chain2(2, 0, w, 16, 32, 48, 64, 1, None) == -1
+    assert L.bfp_axpy(w, 0, 16, 32, 48, 1, None) == -1
     assert bfp.bfp_status_string(-5).startswith("HIP")
 
 

@@ -29,6 +29,7 @@ def sim():
     L.bfpsim_int_binop.argtypes = [ctypes.c_int] * 4 + [ctypes.c_void_p] * 3 + [ctypes.c_uint64]
     L.bfpsim_int_gate_count.restype = ctypes.c_long
     L.bfpsim_int_gate_count.argtypes = [ctypes.c_int] * 3
+    L.bfpsim_binop64.argtypes = [ctypes.c_int] * 5 + [ctypes.c_void_p] * 3 + [ctypes.c_uint64]
     return L
 
 
@@ -196,3 +197,34 @@ def test_int_gate_counts():
         g = np.array([L.bfpsim_int_gate_count(2, int(k), kind) for k in ks], dtype=float)
         c = np.linalg.lstsq(np.stack([np.ones_like(ks), ks, ks ** 2], axis=1), g, rcond=None)[0]
         assert lo < c[2] < hi, (kind, c)
+
+
+WIDE = [(8, 31), (11, 20), (11, 40), (11, 52)]
+
+
+@pytest.mark.parametrize("e,m", WIDE)
+def test_wide_formats(sim, oracle_lib, e, m):
+    """The wide formats (patterns up to 64 bits) against the oracle: random
+    pairs, subnormal-heavy and near-cancelling pairs, and the edge set."""
+    from tests.exact_model import Fmt, edge_patterns
+    B = 1 + e + m
+    rng = np.random.default_rng(e * 100 + m)
+    n = 4000
+    a = rng.integers(0, 1 << B, n, dtype=np.uint64)
+    b = rng.integers(0, 1 << B, n, dtype=np.uint64)
+    low = np.uint64(((1 << (m + 2)) - 1) | (1 << (e + m)))
+    a[:800] &= low
+    b[800:1600] &= low
+    b[1600:2400] = (a[1600:2400] + rng.integers(0, 3, 800).astype(np.uint64)) ^ np.uint64(1 << (e + m))
+    pos = edge_patterns(Fmt(e, m))
+    pats = pos + [p | (1 << (e + m)) for p in pos]
+    a = np.concatenate([a, np.array([x for x in pats for _ in pats], dtype=np.uint64)])
+    b = np.concatenate([b, np.array([y for _ in pats for y in pats], dtype=np.uint64)])
+    for op in range(4):
+        for mode in (0, 1):
+            want = oracle_lib.binop(op, e, m, mode, a, b, nthreads=4).astype(np.uint64)
+            for w in (32, 64):
+                c = np.empty_like(a)
+                assert sim.bfpsim_binop64(op, e, m, mode, w, a.ctypes.data, b.ctypes.data, c.ctypes.data, a.size) == 0
+                bad = np.flatnonzero(c != want)
+                assert bad.size == 0, (op, mode, w, hex(a[bad[0]]), hex(b[bad[0]]), hex(c[bad[0]]), hex(want[bad[0]]))
