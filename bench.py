@@ -20,6 +20,8 @@ Also printed in the same JSON line:
   div           division (Table 1, Div) on resident bitslice vectors of the
                 same size and formats, the launch table's configuration:
                 elements/s and its bitwise VALU rate against peak;
+  wide          binary64 (11,52) add, mul and div on resident bitslice
+                vectors of the same size (tuned one-word kernels);
   int           k-bit integer vectors (k = 5, 9, 13), 2^26 elements: wrapping
                 add and mul, signed-saturating mul;
   chain         d = a*b + c on the same vectors: one two-op chain kernel
@@ -61,6 +63,7 @@ def parse():
     ap.add_argument("--no-div", action="store_true")
     ap.add_argument("--no-chain", action="store_true")
     ap.add_argument("--no-int", action="store_true")
+    ap.add_argument("--no-wide", action="store_true")
     ap.add_argument("--div-reps", type=int, default=10)
     ap.add_argument("--serving-requests", type=int, default=20000)
     return ap.parse_args()
@@ -212,6 +215,38 @@ def bench_chain(torch, bfp, dev, n, reps):
             "valu_frac": G * n / 32 / (us * 1e-6) / VALU_PEAK,
             "device_kernel": "bfp::k_chain2<%d, %d, false, 1, 0, 1>" % (e, m)}
         del pa, pb, pc, pd, pt
+    return out
+
+
+def bench_wide(torch, bfp, dev, n, reps):
+    """binary64 elementwise ops on resident bitslice vectors of n elements,
+    RNE, the launch table's configuration, `reps` launches between events."""
+    import numpy as np
+    s = torch.cuda.current_stream()
+    e, m = 11, 52
+    f = bfp.fmt(e, m)
+    rng = np.random.default_rng(11)
+    pa, pb = (bfp.pack(f, torch.from_numpy(rng.standard_normal(n)).to(dev).view(torch.uint64)) for _ in range(2))
+    pc = bfp.empty_bitslice(f, n, dev)
+    out = {}
+    for op in ("add", "mul", "div"):
+        for _ in range(2):
+            bfp.bfp_binop(op, f, pa, pb, pc, n, s)
+        ev0, ev1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+        ev0.record(s)
+        for _ in range(reps):
+            bfp.bfp_binop(op, f, pa, pb, pc, n, s)
+        ev1.record(s)
+        torch.cuda.synchronize()
+        us = ev0.elapsed_time(ev1) * 1e3 / reps
+        G = bfp.bfp_gate_count(op, f)
+        cfg = bfp.bfp_launch_get(op, f)
+        ops_s = G * n / 32 / (us * 1e-6)
+        bytes_s = 3 * 64 / 8 * n / (us * 1e-6)
+        out["%s(11,52)" % op] = {"us": us, "elements_per_s": n / (us * 1e-6), "gates": G,
+                                 "valu_frac": ops_s / VALU_PEAK, "hbm_frac": bytes_s / HBM_PEAK,
+                                 "block": cfg.block, "blocks_per_cu": cfg.blocks_per_cu}
+    del pa, pb, pc
     return out
 
 
@@ -451,6 +486,8 @@ def main():
         res["chain"] = bench_chain(torch, bfp, dev, n, args.div_reps)
     if not args.no_int:
         res["int"] = bench_int(torch, bfp, dev, n, args.div_reps)
+    if not args.no_wide:
+        res["wide"] = bench_wide(torch, bfp, dev, n, args.div_reps)
     if not args.no_cpu_baseline:
         res["cpu_baseline"] = cpu_baseline()
     print(json.dumps(res), flush=True)

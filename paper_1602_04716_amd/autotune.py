@@ -2,7 +2,8 @@
 
     python -m paper_1602_04716_amd.autotune [--n-log2 24] [--reps 7] [--out tuning/gfx950.txt]
 
-For each format of the sweep (e in {3,4,5,6,8} x m in {1,2,3,5,7,10,15,23}),
+For each format of the sweep (e in {3,4,5,6,8} x m in {1,2,3,5,7,10,15,23})
+and the four wide formats (one-word kernels only),
 each op class (add, mul, div) and each rounding mode, ``bfp_autotune`` times the
 launch variants on a 2^24-element probe with the last-level cache swept clean
 before every run and installs the fastest; the table is saved for
@@ -51,14 +52,14 @@ def main(argv=None):
     ap.add_argument("--n-log2", type=int, default=24)
     ap.add_argument("--reps", type=int, default=7)
     ap.add_argument("--out", default=bfp.TUNE_TABLE)
-    ap.add_argument("--formats", default="", help="comma list like 5:10,8:7; default all 40")
+    ap.add_argument("--formats", default="", help="comma list like 5:10,8:7; default all 44")
     ap.add_argument("--ops", default="add,mul,div", help="op classes to tune (sub shares add's entry)")
     a = ap.parse_args(argv)
     import torch
     assert torch.cuda.is_available()
     os.environ["BFP_TUNE_FILE"] = ""  # start from the built-in defaults
     bfp.lib()
-    fmts = inputs.sweep_formats()
+    fmts = inputs.sweep_formats() + inputs.wide_formats()
     if a.formats:
         fmts = [tuple(int(x) for x in s.split(":")) for s in a.formats.split(",")]
     tune(fmts, ops=tuple(a.ops.split(",")), n=1 << a.n_log2, reps=a.reps, log=lambda s: print(s, flush=True))

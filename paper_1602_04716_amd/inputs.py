@@ -32,6 +32,11 @@ def sweep_formats():
     return [(e, m) for e in SWEEP_E for m in SWEEP_M]
 
 
+def wide_formats():
+    """The compiled formats beyond the sweep (8-byte containers above 32 bits)."""
+    return [(8, 31), (11, 20), (11, 40), (11, 52)]
+
+
 def container_dtype(e: int, m: int):
     B = 1 + e + m
     return np.uint8 if B <= 8 else (np.uint16 if B <= 16 else np.uint32)
