@@ -11,19 +11,21 @@
  * {1,2,3,5,7,10,15,23}.
  *
  * Layouts (Section 2, Figure 1; Section 4, Figure 3):
- *   standard  one element per unsigned container of 1, 2 or 4 bytes
- *             (B <= 8, <= 16, <= 32), value in the low B bits: mantissa in
+ *   standard  one element per unsigned container of 1, 2, 4 or 8 bytes
+ *             (B <= 8, <= 16, <= 32, <= 64), value in the low B bits: mantissa in
  *             bits [0,m), exponent in [m,m+e), sign in bit m+e.  Bits above B
  *             are ignored on input and written as zero on output.
  *   bitslice  B planes of G_pad 32-bit words each, plane k first
  *             (plane-major).  Plane k holds bit k of every element; element
  *             i sits in word i/32 of its plane at bit i%32.
  *             G_pad = bfp_plane_stride_words(n) = ceil(n/32) rounded up to a
- *             multiple of 64, so every plane starts 256-byte aligned.  The
- *             layout is the same for any word width a kernel uses (32 or 64
- *             elements per lane word).  Padding bits past element n are zero
- *             after bfp_pack and stay zero through every operation
- *             (0 op 0 = +0, whose bits are all zero).
+ *             multiple of 64, plus 256 when that is a multiple of 2048: every
+ *             plane starts 256-byte aligned, and plane strides that are
+ *             multiples of 8 KiB (which send all planes of one word group to
+ *             the same HBM channels) are avoided.  The layout is the same for
+ *             any word width a kernel uses (32 or 64 elements per lane
+ *             word).  Padding bits past element n are zero after bfp_pack
+ *             and stay zero through every operation.
  *
  * Semantics: each result is the exact sum, difference or product rounded
  * once, to nearest with ties to even (BFP_RNE) or toward zero (BFP_RZ) -- the
@@ -103,11 +105,11 @@ int bfp_format_supported(bfp_format f);
 
 /* ---- sizing -------------------------------------------------------------- */
 
-/* Bytes of one standard container: 1, 2 or 4; 0 for an invalid format. */
+/* Bytes of one standard container: 1, 2, 4 or 8; 0 for an invalid format. */
 size_t bfp_container_bytes(bfp_format f);
 
 /* G_pad: 32-bit words per plane for n elements (ceil(n/32) rounded up to a
- * multiple of 64). */
+ * multiple of 64, plus 256 if that is a multiple of 2048). */
 uint64_t bfp_plane_stride_words(uint64_t n);
 
 /* Bytes of one bitslice vector: B * G_pad * 4; 0 for an invalid format. */

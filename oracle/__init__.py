@@ -140,9 +140,11 @@ def container_bytes(e: int, m: int) -> int:
 
 
 def plane_stride_words(n: int) -> int:
-    """32-bit words per plane: ceil(n/32) rounded up to a multiple of 64."""
+    """32-bit words per plane: ceil(n/32) rounded up to a multiple of 64, plus
+    256 when that is a multiple of 2048 (the library's documented layout)."""
     g = (n + 31) // 32
-    return (g + 63) // 64 * 64
+    gp = (g + 63) // 64 * 64
+    return gp + 256 if gp % 2048 == 0 else gp
 
 
 def pack(e: int, m: int, x, gpad: int | None = None) -> np.ndarray:

@@ -48,7 +48,13 @@ def test_sizing():
     assert bfp.bfp_plane_stride_words(1) == 64
     assert bfp.bfp_plane_stride_words(64 * 32) == 64
     assert bfp.bfp_plane_stride_words(64 * 32 + 1) == 128
-    assert bfp.bfp_bitslice_bytes(f, 1 << 26) == 16 * (1 << 21) * 4
+    assert bfp.bfp_plane_stride_words(2048 * 32) == 2048 + 256      # 8 KiB-multiple strides are skewed
+    assert bfp.bfp_plane_stride_words(1 << 26) == (1 << 21) + 256
+    assert bfp.bfp_plane_stride_words(2048 * 32 + 1) == 2048 + 64
+    for n in (1, 1000, 65536, 70013, 1 << 20, (1 << 24) + 3):
+        g = bfp.bfp_plane_stride_words(n)
+        assert g % 64 == 0 and g * 32 >= n and g % 2048 != 0
+    assert bfp.bfp_bitslice_bytes(f, 1 << 26) == 16 * ((1 << 21) + 256) * 4
     assert bfp.bfp_bitslice_bytes(bfp.fmt(7, 3), 10) == 0  # not compiled
 
 
