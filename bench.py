@@ -308,28 +308,45 @@ def committed_traffic(kernel):
     return None
 
 
-def cpu_baseline(sample_log2=24):
+def _cpu_model():
+    try:
+        for line in open("/proc/cpuinfo"):
+            if line.startswith("model name"):
+                return line.split(":", 1)[1].strip()
+    except OSError:
+        pass
+    return "unknown"
+
+
+def cpu_baseline(sample_log2=24, single_log2=22):
     """The oracle on a bounded sample of the same workload: 2^24 elements per
-    (format, op), all 6 combinations, on this host's cores."""
+    (format, op), all 6 combinations, on this host's cores; and 2^22 per
+    combination on one thread."""
     import numpy as np
 
     import oracle
     from paper_1602_04716_amd import inputs
     oracle.build()
     threads = max(1, min(os.cpu_count() or 1, 64))
-    n = 1 << sample_log2
-    total = 0
-    elapsed = 0.0
-    for (e, m) in FORMATS:
-        a = inputs.scaled_normal(e, m, n, 2)
-        b = inputs.scaled_normal(e, m, n, 3)
-        for op in OPS:
-            t0 = time.perf_counter()
-            oracle.binop(op, e, m, 0, a, b, nthreads=threads)
-            elapsed += time.perf_counter() - t0
-            total += n
-    return {"value": total / elapsed, "unit": "elements/s", "cores": threads, "kind": "oracle",
-            "sample": "2^%d elements x {(5,10),(8,7)} x {add,sub,mul}, RNE, %.1f s wall" % (sample_log2, elapsed)}
+
+    def timed(n, nthreads):
+        total, elapsed = 0, 0.0
+        for (e, m) in FORMATS:
+            a = inputs.scaled_normal(e, m, n, 2)
+            b = inputs.scaled_normal(e, m, n, 3)
+            for op in OPS:
+                t0 = time.perf_counter()
+                oracle.binop(op, e, m, 0, a, b, nthreads=nthreads)
+                elapsed += time.perf_counter() - t0
+                total += n
+        return total / elapsed, elapsed
+
+    v, el = timed(1 << sample_log2, threads)
+    v1, el1 = timed(1 << single_log2, 1)
+    return {"value": v, "unit": "elements/s", "cores": threads, "kind": "oracle",
+            "sample": "2^%d elements x {(5,10),(8,7)} x {add,sub,mul}, RNE, %.1f s wall on %d threads; "
+                      "2^%d per combination on 1 thread, %.1f s" % (sample_log2, el, threads, single_log2, el1),
+            "single_thread_value": v1, "cpu_model": _cpu_model()}
 
 
 def main():

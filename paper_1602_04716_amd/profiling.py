@@ -1,4 +1,4 @@
-"""Summaries of rocprofv3 databases (kernel trace and byte counters).
+"""Summaries of rocprofv3 databases (kernel trace, byte and VALU counters).
 
     python -m paper_1602_04716_amd.profiling --trace T.db --fetch F.db --write W.db \
         --kernel k_unpack<2> --out profiles/NAME --command-trace "..." --command-fetch "..." \
@@ -10,6 +10,11 @@ kernel's HBM bytes per launch and the hash of the kernel sources the counters
 were taken with).  The byte counters are scaled by what the same counter reads
 for the run's calibration kernel, a plain int32 -> float32 conversion of 2^26
 elements (256 MiB read, 256 MiB written).
+
+    python -m paper_1602_04716_amd.profiling valu --trace T.db --pmc P.db --out profiles/NAME ...
+
+writes ``NAME.md`` with the circuit kernels' measured VALU instructions
+(SQ_INSTS_VALU) per 32 elements beside their gate counts.
 """
 from __future__ import annotations
 
@@ -114,7 +119,83 @@ def read_traffic(path: str):
     return {"kernel": d.get("kernel"), "bytes": float(d["traffic_bytes_per_launch"])}
 
 
+VALU_PEAK = 256 * 4 * 16 * 2.4e9  # 32-bit lane-ops/s: 256 CU x 4 SIMD x 16 lanes x 2.4 GHz
+
+
+def counter_by_name(db: str, counter: str):
+    """(kernel short name) -> list of per-dispatch values of one counter."""
+    c = sqlite3.connect(db).cursor()
+    d = collections.defaultdict(list)
+    for name, cname, val in c.execute("select kernel_name, counter_name, value from counters_collection"):
+        if cname == counter:
+            d[short_name(name)].append(val)
+    return d
+
+
+def _gates(kernel: str):
+    """Gate count per 32 elements of a bench circuit kernel, from its template
+    arguments: k_binop<E, M, RZ, OPC, R> or k_chain2<E, M, RZ, O1, O2, R>."""
+    from . import bfp
+    m = re.match(r"bfp::k_(binop|chain2)<(.*)>$", kernel)
+    if not m:
+        return None
+    args = [x.strip() for x in m.group(2).split(",")]
+    e, mm, rz = int(args[0]), int(args[1]), 1 if args[2] == "true" else 0
+    op_of = {0: "add", 1: "mul", 2: "div"}
+    f = bfp.fmt(e, mm, rz)
+    if m.group(1) == "binop":
+        return bfp.bfp_gate_count(op_of[int(args[3])], f)
+    return bfp.bfp_gate_count(op_of[int(args[3])], f) + bfp.bfp_gate_count(op_of[int(args[4])], f)
+
+
+def valu_summary(trace_db, pmc_db, n, out, commands):
+    """Measured VALU instructions (SQ_INSTS_VALU) of the circuit kernels next
+    to their gate counts: instructions issued per 32 elements against gates
+    per 32 elements, and the VALU utilisation the instruction count implies
+    at the kernel-trace duration."""
+    stats = {k: avg for (k, calls, avg, tot, pct) in trace_stats(trace_db)}
+    insts = counter_by_name(pmc_db, "SQ_INSTS_VALU")
+    lines = ["# rocprofv3 VALU summary: %s" % os.path.basename(out), "",
+             "Kernel sources hash: `%s`" % source_hash(), "",
+             "Commands (run from the repository root on one MI355X):", ""]
+    for k, v in commands.items():
+        lines.append("- %s: `%s`" % (k, v))
+    lines += ["", "n = %d elements per launch; a wave64 VALU instruction is 64 lane-ops; peak %.3g lane-ops/s."
+              % (n, VALU_PEAK), "",
+              "| kernel | dispatches | VALU instr / dispatch | lane-instr / 32 elem | gates / 32 elem | "
+              "instr / gate | trace avg us | VALU utilisation (instr) | gate rate / peak |",
+              "|---|---|---|---|---|---|---|---|---|"]
+    groups = n / 32
+    for name in sorted(insts):
+        g = _gates(name)
+        if g is None or name not in stats:
+            continue
+        vi = sum(insts[name]) / len(insts[name])
+        per32 = vi * 64 / groups
+        us = stats[name]
+        util = vi * 64 / (us * 1e-6) / VALU_PEAK
+        gfrac = g * groups / (us * 1e-6) / VALU_PEAK
+        lines.append("| `%s` | %d | %.4g | %.0f | %d | %.2f | %.1f | %.2f | %.2f |"
+                     % (name, len(insts[name]), vi, per32, g, per32 / g, us, util, gfrac))
+    with open(out + ".md", "w") as fp:
+        fp.write("\n".join(lines) + "\n")
+
+
 def main(argv=None):
+    import sys
+    if argv is None:
+        argv = sys.argv[1:]
+    if argv and argv[0] == "valu":
+        ap = argparse.ArgumentParser()
+        ap.add_argument("--trace", required=True)
+        ap.add_argument("--pmc", required=True)
+        ap.add_argument("--n", type=int, default=1 << 26)
+        ap.add_argument("--out", required=True)
+        ap.add_argument("--command-trace", default="")
+        ap.add_argument("--command-pmc", default="")
+        a = ap.parse_args(argv[1:])
+        valu_summary(a.trace, a.pmc, a.n, a.out, {"trace": a.command_trace, "SQ_INSTS_VALU": a.command_pmc})
+        return
     ap = argparse.ArgumentParser()
     ap.add_argument("--trace", required=True)
     ap.add_argument("--fetch", required=True)
