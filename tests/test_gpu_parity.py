@@ -213,3 +213,36 @@ def test_full_size_2_26(e, m):
         assert not mism.any(), (op, int(mism.sum()))
         del pc, out
     torch.cuda.synchronize()
+
+
+def test_beyond_32_bit_offsets():
+    """n = 2^33 + 77 elements of (5,2) (8 GiB per operand): plane word offsets
+    and element offsets exceed 2^32, through pack, add, mul, unpack and the
+    fused path; the first and last 4096 outputs and 100,000 sampled ones
+    against the oracle, and the two paths against each other on every output."""
+    e, m = 5, 2
+    n = (1 << 33) + 77
+    f = bfp.fmt(e, m)
+    g = torch.Generator(device="cuda")
+    g.manual_seed(33)
+    da = torch.randint(0, 256, (n,), dtype=torch.uint8, device="cuda", generator=g)
+    db = torch.randint(0, 256, (n,), dtype=torch.uint8, device="cuda", generator=g)
+    rng = np.random.default_rng(33)
+    idx = np.unique(np.concatenate([np.arange(4096), np.arange(n - 4096, n),
+                                    rng.integers(0, n, 100000, dtype=np.int64)]))
+    tidx = torch.from_numpy(idx).cuda()
+    a = da[tidx].cpu().numpy()
+    b = db[tidx].cpu().numpy()
+    pa, pb = bfp.pack(f, da), bfp.pack(f, db)
+    for op in ("add", "mul"):
+        pc = bfp.empty_bitslice(f, n)
+        bfp.bfp_binop(op, f, pa, pb, pc, n)
+        out = bfp.unpack(f, pc, n)
+        del pc
+        want = oracle.binop(op, e, m, 0, a, b, nthreads=8)
+        assert np.array_equal(out[tidx].cpu().numpy().astype(np.uint32), want), op
+        fused = torch.empty_like(da)
+        bfp.bfp_binop_std(op, f, da, db, fused, n)
+        assert torch.equal(fused, out), op
+        del out, fused
+    torch.cuda.synchronize()
