@@ -145,11 +145,21 @@ _SIGS = {
 
 
 def lib():
-    """Load libbfp.so; raise if it is not built."""
+    """Load libbfp.so; raise if it is not built.
+
+    torch is imported first when it is installed: PyTorch for ROCm ships its
+    own HIP runtime, and libbfp.so must bind to that one.  Loaded the other
+    way round, the process ends up with two HIP runtimes (the system one for
+    libbfp.so, torch's for the tensors and streams passed to it), and the
+    library's allocations and launches fail."""
     global _lib
     if _lib is None:
         if not os.path.exists(LIB_PATH):
             raise ImportError("libbfp.so is not built (python -m paper_1602_04716_amd.build)")
+        try:
+            import torch  # noqa: F401  (binds the HIP runtime before libbfp.so loads)
+        except ImportError:
+            pass
         L = ctypes.CDLL(LIB_PATH)
         for name, (res, args) in _SIGS.items():
             fn = getattr(L, name)

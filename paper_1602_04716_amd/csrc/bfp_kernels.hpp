@@ -110,8 +110,8 @@ __device__ __forceinline__ void mask_padding(WordR<R>* z, uint64_t off, uint64_t
 // c = a op b on resident bitslice vectors of n elements: every word of every
 // plane (padding words of c are zero).
 template <int E, int M, bool RZ, int OPC, int R>
-__global__ void __launch_bounds__(512) k_binop(const uint32_t* a, const uint32_t* b, uint32_t* c,
-                                               uint64_t gpad, uint64_t n, uint32_t negb) {
+__device__ __forceinline__ void binop_body(const uint32_t* a, const uint32_t* b, uint32_t* c, uint64_t gpad,
+                                           uint64_t n, uint32_t negb) {
   constexpr int B = 1 + E + M;
   const uint64_t nt = gpad / R;
   const uint64_t stride = (uint64_t)gridDim.x * blockDim.x;
@@ -128,6 +128,12 @@ __global__ void __launch_bounds__(512) k_binop(const uint32_t* a, const uint32_t
 #pragma unroll
     for (int k = 0; k < B; ++k) st_words<R>(c + (uint64_t)k * gpad + off, z[k]);
   }
+}
+
+template <int E, int M, bool RZ, int OPC, int R>
+__global__ void __launch_bounds__(512) k_binop(const uint32_t* a, const uint32_t* b, uint32_t* c,
+                                               uint64_t gpad, uint64_t n, uint32_t negb) {
+  binop_body<E, M, RZ, OPC, R>(a, b, c, gpad, n, negb);
 }
 
 // Load the 32 R standard elements starting at element e0 (C bytes each) as
@@ -318,8 +324,8 @@ __global__ void __launch_bounds__(512) k_unpack(const uint32_t* planes, uint8_t*
 
 // Fused standard-in / standard-out op: transposes and circuit in registers.
 template <int E, int M, bool RZ, int OPC>
-__global__ void __launch_bounds__(512) k_binop_std(const uint8_t* a, const uint8_t* b, uint8_t* c,
-                                                   uint64_t n, uint32_t negb) {
+__device__ __forceinline__ void binop_std_body(const uint8_t* a, const uint8_t* b, uint8_t* c, uint64_t n,
+                                               uint32_t negb) {
   constexpr int B = 1 + E + M;
   constexpr int C = B <= 8 ? 1 : (B <= 16 ? 2 : (B <= 32 ? 4 : 8));
   const uint64_t groups = (n + 31) / 32;
@@ -347,6 +353,25 @@ __global__ void __launch_bounds__(512) k_binop_std(const uint8_t* a, const uint8
   }
 }
 
+template <int E, int M, bool RZ, int OPC>
+__global__ void __launch_bounds__(512) k_binop_std(const uint8_t* a, const uint8_t* b, uint8_t* c, uint64_t n,
+                                                   uint32_t negb) {
+  binop_std_body<E, M, RZ, OPC>(a, b, c, n, negb);
+}
+
+// The wide formats' fused kernels hold two 64-word operands and their
+// transposes at once: blocks of at most 256 threads let the compiler use 512
+// registers per lane (accumulation registers included) instead of spilling
+// to scratch (measured at (11,52) mul: 234 registers spilled under the
+// 512-thread bound).  The bitslice kernels keep the 512-thread bound: for
+// them a few spilled registers cost less than halving the resident waves
+// (binary64 mul 645 us against 836 us at 2^26 elements).
+template <int E, int M, bool RZ, int OPC>
+__global__ void __launch_bounds__(256) k_binop_std_w(const uint8_t* a, const uint8_t* b, uint8_t* c, uint64_t n,
+                                                     uint32_t negb) {
+  binop_std_body<E, M, RZ, OPC>(a, b, c, n, negb);
+}
+
 // ---------------------------------------------------------------------------
 // Launchers and the registry of compiled variants
 // ---------------------------------------------------------------------------
@@ -368,6 +393,8 @@ struct Registry {
   // two-op chains: [e][m][opclass of op1][opclass of op2][rz], op classes
   // 0 (add/sub) and 1 (mul)
   ChainLauncher chain[kMaxE + 1][kMaxM + 1][2][2][2] = {};
+  // largest block the format's binop kernels are compiled for (0: none)
+  int max_block[kMaxE + 1][kMaxM + 1] = {};
 };
 Registry& registry();
 
@@ -389,9 +416,19 @@ hipError_t launch_binop_std(const void* a, const void* b, void* c, uint64_t n, u
   return hipGetLastError();
 }
 
+template <int E, int M, bool RZ, int OPC>
+hipError_t launch_binop_std_w(const void* a, const void* b, void* c, uint64_t n, uint32_t negb, unsigned grid,
+                              unsigned block, hipStream_t s) {
+  hipLaunchKernelGGL((k_binop_std_w<E, M, RZ, OPC>), dim3(grid), dim3(block), 0, s,
+                     static_cast<const uint8_t*>(a), static_cast<const uint8_t*>(b), static_cast<uint8_t*>(c),
+                     n, negb);
+  return hipGetLastError();
+}
+
 template <int E, int M>
 void register_format() {
   Registry& r = registry();
+  r.max_block[E][M] = 512;
   r.binop[E][M][0][0][0] = launch_binop<E, M, false, 0, 1>;
   r.binop[E][M][0][1][0] = launch_binop<E, M, true, 0, 1>;
   r.binop[E][M][1][0][0] = launch_binop<E, M, false, 1, 1>;
@@ -417,11 +454,12 @@ void register_format() {
 template <int E, int M>
 void register_wide_format() {
   Registry& r = registry();
-#define BFP_WIDE_REG(OPC)                                         \
-  r.binop[E][M][OPC][0][0] = launch_binop<E, M, false, OPC, 1>;  \
-  r.binop[E][M][OPC][1][0] = launch_binop<E, M, true, OPC, 1>;   \
-  r.std_op[E][M][OPC][0] = launch_binop_std<E, M, false, OPC>;   \
-  r.std_op[E][M][OPC][1] = launch_binop_std<E, M, true, OPC>;
+  r.max_block[E][M] = 512;
+#define BFP_WIDE_REG(OPC)                                           \
+  r.binop[E][M][OPC][0][0] = launch_binop<E, M, false, OPC, 1>;    \
+  r.binop[E][M][OPC][1][0] = launch_binop<E, M, true, OPC, 1>;     \
+  r.std_op[E][M][OPC][0] = launch_binop_std_w<E, M, false, OPC>;   \
+  r.std_op[E][M][OPC][1] = launch_binop_std_w<E, M, true, OPC>;
   BFP_WIDE_REG(0)
   BFP_WIDE_REG(1)
   BFP_WIDE_REG(2)

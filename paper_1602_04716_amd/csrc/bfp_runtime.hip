@@ -94,7 +94,7 @@ void cfg_init_locked() {
           const bool valu_heavy = (o == 1 && m >= 15) || (o == 2 && m >= 10);
           const bool one_word_only = !registry().binop[e][m][o][r][1];
           c.words_per_lane = (B <= 8 || valu_heavy || one_word_only) ? 1 : 2;
-          c.block = B <= 8 ? 128 : 256;
+          c.block = B <= 8 ? 128 : 256;  // within every format's max_block
           c.blocks_per_cu = 0;
           c.pad = 0;
         }
@@ -370,8 +370,9 @@ bfp_status bfp_launch_set(int op, bfp_format f, const bfp_launch* cfg) {
   if (!format_ok(f)) return BFP_E_FORMAT;
   if (!cfg) return BFP_E_NULL;
   if (!cfg_valid(*cfg)) return BFP_E_ARG;
-  // the wide formats have one-word kernels only
+  // the wide formats have one-word kernels only, compiled for blocks of at most 256
   if (!registry().binop[f.e][f.m][opclass_of(op)][f.round][cfg->words_per_lane - 1]) return BFP_E_ARG;
+  if (cfg->block > registry().max_block[f.e][f.m]) return BFP_E_ARG;
   std::lock_guard<std::mutex> lk(g_cfg_mu);
   cfg_init_locked();
   g_cfg[opclass_of(op)][f.e][f.m][f.round] = *cfg;

@@ -95,6 +95,7 @@ extern "C" bfp_status bfp_autotune(int op, bfp_format f, uint64_t n_probe, int w
     if (!registry().binop[f.e][f.m][opclass_of(op)][f.round][wpl - 1]) continue;  // not compiled
     any = true;
     for (int blk : blocks) {
+      if (blk > registry().max_block[f.e][f.m]) continue;  // not compiled for such blocks
       for (int bpc : bpcs) {
         bfp_launch cfg;
         cfg.words_per_lane = wpl;

@@ -166,3 +166,21 @@ def test_gate_counts_positive():
     assert bfp.bfp_gate_count(4, bfp.fmt(5, 10)) == -1
     assert bfp.bfp_gate_count("add", bfp.fmt(5, 10)) == bfp.bfp_gate_count("sub", bfp.fmt(5, 10))
     assert bfp.bfp_gate_count("add", bfp.fmt(7, 3)) == -1
+
+
+def test_one_hip_runtime_per_process():
+    """Loading the binding first and torch afterwards leaves one HIP runtime in
+    the process (the binding binds torch's before libbfp.so loads)."""
+    import subprocess
+    import sys
+    code = ("import sys; sys.path.insert(0, %r)\n"
+            "from paper_1602_04716_amd import bfp\n"
+            "bfp.lib()\n"
+            "import torch\n"
+            "print(sorted(set(l.split()[-1] for l in open('/proc/self/maps') if 'amdhip64' in l)))\n"
+            % os.path.dirname(os.path.dirname(os.path.abspath(__file__))))
+    out = subprocess.run([sys.executable, "-c", code], capture_output=True, text=True, timeout=300)
+    assert out.returncode == 0, out.stderr[-2000:]
+    import ast
+    runtimes = ast.literal_eval(out.stdout.strip().splitlines()[-1])
+    assert len(runtimes) == 1, runtimes
