@@ -1,4 +1,4 @@
-"""Benchmark: bitslice custom-precision FP add/sub/mul on one MI355X.
+"""Benchmark: bitslice custom-precision FP on one MI355X.
 
 Workload (default): 2^26-element vectors in (5,10) and (8,7), operands
 N(0,1) * 2^U(-8,8) mapped to the format, 64-element lane words,
@@ -15,8 +15,10 @@ Also printed in the same JSON line:
                 HIP events around each group of its launches on the kernels'
                 stream (the first, event-free pass gives ``value``);
   kernels       every kernel's mean duration and rates, measured the same way;
-  batched       (with --batched) 4096 mixed vectors: one persistent launch vs
-                one launch per vector;
+  batched       4096 mixed vectors: one persistent launch vs one launch per
+                vector (skipped with --no-batched);
+  serving       the serving loop at saturation and at Poisson loads of 0.5
+                and 0.9 of it (skipped with --no-serving);
   div           division (Table 1, Div) on resident bitslice vectors of the
                 same size and formats, the launch table's configuration:
                 elements/s and its bitwise VALU rate against peak;
@@ -27,7 +29,8 @@ Also printed in the same JSON line:
   chain         d = a*b + c on the same vectors: one two-op chain kernel
                 (intermediate in registers, 4 vectors through HBM) against
                 the two separate launches (6 vectors);
-  cpu_baseline  the oracle timed on this host on a bounded sample.
+  cpu_baseline  the oracle timed on this host on a bounded sample (threads
+                and one thread), with the CPU model.
 """
 from __future__ import annotations
 

@@ -8,7 +8,10 @@
  * configuration (Section 1 contributions; Section 5.1); here the same three
  * numbers are a runtime argument, `bfp_format`, and the library carries the
  * compiled circuits of every format e in {3,4,5,6,8} x m in
- * {1,2,3,5,7,10,15,23}.
+ * {1,2,3,5,7,10,15,23} and of the wide formats (8,31), (11,20), (11,40) and
+ * (11,52) = binary64 (the wide formats have the elementwise and fused
+ * standard ops, not the chain, batch and serving calls).  k-bit integer
+ * vectors share the layout (see bfp_int_binop).
  *
  * Layouts (Section 2, Figure 1; Section 4, Figure 3):
  *   standard  one element per unsigned container of 1, 2, 4 or 8 bytes
@@ -27,9 +30,9 @@
  *             word).  Padding bits past element n are zero after bfp_pack
  *             and stay zero through every operation.
  *
- * Semantics: each result is the exact sum, difference or product rounded
- * once, to nearest with ties to even (BFP_RNE) or toward zero (BFP_RZ) -- the
- * two modes of Section 4.  Exponent bias 2^(e-1)-1; exponent field 0 holds
+ * Semantics: each result is the exact sum, difference, product or quotient
+ * rounded once, to nearest with ties to even (BFP_RNE) or toward zero
+ * (BFP_RZ) -- the two modes of Section 4.  Exponent bias 2^(e-1)-1; exponent field 0 holds
  * zero and subnormals; all ones holds Inf (mantissa 0) and NaN.  Overflow
  * gives Inf (RNE) or the largest finite value (RZ).  An exact zero sum of
  * opposite-signed operands is +0.  NaN results are the canonical quiet NaN
