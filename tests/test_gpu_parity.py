@@ -246,3 +246,28 @@ def test_beyond_32_bit_offsets():
         assert torch.equal(fused, out), op
         del out, fused
     torch.cuda.synchronize()
+
+
+@pytest.mark.parametrize("e,m", FORMATS + inputs.wide_formats())
+def test_small_ragged_lengths_all_formats(e, m):
+    """Three random lengths in [1, 3000] per format (a partial last word and
+    a partial last tile), every op, both modes, both paths, against the oracle."""
+    B = 1 + e + m
+    rng = np.random.default_rng(500 + 13 * e + m)
+    dt = {1: np.uint8, 2: np.uint16, 4: np.uint32, 8: np.uint64}[oracle.container_bytes(e, m)]
+    for n in rng.integers(1, 3001, 3):
+        n = int(n)
+        a = rng.integers(0, 1 << B, n, dtype=np.uint64).astype(dt)
+        b = rng.integers(0, 1 << B, n, dtype=np.uint64).astype(dt)
+        da, db = _dev(a), _dev(b)
+        for mode in (0, 1):
+            f = bfp.fmt(e, m, mode)
+            pa, pb = bfp.pack(f, da), bfp.pack(f, db)
+            for op in OPS:
+                want = oracle.binop(op, e, m, mode, a, b).astype(np.uint64)
+                pc = bfp.empty_bitslice(f, n)
+                bfp.bfp_binop(op, f, pa, pb, pc, n)
+                assert np.array_equal(_host(pc), oracle.pack(e, m, want)), (n, op, mode, "bitslice")
+                dc = torch.empty_like(da)
+                bfp.bfp_binop_std(op, f, da, db, dc, n)
+                assert np.array_equal(_host(dc).astype(np.uint64), want), (n, op, mode, "std")
