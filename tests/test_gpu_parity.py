@@ -271,3 +271,61 @@ def test_small_ragged_lengths_all_formats(e, m):
                 dc = torch.empty_like(da)
                 bfp.bfp_binop_std(op, f, da, db, dc, n)
                 assert np.array_equal(_host(dc).astype(np.uint64), want), (n, op, mode, "std")
+
+
+@pytest.mark.parametrize("e,m", [(5, 10), (8, 7)])
+def test_all_2_32_pairs_against_device_arithmetic(e, m):
+    """Every pair of 16-bit patterns (2^32 pairs) of binary16 and bfloat16,
+    add/sub/mul/div to nearest even, on the fused path against the GPU's own
+    arithmetic in torch (computed in float32 and rounded once to the 16-bit
+    type, which is the correctly rounded result since 24 >= 2p + 2); NaN
+    results compared as NaN."""
+    f = bfp.fmt(e, m)
+    dt = torch.float16 if (e, m) == (5, 10) else torch.bfloat16
+    chunk = 1 << 28
+    for base in range(0, 1 << 32, chunk):
+        i = torch.arange(base, base + chunk, device="cuda", dtype=torch.int64)
+        a = (i >> 16).to(torch.int32).to(torch.int16)
+        b = (i & 0xFFFF).to(torch.int32).to(torch.int16)
+        del i
+        fa, fb = a.view(dt).float(), b.view(dt).float()
+        for op in OPS:
+            ours = torch.empty_like(a)
+            bfp.bfp_binop_std(op, f, a, b, ours, chunk)
+            r = {"add": fa + fb, "sub": fa - fb, "mul": fa * fb, "div": fa / fb}[op].to(dt)
+            same = (ours == r.view(torch.int16)) | (torch.isnan(ours.view(dt)) & torch.isnan(r))
+            if not bool(same.all()):
+                bad = torch.nonzero(~same)[:5, 0]
+                pytest.fail("%s (%d,%d): %d mismatches, e.g. %s" % (
+                    op, e, m, int((~same).sum()),
+                    [(hex(int(a[k]) & 0xFFFF), hex(int(b[k]) & 0xFFFF), hex(int(ours[k]) & 0xFFFF),
+                      hex(int(r.view(torch.int16)[k]) & 0xFFFF)) for k in bad.tolist()]))
+            del ours, r, same
+        del a, b, fa, fb
+    torch.cuda.synchronize()
+
+
+def test_binary32_against_device_arithmetic():
+    """(8,23) = binary32: 2^28 random pairs (uniform bit patterns, and pairs
+    near cancellation) on the bitslice path against the GPU's own float32
+    add/sub/mul/div (round to nearest even), NaN results compared as NaN."""
+    f = bfp.fmt(8, 23)
+    n = 1 << 28
+    g = torch.Generator(device="cuda")
+    g.manual_seed(32)
+    a = torch.randint(-(1 << 31), 1 << 31, (n,), dtype=torch.int64, device="cuda", generator=g).to(torch.int32)
+    b = torch.randint(-(1 << 31), 1 << 31, (n,), dtype=torch.int64, device="cuda", generator=g).to(torch.int32)
+    q = n // 4
+    b[:q] = (a[:q] + torch.randint(0, 3, (q,), dtype=torch.int32, device="cuda", generator=g)) ^ (-(1 << 31))
+    pa, pb = bfp.pack(f, a), bfp.pack(f, b)
+    fa, fb = a.view(torch.float32), b.view(torch.float32)
+    for op in OPS:
+        pc = bfp.empty_bitslice(f, n)
+        bfp.bfp_binop(op, f, pa, pb, pc, n)
+        ours = bfp.unpack(f, pc, n).view(torch.int32)
+        del pc
+        r = {"add": fa + fb, "sub": fa - fb, "mul": fa * fb, "div": fa / fb}[op]
+        same = (ours == r.view(torch.int32)) | (torch.isnan(ours.view(torch.float32)) & torch.isnan(r))
+        assert bool(same.all()), (op, int((~same).sum()))
+        del ours, r, same
+    torch.cuda.synchronize()
