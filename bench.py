@@ -469,6 +469,12 @@ def main():
     else:
         roof = {"kernel": dom, "bound": "hbm", "achieved": dk["GB/s"], "peak": HBM_PEAK / 1e9, "unit": "GB/s",
                 "frac": dk["hbm_frac"], "traffic": None}
+    # practical ceiling on this machine: the library's plain 16-byte-vector copy
+    # of 512 MiB (read and write), timed with events on the same stream
+    copy_gbps = bfp.bfp_measure_copy(512 << 20, 10, stream)
+    roof["copy_GBps"] = copy_gbps
+    if roof["unit"] == "GB/s":
+        roof["frac_of_copy"] = roof["achieved"] / copy_gbps
     roof["us_per_launch"] = dk["us"]
     roof["algorithmic_bytes_per_launch"] = dk["bytes"]
     roof["device_kernel"] = device_kernel(dom)

@@ -235,6 +235,15 @@ bfp_status bfp_launch_save(const char* path);
 bfp_status bfp_autotune(int op, bfp_format f, uint64_t n_probe, int words_per_lane_mask, int reps, void* stream,
                         bfp_launch* best, double* best_us);
 
+/* Measurement helper (not an operation of the paper): the bandwidth of a
+ * plain device copy of `bytes` bytes (16-byte vector loads and stores,
+ * grid-stride), the practical HBM ceiling on this device.  Allocates and
+ * frees two buffers of `bytes` bytes, runs `reps` timed copies on `stream`
+ * after two warm-up copies, synchronises `stream`, and returns read + write
+ * GB/s in *gbps.  2^20 <= bytes <= 2^36, bytes a multiple of 16,
+ * 1 <= reps <= 1000. */
+bfp_status bfp_measure_copy(uint64_t bytes, int reps, void* stream, double* gbps);
+
 /* Gate count of one circuit instance (one group of 32 elements per word),
  * constants folded: the cost model of Table 1.  Returns -1 if the format
  * is not compiled. */

@@ -111,6 +111,8 @@ _SIGS = {
     "bfp_launch_get": (ctypes.c_int, [ctypes.c_int, bfp_format, ctypes.POINTER(bfp_launch)]),
     "bfp_launch_set": (ctypes.c_int, [ctypes.c_int, bfp_format, ctypes.POINTER(bfp_launch)]),
     "bfp_launch_load": (ctypes.c_int, [ctypes.c_char_p]),
+    "bfp_measure_copy": (ctypes.c_int, [ctypes.c_uint64, ctypes.c_int, ctypes.c_void_p,
+                                        ctypes.POINTER(ctypes.c_double)]),
     "bfp_launch_save": (ctypes.c_int, [ctypes.c_char_p]),
     "bfp_gate_count": (ctypes.c_long, [ctypes.c_int, bfp_format]),
     "bfp_autotune": (ctypes.c_int, [ctypes.c_int, bfp_format, ctypes.c_uint64, ctypes.c_int, ctypes.c_int,
@@ -337,6 +339,13 @@ def bfp_launch_get(op, f) -> bfp_launch:
 def bfp_launch_set(op, f, words_per_lane: int, block: int, blocks_per_cu: int):
     cfg = bfp_launch(words_per_lane, block, blocks_per_cu, 0)
     _check(lib().bfp_launch_set(_op(op), f, ctypes.byref(cfg)), "bfp_launch_set")
+
+
+def bfp_measure_copy(nbytes: int, reps: int = 10, stream=None) -> float:
+    """Read + write GB/s of a plain 16-byte-vector device copy of nbytes."""
+    g = ctypes.c_double()
+    _check(lib().bfp_measure_copy(nbytes, reps, _stream(stream), ctypes.byref(g)), "bfp_measure_copy")
+    return g.value
 
 
 def bfp_launch_load(path: str):

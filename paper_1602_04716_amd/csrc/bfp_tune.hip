@@ -43,6 +43,13 @@ __global__ void k_sweep_read(const u32x4* p, uint64_t n4, uint32_t* sink) {
   if (acc == 0x9E3779B9u) sink[threadIdx.x & 63] = acc;  // keeps the loads live; practically never taken
 }
 
+// Plain copy, 16 bytes per lane per iteration, grid-stride: the practical
+// HBM ceiling the kernels' fractions are read against.
+__global__ void k_copy16(const u32x4* src, u32x4* dst, uint64_t n4) {
+  for (uint64_t i = blockIdx.x * (uint64_t)blockDim.x + threadIdx.x; i < n4; i += (uint64_t)gridDim.x * blockDim.x)
+    dst[i] = src[i];
+}
+
 struct DevBuf {
   void* p = nullptr;
   ~DevBuf() {
@@ -54,6 +61,39 @@ struct DevBuf {
 }  // namespace bfp
 
 using namespace bfp;
+
+extern "C" bfp_status bfp_measure_copy(uint64_t bytes, int reps, void* stream, double* gbps) {
+  if (!gbps) return BFP_E_NULL;
+  if (bytes < (1u << 20) || bytes > (1ull << 36) || (bytes & 15u) || reps < 1 || reps > 1000) return BFP_E_ARG;
+  hipStream_t s = (hipStream_t)stream;
+  DevBuf src, dst;
+  if (hipMalloc(&src.p, bytes) != hipSuccess || hipMalloc(&dst.p, bytes) != hipSuccess) return BFP_E_NOMEM;
+  const uint64_t n4 = bytes / 16;
+  hipLaunchKernelGGL(k_fill_random, dim3(2048), dim3(256), 0, s, (uint32_t*)src.p, bytes / 4, 0x4242u);
+  const unsigned grid = (unsigned)std::min<uint64_t>((n4 + 255) / 256, 256ull * 64);
+  for (int w = 0; w < 2; ++w)
+    hipLaunchKernelGGL(k_copy16, dim3(grid), dim3(256), 0, s, (const u32x4*)src.p, (u32x4*)dst.p, n4);
+  if (hipGetLastError() != hipSuccess) return BFP_E_HIP;
+  hipEvent_t e0, e1;
+  if (hipEventCreate(&e0) != hipSuccess) return BFP_E_HIP;
+  if (hipEventCreate(&e1) != hipSuccess) {
+    (void)hipEventDestroy(e0);
+    return BFP_E_HIP;
+  }
+  bfp_status st = BFP_OK;
+  float ms = 0.f;
+  if (hipEventRecord(e0, s) != hipSuccess) st = BFP_E_HIP;
+  for (int r = 0; r < reps && st == BFP_OK; ++r)
+    hipLaunchKernelGGL(k_copy16, dim3(grid), dim3(256), 0, s, (const u32x4*)src.p, (u32x4*)dst.p, n4);
+  if (st == BFP_OK && hipGetLastError() != hipSuccess) st = BFP_E_HIP;
+  if (st == BFP_OK && hipEventRecord(e1, s) != hipSuccess) st = BFP_E_HIP;
+  if (st == BFP_OK && hipEventSynchronize(e1) != hipSuccess) st = BFP_E_HIP;
+  if (st == BFP_OK && hipEventElapsedTime(&ms, e0, e1) != hipSuccess) st = BFP_E_HIP;
+  (void)hipEventDestroy(e0);
+  (void)hipEventDestroy(e1);
+  if (st == BFP_OK) *gbps = 2.0 * (double)bytes / ((double)ms / reps * 1e-3) / 1e9;
+  return st;
+}
 
 extern "C" bfp_status bfp_autotune(int op, bfp_format f, uint64_t n_probe, int words_per_lane_mask, int reps,
                                    void* stream, bfp_launch* best_out, double* best_us_out) {

@@ -127,6 +127,11 @@ def test_argument_errors_before_any_device_work():
     assert L.bfp_chain2(2, 0, w, 16, 32, 48, 64, 1, None) == -1
     assert L.bfp_axpy(w, 0, 16, 32, 48, 1, None) == -1
     assert bfp.bfp_status_string(-5).startswith("HIP")
+    g = ctypes.c_double()
+    assert L.bfp_measure_copy(1 << 10, 10, None, ctypes.byref(g)) == -6   # too small
+    assert L.bfp_measure_copy((1 << 20) + 8, 10, None, ctypes.byref(g)) == -6
+    assert L.bfp_measure_copy(1 << 20, 0, None, ctypes.byref(g)) == -6
+    assert L.bfp_measure_copy(1 << 20, 10, None, None) == -2
 
 
 def test_launch_table_roundtrip(tmp_path):

@@ -63,3 +63,9 @@ def test_autotune_errors():
         bfp.bfp_autotune("add", f, 1024, 0, 1)
     with pytest.raises(bfp.BfpError):
         bfp.bfp_autotune("add", bfp.fmt(7, 4), 1024, 3, 1)
+
+
+def test_measure_copy_is_plausible():
+    """The copy-bandwidth helper reports a rate between 1 TB/s and the 8 TB/s peak."""
+    g = bfp.bfp_measure_copy(256 << 20, 5)
+    assert 1000.0 < g < 8000.0, g
