@@ -29,6 +29,9 @@ Also printed in the same JSON line:
   chain         d = a*b + c on the same vectors: one two-op chain kernel
                 (intermediate in registers, 4 vectors through HBM) against
                 the two separate launches (6 vectors);
+  small         the 65,536-element (5,2) workload (launch-latency bound): the
+                fused standard-in/standard-out add, and pack + add + unpack
+                as three launches, microseconds per call;
   cpu_baseline  the oracle timed on this host on a bounded sample (threads
                 and one thread), with the CPU model.
 """
@@ -67,6 +70,7 @@ def parse():
     ap.add_argument("--no-chain", action="store_true")
     ap.add_argument("--no-int", action="store_true")
     ap.add_argument("--no-wide", action="store_true")
+    ap.add_argument("--no-small", action="store_true")
     ap.add_argument("--div-reps", type=int, default=10)
     ap.add_argument("--serving-requests", type=int, default=20000)
     return ap.parse_args()
@@ -218,6 +222,44 @@ def bench_chain(torch, bfp, dev, n, reps):
             "valu_frac": G * n / 32 / (us * 1e-6) / VALU_PEAK,
             "device_kernel": "bfp::k_chain2<%d, %d, false, 1, 0, 1>" % (e, m)}
         del pa, pb, pc, pd, pt
+    return out
+
+
+def bench_small(torch, bfp, dev, reps=200):
+    """65,536 uniform (5,2) patterns without NaN/Inf, add to nearest even:
+    the fused kernel and the three-kernel path, `reps` back-to-back calls
+    between two events."""
+    from paper_1602_04716_amd import inputs
+    s = torch.cuda.current_stream()
+    n = 65536
+    f = bfp.fmt(5, 2)
+    a = torch.from_numpy(inputs.plain_8bit(n, seed=1)).to(dev)
+    b = torch.from_numpy(inputs.plain_8bit(n, seed=101)).to(dev)
+    c = torch.empty_like(a)
+    pa, pb, pc = (bfp.empty_bitslice(f, n, dev) for _ in range(3))
+
+    def fused():
+        bfp.bfp_binop_std("add", f, a, b, c, n, s)
+
+    def three():
+        bfp.bfp_pack(f, a, pa, n, s)
+        bfp.bfp_pack(f, b, pb, n, s)
+        bfp.bfp_add(f, pa, pb, pc, n, s)
+        bfp.bfp_unpack(f, pc, c, n, s)
+
+    out = {"n": n, "format": "(5,2)"}
+    for name, fn in (("fused", fused), ("pack_add_unpack", three)):
+        for _ in range(10):
+            fn()
+        ev0, ev1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+        ev0.record(s)
+        for _ in range(reps):
+            fn()
+        ev1.record(s)
+        torch.cuda.synchronize()
+        us = ev0.elapsed_time(ev1) * 1e3 / reps
+        out[name + "_us"] = us
+        out[name + "_elements_per_s"] = n / (us * 1e-6)
     return out
 
 
@@ -514,6 +556,8 @@ def main():
         res["int"] = bench_int(torch, bfp, dev, n, args.div_reps)
     if not args.no_wide:
         res["wide"] = bench_wide(torch, bfp, dev, n, args.div_reps)
+    if not args.no_small:
+        res["small"] = bench_small(torch, bfp, dev)
     if not args.no_cpu_baseline:
         res["cpu_baseline"] = cpu_baseline()
     print(json.dumps(res), flush=True)
