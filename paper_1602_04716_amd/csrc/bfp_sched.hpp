@@ -162,7 +162,25 @@ class Scheduler {
 
   // One scheduling pass (caller holds mutex): collect finished ticks, admit,
   // launch.  Returns true if anything changed.
+  // One scheduling pass: completions, FIFO admission, and a launch of the
+  // admitted requests on a free stream.  Equivalent to collect(), launching
+  // the returned batch, and commit().
   bool step() {
+    std::vector<SchedRequest> batch;
+    bool changed = collect(&batch);
+    if (!batch.empty()) {
+      commit(&batch, ex_.launch(batch));
+      changed = true;
+    }
+    return changed;
+  }
+
+  // Completions and admission; if a stream is free and requests were
+  // admitted, moves them into *batch (stamped with their launch time) and
+  // reserves the stream.  The caller launches the batch on the executor --
+  // without the scheduler's lock if it holds one, since only the scheduling
+  // thread touches the executor -- and then calls commit().
+  bool collect(std::vector<SchedRequest>* batch) {
     bool changed = false;
     // completions
     std::vector<SchedRequest> done;
@@ -199,31 +217,40 @@ class Scheduler {
       stats_.admitted++;
       changed = true;
     }
-    // launch a tick on a free stream
+    // hand a tick to the caller if a stream is free
     if (!next_.empty() && inflight_ticks_ < Executor::kStreams) {
       const int64_t t = now_ns();
       for (auto& r : next_) r.t_launch = t;
-      const int st = ex_.launch(next_);
-      if (st != 0) {
-        for (auto& r : next_) {  // failed launch: release the results, report the error
-          free_resident(r.c_handle);
-          r.c_handle = 0;
-          r.status = st;
-          r.t_done = now_ns();
-          completed_.push_back(r);
-          stats_.completed++;
-        }
-      } else {
-        inflight_reqs_ += (int)next_.size();
-        inflight_ticks_++;
-        stats_.ticks++;
-        if (next_.size() > stats_.max_tick_requests) stats_.max_tick_requests = next_.size();
-        if ((uint64_t)inflight_ticks_ > stats_.max_inflight_ticks) stats_.max_inflight_ticks = inflight_ticks_;
-      }
+      batch->swap(next_);
       next_.clear();
+      inflight_ticks_++;          // the stream is taken until commit() or the tick's completion
+      inflight_reqs_ += (int)batch->size();
       changed = true;
     }
     return changed;
+  }
+
+  // Record the outcome of launching a batch from collect(): st == 0 keeps it
+  // in flight until the executor reports it done; otherwise its results are
+  // released and it completes with status st.
+  void commit(std::vector<SchedRequest>* batch, int st) {
+    if (st != 0) {
+      inflight_ticks_--;
+      inflight_reqs_ -= (int)batch->size();
+      for (auto& r : *batch) {  // failed launch: release the results, report the error
+        free_resident(r.c_handle);
+        r.c_handle = 0;
+        r.status = st;
+        r.t_done = now_ns();
+        completed_.push_back(r);
+        stats_.completed++;
+      }
+    } else {
+      stats_.ticks++;
+      if (batch->size() > stats_.max_tick_requests) stats_.max_tick_requests = batch->size();
+      if ((uint64_t)inflight_ticks_ > stats_.max_inflight_ticks) stats_.max_inflight_ticks = inflight_ticks_;
+    }
+    batch->clear();
   }
 
   size_t take_completed(SchedRequest* out, size_t max) {

@@ -181,8 +181,18 @@ namespace {
 void worker_loop(bfp_server* s) {
   (void)hipSetDevice(s->device);
   std::unique_lock<std::mutex> lk(s->sched->mutex());
+  std::vector<SchedRequest> batch;
   while (!s->stop.load()) {
-    const bool changed = s->sched->step();
+    bool changed = s->sched->collect(&batch);
+    if (!batch.empty()) {
+      // launch without the lock: submitters and pollers proceed meanwhile;
+      // only this thread touches the executor
+      lk.unlock();
+      const int st = s->ex.launch(batch);
+      lk.lock();
+      s->sched->commit(&batch, st);
+      changed = true;
+    }
     if (s->sched->idle()) {
       s->cv.wait_for(lk, std::chrono::milliseconds(2));
     } else if (!changed) {
