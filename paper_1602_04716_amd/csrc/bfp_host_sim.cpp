@@ -248,6 +248,7 @@ struct SimServer {
   FakeExecutor ex;
   bfp::Scheduler<FakeExecutor> sched;
   uint64_t next_id = 1;
+  std::vector<bfp::SchedRequest> batch;  // collected, not yet launched
   SimServer(uint64_t budget, int slots) : sched(ex, budget, slots) {}
 };
 }  // namespace
@@ -272,6 +273,19 @@ uint64_t simsrv_submit(void* p, uint64_t n, uint64_t c_bytes) {
   return r.id;
 }
 int simsrv_step(void* p) { return static_cast<SimServer*>(p)->sched.step() ? 1 : 0; }
+// The serving worker's split step: collect (returns the batch size), then,
+// after any number of other calls, launch the batch and commit it.
+int simsrv_collect(void* p) {
+  auto* s = static_cast<SimServer*>(p);
+  s->sched.collect(&s->batch);
+  return (int)s->batch.size();
+}
+void simsrv_launch_commit(void* p) {
+  auto* s = static_cast<SimServer*>(p);
+  if (s->batch.empty()) return;
+  const int st = s->ex.launch(s->batch);
+  s->sched.commit(&s->batch, st);
+}
 void simsrv_release(void* p, int k) { static_cast<SimServer*>(p)->ex.releasable += k; }
 void simsrv_fail_next(void* p) { static_cast<SimServer*>(p)->ex.fail_next = 1; }
 int simsrv_running_ticks(void* p) { return (int)static_cast<SimServer*>(p)->ex.running.size(); }

@@ -22,6 +22,7 @@ def L():
         "simsrv_create": (VP, [U64, ctypes.c_int]), "simsrv_destroy": (None, [VP]),
         "simsrv_put": (U32, [VP, U64, U64]), "simsrv_free": (ctypes.c_int, [VP, U32]),
         "simsrv_submit": (U64, [VP, U64, U64]), "simsrv_step": (ctypes.c_int, [VP]),
+        "simsrv_collect": (ctypes.c_int, [VP]), "simsrv_launch_commit": (None, [VP]),
         "simsrv_release": (None, [VP, ctypes.c_int]), "simsrv_fail_next": (None, [VP]),
         "simsrv_running_ticks": (ctypes.c_int, [VP]),
         "simsrv_take": (ctypes.c_int, [VP, VP, VP, VP, ctypes.c_int]), "simsrv_stats": (None, [VP, VP]),
@@ -156,5 +157,58 @@ def test_launch_failure_releases_results(L):
     L.simsrv_step(s)
     out = take(L, s)
     assert [x[0] for x in out] == ids and all(x[2] == -5 and x[1] == 0 for x in out)
+    assert stats(L, s)["used"] == used0
+    L.simsrv_destroy(s)
+
+
+def test_split_step_submissions_during_launch(L):
+    """The worker collects a batch under the lock and launches it unlocked:
+    requests submitted in between count against the slots the batch holds,
+    wait in FIFO order, and go out in the next tick on the other stream."""
+    s = L.simsrv_create(1 << 30, 6)
+    a = [L.simsrv_submit(s, 10, 256) for _ in range(4)]
+    assert L.simsrv_collect(s) == 4                      # batch taken, stream reserved
+    st = stats(L, s)
+    assert st["inflight"] == 4 and st["pending"] == 0
+    b = [L.simsrv_submit(s, 10, 256) for _ in range(4)]  # arrive during the launch
+    assert stats(L, s)["pending"] == 4
+    L.simsrv_launch_commit(s)
+    assert L.simsrv_running_ticks(s) == 1
+    assert L.simsrv_collect(s) == 2                      # 2 slots left; the second stream is free
+    L.simsrv_launch_commit(s)
+    st = stats(L, s)
+    assert L.simsrv_running_ticks(s) == 2 and st["inflight"] == 6 and st["pending"] == 2
+    assert L.simsrv_collect(s) == 0                      # no slot and no stream
+    L.simsrv_release(s, 1)
+    L.simsrv_step(s)                                     # first tick done; its slots admit b[2:]
+    assert [x[0] for x in take(L, s)] == a
+    L.simsrv_release(s, 2)
+    L.simsrv_step(s)
+    L.simsrv_step(s)
+    assert [x[0] for x in take(L, s)] == b
+    st = stats(L, s)
+    assert st["ticks"] == 3 and st["max_inflight_ticks"] == 2 and st["inflight"] == 0
+    L.simsrv_destroy(s)
+
+
+def test_split_step_failure_releases_results(L):
+    s = L.simsrv_create(1 << 20, 100)
+    used0 = stats(L, s)["used"]
+    ids = [L.simsrv_submit(s, 10, 4096) for _ in range(3)]
+    assert L.simsrv_collect(s) == 3
+    more = [L.simsrv_submit(s, 10, 4096) for _ in range(2)]
+    L.simsrv_fail_next(s)
+    L.simsrv_launch_commit(s)
+    out = take(L, s)
+    assert [x[0] for x in out] == ids and all(x[2] == -5 and x[1] == 0 for x in out)
+    st = stats(L, s)
+    assert st["inflight"] == 0 and st["pending"] == 2 and st["used"] == used0
+    L.simsrv_step(s)
+    L.simsrv_release(s, 1)
+    L.simsrv_step(s)
+    done = take(L, s)
+    assert [x[0] for x in done] == more and all(x[2] == 0 for x in done)
+    for (_id, h, _st) in done:
+        assert L.simsrv_free(s, h) == 0
     assert stats(L, s)["used"] == used0
     L.simsrv_destroy(s)
