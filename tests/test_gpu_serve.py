@@ -135,3 +135,46 @@ def test_native_replay_poisson_autofree():
                     ("add", bfp.fmt(5, 10), pool[(5, 10)][0], pool[(5, 10)][1], 10, 0)])
     assert srv.stats()["submitted"] == st["submitted"]
     srv.close()
+
+
+def test_full_size_mix_all_sweep_formats():
+    """The serving workload at its full shape: every sweep format resident at
+    2^22 elements, 600 requests of length log-uniform in 2^10..2^22 over
+    add/sub/mul/div, all submitted at once under the budget.  Each result
+    matches the oracle on 2048 sampled elements; every 15th request, run
+    alone, gives the same result planes."""
+    fmts = inputs.sweep_formats()
+    n0 = 1 << 22
+    srv = serving.Server(8 << 30, 256)
+    pool = serving.build_pool(srv, fmts, n0, seed=21, device="cuda")
+    host = _pool_host(srv, pool, fmts)
+    reqs = serving.request_stream(600, fmts, seed=22, nmin_log2=10, nmax_log2=22, nmax=n0, ops=serving.ALL_OPS)
+    res = serving.run(srv, pool, reqs, rate=None, rnd=0, keep_results=True)
+    assert res["errors"] == 0
+    st = srv.stats()
+    assert st["completed"] == 600 and st["high_water"] <= st["budget"]
+    rng = np.random.default_rng(23)
+    for k, rid in enumerate(res["ids"]):
+        op, (e, m), n = reqs[k]
+        f = bfp.fmt(e, m)
+        status, h, *_t = res["completions"][rid]
+        assert status == 0
+        out = torch.empty(n, dtype=bfp.container_dtype(f), device="cuda")
+        srv.get(h, f, out)
+        idx = np.sort(rng.choice(n, min(n, 2048), replace=False))
+        got = out.cpu().numpy()[idx].astype(np.uint32)
+        a, b = host[(e, m)]
+        want = oracle.binop(op, e, m, 0, a[idx], b[idx])
+        assert np.array_equal(got, want), (k, reqs[k])
+    for k in range(0, 600, 15):
+        op, (e, m), n = reqs[k]
+        f = bfp.fmt(e, m)
+        a, b, _n0 = pool[(e, m)]
+        rid = srv.submit(op, f, a, b, n)
+        srv.wait_idle()
+        comp = [c for c in srv.poll() if c.req_id == rid]
+        assert len(comp) == 1 and comp[0].status == 0
+        assert torch.equal(_result(srv, comp[0].result, f, n),
+                           _result(srv, res["completions"][res["ids"][k]][1], f, n)), (k, reqs[k])
+        srv.free(comp[0].result)
+    srv.close()
