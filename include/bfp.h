@@ -271,8 +271,8 @@ typedef struct {
 
 typedef struct bfp_batch_plan bfp_batch_plan;
 
-/* Validate `count` tasks, cut them into chunks sorted by circuit variant,
- * upload the descriptors and capture the graph on the current device.
+/* Validate `count` tasks, cut them into chunks grouped by circuit variant
+ * (slowest variants per word first, division last), upload the descriptors and capture the graph on the current device.
  * Errors: BFP_E_ARG (count 0, n 0), BFP_E_FORMAT, BFP_E_OP, BFP_E_NULL,
  * BFP_E_ALIGN, BFP_E_NOMEM, BFP_E_HIP.  On error *out is NULL. */
 bfp_status bfp_batch_plan_create(const bfp_task* tasks, uint32_t count, bfp_batch_plan** out);

@@ -2,10 +2,12 @@
 // persistent kernel, captured once in a HIP graph.
 //
 // Plan (host): every task (a op b -> c on bitslice vectors of one format) is
-// cut into chunks of at most kChunkWords words per plane; chunks are sorted
+// cut into chunks of at most kChunkWords words per plane; chunks are grouped
 // by circuit variant so that consecutive chunks run the same code (one
-// instruction-cache footprint at a time) and, within a variant, longest task
-// first.  Descriptors go to device memory once.
+// instruction-cache footprint at a time), the variants taken in decreasing
+// time per word so that the slowest chunks start first and the grid drains
+// on short ones, and, within a variant, longest task first.  Descriptors go
+// to device memory once.
 //
 // Device: a grid sized to the GPU's resident capacity; each block takes the
 // next chunk index from an atomic counter, reads the chunk's task, and
@@ -107,6 +109,8 @@ __global__ void __launch_bounds__(kBatchBlock) k_batch(const BatchTask* tasks, c
   }
 }
 
+constexpr int kBatchFormats = 40;  // format_index covers 5 exponent x 8 mantissa widths
+
 bool batch_format_ok(const bfp_format& f) { return format_index(f.e, f.m) >= 0 && f.round <= 1; }
 
 bool batch_task(const void* a, uint64_t na, const void* b, uint64_t nb, void* c, uint64_t n, bfp_format f, int op,
@@ -127,6 +131,29 @@ bool batch_task(const void* a, uint64_t na, const void* b, uint64_t nb, void* c,
   return true;
 }
 
+// Relative time per word of each variant's circuit: the larger of its HBM
+// traffic (two operands and a result of B planes, 4 bytes a plane-word, at
+// 8 TB/s: 1.5 ps per plane) and its gates (one 32-bit lane operation each, at
+// 256 CUs x 64 lanes x 2.4 GHz: 0.025 ps per gate), so one plane of traffic
+// weighs as much as 59 gates.  Computed once, from the circuits' gate counts.
+static const std::vector<uint32_t>& variant_cost() {
+  static const std::vector<uint32_t> cost = [] {
+    std::vector<uint32_t> c(kBatchFormats * kOpClasses * 2, 0);
+    const int ops[kOpClasses] = {BFP_ADD, BFP_MUL, BFP_DIV};
+#define BFP_COST_CASE(EE, MM)                                                          \
+  for (int oc = 0; oc < kOpClasses; ++oc)                                              \
+    for (int rz = 0; rz < 2; ++rz) {                                                   \
+      const long g = bfp_gate_count(ops[oc], bfp_format{EE, MM, (uint8_t)rz, 0});      \
+      c[(format_index(EE, MM) * kOpClasses + oc) * 2 + rz] =                           \
+          (uint32_t)std::max<long>(59L * (1 + EE + MM), g);                            \
+    }
+    BFP_FOR_EACH_FORMAT(BFP_COST_CASE)
+#undef BFP_COST_CASE
+    return c;
+  }();
+  return cost;
+}
+
 void batch_chunks(const std::vector<BatchTask>& dt, std::vector<BatchChunk>* out) {
   std::vector<BatchChunk>& chunks = *out;
   chunks.clear();
@@ -139,11 +166,13 @@ void batch_chunks(const std::vector<BatchTask>& dt, std::vector<BatchChunk>* out
       chunks.push_back(ch);
     }
   }
-  // division last, then variant order; within a variant, longer tasks
-  // first, then by position
+  // division last, then variants by decreasing time per word (ties by
+  // variant); within a variant, longer tasks first, then by position
+  const std::vector<uint32_t>& cost = variant_cost();
   std::stable_sort(chunks.begin(), chunks.end(), [&](const BatchChunk& x, const BatchChunk& y) {
     const uint32_t vx = dt[x.task].variant, vy = dt[y.task].variant;
     if (variant_is_div(vx) != variant_is_div(vy)) return variant_is_div(vy);
+    if (cost[vx] != cost[vy]) return cost[vx] > cost[vy];
     if (vx != vy) return vx < vy;
     if (dt[x.task].words != dt[y.task].words) return dt[x.task].words > dt[y.task].words;
     if (x.task != y.task) return x.task < y.task;

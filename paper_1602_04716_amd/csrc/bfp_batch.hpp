@@ -40,9 +40,10 @@ bool batch_task(const void* a, uint64_t na, const void* b, uint64_t nb, void* c,
 // Formats the persistent batch kernels compile (the 40 sweep formats).
 bool batch_format_ok(const bfp_format& f);
 
-// Cut tasks into chunks of at most kChunkWords words, sorted by circuit
-// variant and, within a variant, longest task first; chunks of the division
-// circuit come last.
+// Cut tasks into chunks of at most kChunkWords words, grouped by circuit
+// variant, variants in decreasing time per word (the larger of the circuit's
+// plane traffic and its gate count) and, within a variant, longest task
+// first; chunks of the division circuit come last.
 void batch_chunks(const std::vector<BatchTask>& tasks, std::vector<BatchChunk>* out);
 
 // Division chunks run in a persistent kernel of their own: the divider's
