@@ -76,6 +76,9 @@ typedef int bfp_status;
 #define BFP_E_BUDGET (-8)   /* serving: memory budget exceeded */
 #define BFP_E_NOMEM (-9)    /* host or device allocation failed */
 #define BFP_E_NODEV (-10)   /* no usable gfx950 device */
+#define BFP_E_CANCELLED (-11) /* serving: request withdrawn by bfp_server_cancel */
+#define BFP_E_TIMEOUT (-12) /* serving: request not launched within the queue timeout */
+#define BFP_E_BUSY (-13)    /* serving: request already on the device */
 
 #define BFP_RNE 0 /* round to nearest, ties to even (Section 4) */
 #define BFP_RZ 1  /* round toward zero (Section 4) */
@@ -307,18 +310,24 @@ void bfp_batch_plan_destroy(bfp_batch_plan* plan);
  * is free (continuous batching: requests that arrive while a batch runs join
  * the next one, which may start before the first ends).
  *
- * Handles are uint32 (0 is never a handle).  A request computes its op on
- * the first n elements of both operands (same format as the request's e, m;
- * the rounding mode comes from the request); its result is a new resident
- * vector of n elements.  When a request's n is shorter than an operand, the
- * result's padding bits hold the op of the operands' following elements
- * (unpack never reads them).  Times are steady-clock nanoseconds. */
+ * Handles are 64-bit (0 is never a handle): the low half names a slot of the
+ * server's vector table and the high half that slot's generation, so the
+ * handle of a freed vector stays invalid after its slot is reused.  A
+ * request computes its op on the first n elements of both operands (same
+ * format as the request's e, m; the rounding mode comes from the request);
+ * its result is a new resident vector of n elements whose padding bits are
+ * zero, whatever the operands hold past n.  Every vector counts the queued,
+ * admitted and running requests that use it: freeing a vector retires its
+ * handle at once and returns its memory when the last of them completes.
+ * Times are steady-clock nanoseconds. */
 typedef struct bfp_server bfp_server;
+typedef uint64_t bfp_handle;
 
 typedef struct {
   uint64_t req_id;
-  uint32_t result; /* handle of the result vector (0 on error) */
-  int32_t status;  /* BFP_OK or an error */
+  bfp_handle result; /* handle of the result vector (0 on error or with autofree) */
+  int32_t status;    /* BFP_OK, an error, BFP_E_CANCELLED or BFP_E_TIMEOUT */
+  uint32_t _pad;
   uint64_t n;
   int64_t t_submit_ns, t_admit_ns, t_launch_ns, t_done_ns; /* t_done: completion observed */
 } bfp_completion;
@@ -328,6 +337,9 @@ typedef struct {
   uint64_t submitted, admitted, completed, ticks;
   uint64_t max_tick_requests, max_inflight_ticks, deferred_budget;
   uint64_t pending, inflight;
+  uint64_t deferred_frees; /* frees whose memory waited for running requests */
+  uint64_t cancelled, timed_out;
+  uint64_t live_vectors, table_slots; /* resident vectors now, and table slots ever used */
 } bfp_server_stats;
 
 /* Create a server on the current device.  Errors: BFP_E_ARG (budget < 256
@@ -338,13 +350,26 @@ bfp_status bfp_server_create(uint64_t hbm_budget_bytes, int32_t slots, bfp_serve
  * into a new resident vector; synchronises `stream` before returning, so the
  * vector is ready for any later request.  BFP_E_BUDGET if the arena is full. */
 bfp_status bfp_server_put(bfp_server* s, bfp_format f, const void* std_dev, uint64_t n, void* stream,
-                          uint32_t* handle);
+                          bfp_handle* handle);
 
 /* Queue c = a op b on the first n elements of resident vectors a and b
- * (n <= both lengths).  Returns at once with the request id.  BFP_E_BUDGET if
- * the result could never fit in the arena. */
-bfp_status bfp_server_submit(bfp_server* s, int op, bfp_format f, uint32_t a, uint32_t b, uint64_t n,
+ * (n <= both lengths).  Returns at once with the request id.  BFP_E_ARG for
+ * a handle that is not live or a bad length, BFP_E_FORMAT if an operand's
+ * format differs from f, BFP_E_BUDGET if the result could never fit in the
+ * arena. */
+bfp_status bfp_server_submit(bfp_server* s, int op, bfp_format f, bfp_handle a, bfp_handle b, uint64_t n,
                              uint64_t* req_id);
+
+/* Withdraw a request that is queued or admitted but not yet launched: it
+ * completes with status BFP_E_CANCELLED and holds nothing afterwards.
+ * BFP_E_BUSY if it is already on the device (it completes normally),
+ * BFP_E_ARG if no request with this id is queued or running. */
+bfp_status bfp_server_cancel(bfp_server* s, uint64_t req_id);
+
+/* Requests not launched within `timeout_ns` of their submission complete
+ * with status BFP_E_TIMEOUT (0 or negative: no limit, the default).  A
+ * request on the device always runs to completion. */
+bfp_status bfp_server_set_queue_timeout(bfp_server* s, int64_t timeout_ns);
 
 /* Move up to `max` completions (oldest first) to `out`; *count is set. */
 bfp_status bfp_server_poll(bfp_server* s, bfp_completion* out, uint32_t max, uint32_t* count);
@@ -353,7 +378,7 @@ bfp_status bfp_server_poll(bfp_server* s, bfp_completion* out, uint32_t max, uin
 typedef struct {
   int32_t op;
   bfp_format f;
-  uint32_t a, b;       /* operand handles */
+  bfp_handle a, b;     /* operand handles */
   uint64_t n;
   int64_t arrival_ns;  /* submission time, ns after the replay call starts; non-decreasing */
 } bfp_request;
@@ -371,19 +396,25 @@ bfp_status bfp_server_replay(bfp_server* s, const bfp_request* reqs, uint32_t co
  * its request completes (its completion reports result 0). */
 bfp_status bfp_server_set_autofree(bfp_server* s, int32_t on);
 
-/* Wait until no request is queued, admitted or running (BFP_E_ARG on timeout). */
+/* Wait until no request is queued, admitted or running (BFP_E_TIMEOUT on
+ * timeout). */
 bfp_status bfp_server_wait_idle(bfp_server* s, int64_t timeout_ms);
 
-/* Device address and length of a resident vector (valid until it is freed). */
-bfp_status bfp_server_view(bfp_server* s, uint32_t handle, void** bitslice_dev, uint64_t* n);
+/* Device address and length of a resident vector.  The address stays valid
+ * only while the caller keeps the handle live (until bfp_server_free). */
+bfp_status bfp_server_view(bfp_server* s, bfp_handle handle, void** bitslice_dev, uint64_t* n);
 
 /* Unpack a resident vector of format f into its n standard containers at
- * std_dev_out (device), on `stream`, and synchronise `stream`.  Call it only
- * for vectors whose request has completed. */
-bfp_status bfp_server_get(bfp_server* s, uint32_t handle, bfp_format f, void* std_dev_out, void* stream);
+ * std_dev_out (device), on `stream`, and synchronise `stream`.  The vector
+ * is held for the duration of the call, so a concurrent free cannot hand its
+ * memory to another vector mid-unpack.  Call it only for vectors whose
+ * request has completed. */
+bfp_status bfp_server_get(bfp_server* s, bfp_handle handle, bfp_format f, void* std_dev_out, void* stream);
 
-/* Release a resident vector (operand or result) back to the arena. */
-bfp_status bfp_server_free(bfp_server* s, uint32_t handle);
+/* Retire a resident vector (operand or result): the handle is invalid from
+ * now on, and the memory returns to the arena once no queued, admitted or
+ * running request uses it.  BFP_E_ARG if the handle is not live. */
+bfp_status bfp_server_free(bfp_server* s, bfp_handle handle);
 
 bfp_status bfp_server_stats_get(bfp_server* s, bfp_server_stats* out);
 

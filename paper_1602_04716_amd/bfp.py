@@ -19,6 +19,8 @@ LIB_PATH = os.path.join(_HERE, "libbfp.so")
 TUNE_TABLE = os.path.join(_HERE, "tuning", "gfx950.txt")
 
 BFP_OK = 0
+BFP_E_FORMAT, BFP_E_NULL, BFP_E_ALIGN, BFP_E_OP, BFP_E_HIP = -1, -2, -3, -4, -5
+BFP_E_ARG, BFP_E_BUDGET, BFP_E_CANCELLED, BFP_E_TIMEOUT, BFP_E_BUSY = -6, -8, -11, -12, -13
 BFP_RNE, BFP_RZ = 0, 1
 BFP_ADD, BFP_SUB, BFP_MUL, BFP_DIV = 0, 1, 2, 3
 OPS = {"add": BFP_ADD, "sub": BFP_SUB, "mul": BFP_MUL, "div": BFP_DIV}
@@ -47,20 +49,21 @@ class bfp_task(ctypes.Structure):
 
 
 class bfp_completion(ctypes.Structure):
-    _fields_ = [("req_id", ctypes.c_uint64), ("result", ctypes.c_uint32), ("status", ctypes.c_int32),
-                ("n", ctypes.c_uint64), ("t_submit_ns", ctypes.c_int64), ("t_admit_ns", ctypes.c_int64),
+    _fields_ = [("req_id", ctypes.c_uint64), ("result", ctypes.c_uint64), ("status", ctypes.c_int32),
+                ("_pad", ctypes.c_uint32), ("n", ctypes.c_uint64), ("t_submit_ns", ctypes.c_int64), ("t_admit_ns", ctypes.c_int64),
                 ("t_launch_ns", ctypes.c_int64), ("t_done_ns", ctypes.c_int64)]
 
 
 class bfp_request(ctypes.Structure):
-    _fields_ = [("op", ctypes.c_int32), ("f", bfp_format), ("a", ctypes.c_uint32), ("b", ctypes.c_uint32),
+    _fields_ = [("op", ctypes.c_int32), ("f", bfp_format), ("a", ctypes.c_uint64), ("b", ctypes.c_uint64),
                 ("n", ctypes.c_uint64), ("arrival_ns", ctypes.c_int64)]
 
 
 class bfp_server_stats(ctypes.Structure):
     _fields_ = [(k, ctypes.c_uint64) for k in (
         "budget", "used", "high_water", "submitted", "admitted", "completed", "ticks", "max_tick_requests",
-        "max_inflight_ticks", "deferred_budget", "pending", "inflight")]
+        "max_inflight_ticks", "deferred_budget", "pending", "inflight", "deferred_frees", "cancelled",
+        "timed_out", "live_vectors", "table_slots")]
 
     def as_dict(self):
         return {k: int(getattr(self, k)) for (k, _t) in self._fields_}
@@ -127,20 +130,22 @@ _SIGS = {
     "bfp_batch_plan_destroy": (None, [ctypes.c_void_p]),
     "bfp_server_create": (ctypes.c_int, [ctypes.c_uint64, ctypes.c_int32, ctypes.POINTER(ctypes.c_void_p)]),
     "bfp_server_put": (ctypes.c_int, [ctypes.c_void_p, bfp_format, ctypes.c_void_p, ctypes.c_uint64,
-                                      ctypes.c_void_p, ctypes.POINTER(ctypes.c_uint32)]),
-    "bfp_server_submit": (ctypes.c_int, [ctypes.c_void_p, ctypes.c_int, bfp_format, ctypes.c_uint32,
-                                         ctypes.c_uint32, ctypes.c_uint64, ctypes.POINTER(ctypes.c_uint64)]),
+                                      ctypes.c_void_p, ctypes.POINTER(ctypes.c_uint64)]),
+    "bfp_server_submit": (ctypes.c_int, [ctypes.c_void_p, ctypes.c_int, bfp_format, ctypes.c_uint64,
+                                         ctypes.c_uint64, ctypes.c_uint64, ctypes.POINTER(ctypes.c_uint64)]),
+    "bfp_server_cancel": (ctypes.c_int, [ctypes.c_void_p, ctypes.c_uint64]),
+    "bfp_server_set_queue_timeout": (ctypes.c_int, [ctypes.c_void_p, ctypes.c_int64]),
     "bfp_server_poll": (ctypes.c_int, [ctypes.c_void_p, ctypes.POINTER(bfp_completion), ctypes.c_uint32,
                                        ctypes.POINTER(ctypes.c_uint32)]),
     "bfp_server_wait_idle": (ctypes.c_int, [ctypes.c_void_p, ctypes.c_int64]),
     "bfp_server_replay": (ctypes.c_int, [ctypes.c_void_p, ctypes.POINTER(bfp_request), ctypes.c_uint32,
                                          ctypes.POINTER(ctypes.c_uint64)]),
     "bfp_server_set_autofree": (ctypes.c_int, [ctypes.c_void_p, ctypes.c_int32]),
-    "bfp_server_view": (ctypes.c_int, [ctypes.c_void_p, ctypes.c_uint32, ctypes.POINTER(ctypes.c_void_p),
+    "bfp_server_view": (ctypes.c_int, [ctypes.c_void_p, ctypes.c_uint64, ctypes.POINTER(ctypes.c_void_p),
                                        ctypes.POINTER(ctypes.c_uint64)]),
-    "bfp_server_get": (ctypes.c_int, [ctypes.c_void_p, ctypes.c_uint32, bfp_format, ctypes.c_void_p,
+    "bfp_server_get": (ctypes.c_int, [ctypes.c_void_p, ctypes.c_uint64, bfp_format, ctypes.c_void_p,
                                       ctypes.c_void_p]),
-    "bfp_server_free": (ctypes.c_int, [ctypes.c_void_p, ctypes.c_uint32]),
+    "bfp_server_free": (ctypes.c_int, [ctypes.c_void_p, ctypes.c_uint64]),
     "bfp_server_stats_get": (ctypes.c_int, [ctypes.c_void_p, ctypes.POINTER(bfp_server_stats)]),
     "bfp_server_destroy": (None, [ctypes.c_void_p]),
 }
@@ -440,7 +445,7 @@ def bfp_server_create(budget_bytes: int, slots: int) -> int:
 
 
 def bfp_server_put(server: int, f, std_dev, n: int, stream=None) -> int:
-    h = ctypes.c_uint32()
+    h = ctypes.c_uint64()
     _check(lib().bfp_server_put(server, f, _ptr(std_dev), n, _stream(stream), ctypes.byref(h)), "bfp_server_put")
     return h.value
 
@@ -449,6 +454,14 @@ def bfp_server_submit(server: int, op, f, a: int, b: int, n: int) -> int:
     rid = ctypes.c_uint64()
     _check(lib().bfp_server_submit(server, _op(op), f, a, b, n, ctypes.byref(rid)), "bfp_server_submit")
     return rid.value
+
+
+def bfp_server_cancel(server: int, req_id: int):
+    _check(lib().bfp_server_cancel(server, req_id), "bfp_server_cancel")
+
+
+def bfp_server_set_queue_timeout(server: int, timeout_ns: int):
+    _check(lib().bfp_server_set_queue_timeout(server, timeout_ns), "bfp_server_set_queue_timeout")
 
 
 def bfp_server_poll(server: int, max_items: int = 4096):

@@ -9,12 +9,13 @@
 // on short ones, and, within a variant, longest task first.  Descriptors go
 // to device memory once.
 //
-// Device: a grid sized to the GPU's resident capacity; each block takes the
-// next chunk index from an atomic counter, reads the chunk's task, and
-// switches (block-uniformly) to the compiled circuit of the task's
-// (e, m, operation class, rounding mode).  Division chunks go to a second
-// persistent kernel after the first, so that the divider's registers do not
-// lower the first kernel's occupancy.  The counters are cleared by a
+// Device: one persistent kernel per register class (light circuits, wide
+// adders and m = 15 multipliers, m = 23 multipliers, dividers), each
+// compiled for the occupancy its heaviest circuit allows and launched on a
+// grid sized to the GPU's resident capacity for it.  Each block takes the
+// next chunk index of its class from an atomic counter, reads the chunk's
+// task, and switches (block-uniformly) to the compiled circuit of the task's
+// (e, m, operation class, rounding mode).  The counters are cleared by a
 // one-thread kernel at the head of the graph, so each replay starts at chunk 0.
 #include <hip/hip_runtime.h>
 
@@ -27,84 +28,107 @@
 #include "bfp_formats.hpp"
 #include "bfp_batch.hpp"
 #include "bfp_kernels.hpp"
+#include "bfp_layout.hpp"
 
 namespace bfp {
 
-// variant = ((format index) * kOpClasses + opclass) * 2 + rz, format index in
-// the order of BFP_FOR_EACH_FORMAT
-
-__host__ __device__ constexpr int format_index(int e, int m) {
-  const int ei = e == 3 ? 0 : e == 4 ? 1 : e == 5 ? 2 : e == 6 ? 3 : e == 8 ? 4 : -1;
-  const int mi = m == 1 ? 0 : m == 2 ? 1 : m == 3 ? 2 : m == 5 ? 3 : m == 7 ? 4 : m == 10 ? 5
-               : m == 15 ? 6 : m == 23 ? 7 : -1;
-  return (ei < 0 || mi < 0) ? -1 : ei * 8 + mi;
-}
-
-// One chunk of one task: the block's threads stride over the chunk's words.
-// One word per lane: two would double the registers of the light circuits,
-// and any two-word instance raises the whole kernel's register allocation
-// (measured: 131 -> 176 VGPRs), cutting resident waves from 3 to 2 per SIMD.
+// One chunk of one task: the block's threads stride over the chunk's words,
+// one word per lane (two would double every circuit's registers).
+//
+// A task may compute a prefix of longer operands (the serving loop does),
+// and the operands' plane strides need not cover the result's: the stride
+// rule is not monotonic in the length.  So operand words are read only up to
+// the last word holding an element below n, which every operand plane holds:
+// words past it read that word again, and their results are cleared.  Bits
+// of elements at or past n are cleared in every result word, so c's padding
+// is zero whatever the operands hold there (division would otherwise map
+// zero padding to NaN).  The clamp and the mask are branch-free: a branch
+// around the loads, or around the mask, raised the kernel's registers from
+// about 130 to 235 VGPRs (measured on the (8,23) multiplier).
 template <int E, int M, bool RZ, int OPC>
 __device__ __forceinline__ void batch_chunk(const BatchTask& tk, uint64_t w0, uint32_t nw) {
   constexpr int B = 1 + E + M;
   constexpr int R = 1;
   const uint64_t end = w0 + nw;
+  const uint64_t wlast = data_words(tk.n) - 1;  // last word holding an element below n
   for (uint64_t off = w0 + (uint64_t)threadIdx.x * R; off < end; off += (uint64_t)blockDim.x * R) {
+    const uint64_t src = off < wlast ? off : wlast;
     WordR<R> x[B], y[B], z[B];
 #pragma unroll
     for (int k = 0; k < B; ++k) {
-      x[k] = ld_words<R>(tk.a + (uint64_t)k * tk.sa + off);
-      y[k] = ld_words<R>(tk.b + (uint64_t)k * tk.sb + off);
+      x[k] = ld_words<R>(tk.a + (uint64_t)k * tk.sa + src);
+      y[k] = ld_words<R>(tk.b + (uint64_t)k * tk.sb + src);
     }
     circuit<E, M, RZ, OPC, R>(x, y, tk.negb, z);
-    mask_padding<OPC, R, B>(z, off, tk.n);
+    const uint32_t mk = word_mask(off, tk.n);
+#pragma unroll
+    for (int k = 0; k < B; ++k) z[k].w[0] &= mk;
 #pragma unroll
     for (int k = 0; k < B; ++k) st_words<R>(tk.c + (uint64_t)k * tk.sc + off, z[k]);
   }
 }
 
-constexpr bool variant_is_div(uint32_t v) { return (v / 2) % kOpClasses == 2; }
-
 __global__ void k_batch_reset(uint32_t* counter) {
-  if (threadIdx.x == 0 && blockIdx.x == 0) {
-    counter[0] = 0u;
-    counter[1] = 0u;
-  }
+  if (threadIdx.x < kBatchClasses && blockIdx.x == 0) counter[threadIdx.x] = 0u;
 }
 
-// Persistent kernel over chunks [first, first + nchunks).  DIV selects the
-// division variants; the other kernel holds add/sub and mul.
-template <bool DIV>
-__global__ void __launch_bounds__(kBatchBlock) k_batch(const BatchTask* tasks, const BatchChunk* chunks,
-                                                       uint32_t first, uint32_t nchunks, uint32_t* counter) {
+// Waves per SIMD each class kernel is compiled for.
+template <int CLS>
+struct ClassWaves {
+  static constexpr int value = CLS == 0 ? 4 : (CLS == 1 ? 3 : 2);
+};
+
+// Persistent kernel of register class CLS over chunks [first, first +
+// nchunks) of the chunk table, or, when `index` is not null, over the
+// index's chunks of class CLS: task t owns chunks [prefix[t], prefix[t+1]),
+// cut at kChunkWords words in task order.  Thread 0 takes the next chunk from
+// the counter and resolves it; the block then runs it.
+template <int CLS>
+__global__ void __launch_bounds__(kBatchBlock) __attribute__((amdgpu_waves_per_eu(ClassWaves<CLS>::value)))
+k_batch(const BatchTask* tasks, const BatchChunk* chunks, uint32_t first, uint32_t nchunks, uint32_t* counter,
+        const BatchIndex* index, const uint64_t* prefix) {
+  __shared__ BatchChunk s_ch;
   __shared__ uint32_t s_next;
+  const uint64_t total = index ? index->total[CLS] : nchunks;
   for (;;) {
-    if (threadIdx.x == 0) s_next = atomicAdd(counter, 1u);
+    if (threadIdx.x == 0) {
+      const uint32_t ci = atomicAdd(counter, 1u);
+      s_next = ci;
+      if (ci < total) {
+        if (index) {
+          uint32_t lo = 0, hi = index->ntasks;  // largest t with prefix[t] <= ci
+          while (hi - lo > 1) {
+            const uint32_t mid = (lo + hi) / 2;
+            if (prefix[mid] <= ci) lo = mid;
+            else hi = mid;
+          }
+          const uint64_t w0 = (ci - prefix[lo]) * (uint64_t)kChunkWords;
+          s_ch.task = lo;
+          s_ch.w0 = w0;
+          s_ch.nwords = (uint32_t)min((uint64_t)kChunkWords, tasks[lo].words - w0);
+        } else {
+          s_ch = chunks[first + ci];
+        }
+      }
+    }
     __syncthreads();
     const uint32_t ci = s_next;
+    const BatchChunk ch = s_ch;
     __syncthreads();
-    if (ci >= nchunks) break;  // every block sees the counter pass nchunks and leaves
-    const BatchChunk ch = chunks[first + ci];
+    if (ci >= total) break;  // every block sees the counter pass the total and leaves
     const BatchTask tk = tasks[ch.task];
-    if constexpr (DIV) {
-      switch (tk.variant) {
-#define BFP_BATCH_VARIANT(EE, MM, OPC, RZ) \
-  case (format_index(EE, MM) * kOpClasses + OPC) * 2 + RZ: batch_chunk<EE, MM, RZ, OPC>(tk, ch.w0, ch.nwords); break;
-#define BFP_BATCH_CASE(EE, MM) BFP_BATCH_VARIANT(EE, MM, 2, false) BFP_BATCH_VARIANT(EE, MM, 2, true)
-        BFP_FOR_EACH_FORMAT(BFP_BATCH_CASE)
-#undef BFP_BATCH_CASE
-        default: break;
-      }
-    } else {
-      switch (tk.variant) {
+    switch (tk.variant) {
+#define BFP_BATCH_VARIANT(EE, MM, OPC, RZ)                                          \
+  case (format_index(EE, MM) * kOpClasses + OPC) * 2 + RZ:                          \
+    if constexpr (variant_class(MM, OPC) == CLS) batch_chunk<EE, MM, RZ, OPC>(tk, ch.w0, ch.nwords); \
+    break;
 #define BFP_BATCH_CASE(EE, MM)                                                                           \
   BFP_BATCH_VARIANT(EE, MM, 0, false) BFP_BATCH_VARIANT(EE, MM, 0, true) BFP_BATCH_VARIANT(EE, MM, 1, false) \
-  BFP_BATCH_VARIANT(EE, MM, 1, true)
-        BFP_FOR_EACH_FORMAT(BFP_BATCH_CASE)
+  BFP_BATCH_VARIANT(EE, MM, 1, true) BFP_BATCH_VARIANT(EE, MM, 2, false) BFP_BATCH_VARIANT(EE, MM, 2, true)
+      BFP_FOR_EACH_FORMAT(BFP_BATCH_CASE)
 #undef BFP_BATCH_CASE
 #undef BFP_BATCH_VARIANT
-        default: break;
-      }
+      default: break;
     }
   }
 }
@@ -115,20 +139,8 @@ bool batch_format_ok(const bfp_format& f) { return format_index(f.e, f.m) >= 0 &
 
 bool batch_task(const void* a, uint64_t na, const void* b, uint64_t nb, void* c, uint64_t n, bfp_format f, int op,
                 BatchTask* out) {
-  const int fi = format_index(f.e, f.m);
-  if (fi < 0 || f.round > 1 || !op_valid(op)) return false;
-  if (na < n || nb < n) return false;
-  out->a = static_cast<const uint32_t*>(a);
-  out->b = static_cast<const uint32_t*>(b);
-  out->c = static_cast<uint32_t*>(c);
-  out->sa = bfp_plane_stride_words(na);
-  out->sb = bfp_plane_stride_words(nb);
-  out->sc = bfp_plane_stride_words(n);
-  out->words = out->sc;
-  out->n = n;
-  out->negb = op == BFP_SUB ? 0xFFFFFFFFu : 0u;
-  out->variant = (uint32_t)((fi * kOpClasses + opclass_of(op)) * 2 + f.round);
-  return true;
+  if (!op_valid(op)) return false;
+  return make_batch_task(a, na, b, nb, c, n, f, op, out);
 }
 
 // Relative time per word of each variant's circuit: the larger of its HBM
@@ -154,6 +166,12 @@ static const std::vector<uint32_t>& variant_cost() {
   return cost;
 }
 
+int task_class(const BatchTask& t) {
+  const uint32_t fo = t.variant / 2;  // format index * kOpClasses + op class
+  static const int kM[8] = {1, 2, 3, 5, 7, 10, 15, 23};
+  return variant_class(kM[(fo / kOpClasses) % 8], (int)(fo % kOpClasses));
+}
+
 void batch_chunks(const std::vector<BatchTask>& dt, std::vector<BatchChunk>* out) {
   std::vector<BatchChunk>& chunks = *out;
   chunks.clear();
@@ -166,12 +184,14 @@ void batch_chunks(const std::vector<BatchTask>& dt, std::vector<BatchChunk>* out
       chunks.push_back(ch);
     }
   }
-  // division last, then variants by decreasing time per word (ties by
+  // by register class, then variants by decreasing time per word (ties by
   // variant); within a variant, longer tasks first, then by position
   const std::vector<uint32_t>& cost = variant_cost();
+  std::vector<int> cls(dt.size());
+  for (size_t i = 0; i < dt.size(); ++i) cls[i] = task_class(dt[i]);
   std::stable_sort(chunks.begin(), chunks.end(), [&](const BatchChunk& x, const BatchChunk& y) {
     const uint32_t vx = dt[x.task].variant, vy = dt[y.task].variant;
-    if (variant_is_div(vx) != variant_is_div(vy)) return variant_is_div(vy);
+    if (cls[x.task] != cls[y.task]) return cls[x.task] < cls[y.task];
     if (cost[vx] != cost[vy]) return cost[vx] > cost[vy];
     if (vx != vy) return vx < vy;
     if (dt[x.task].words != dt[y.task].words) return dt[x.task].words > dt[y.task].words;
@@ -180,38 +200,53 @@ void batch_chunks(const std::vector<BatchTask>& dt, std::vector<BatchChunk>* out
   });
 }
 
-int batch_resident_blocks(bool div) {
-  int dev = 0, per_cu = 0;
-  hipDeviceProp_t prop;
-  if (hipGetDevice(&dev) != hipSuccess || hipGetDeviceProperties(&prop, dev) != hipSuccess) return 0;
-  const hipError_t e = div ? hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, k_batch<true>, kBatchBlock, 0)
-                           : hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, k_batch<false>, kBatchBlock, 0);
-  if (e != hipSuccess) return 0;
-  if (per_cu < 1) per_cu = 1;
-  return per_cu * prop.multiProcessorCount;
+template <int CLS>
+static int resident_blocks_of(int cus) {
+  int per_cu = 0;
+  if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, k_batch<CLS>, kBatchBlock, 0) != hipSuccess) return 0;
+  return (per_cu < 1 ? 1 : per_cu) * cus;
 }
 
-BatchSplit batch_split(const std::vector<BatchTask>& tasks, const std::vector<BatchChunk>& chunks, int cap_main,
-                       int cap_div) {
-  BatchSplit sp;
-  for (const BatchChunk& ch : chunks) {
-    if (variant_is_div(tasks[ch.task].variant)) ++sp.n_div;
-    else ++sp.n_main;
+int batch_resident_blocks(int c) {
+  int dev = 0;
+  hipDeviceProp_t prop;
+  if (hipGetDevice(&dev) != hipSuccess || hipGetDeviceProperties(&prop, dev) != hipSuccess) return 0;
+  switch (c) {
+    case 0: return resident_blocks_of<0>(prop.multiProcessorCount);
+    case 1: return resident_blocks_of<1>(prop.multiProcessorCount);
+    case 2: return resident_blocks_of<2>(prop.multiProcessorCount);
+    case 3: return resident_blocks_of<3>(prop.multiProcessorCount);
+    default: return 0;
   }
-  sp.grid_main = (unsigned)std::min<uint64_t>((uint64_t)std::max(cap_main, 1), sp.n_main);
-  sp.grid_div = (unsigned)std::min<uint64_t>((uint64_t)std::max(cap_div, 1), sp.n_div);
+}
+
+BatchSplit batch_split(const std::vector<BatchTask>& tasks, const std::vector<BatchChunk>& chunks, const int* cap) {
+  BatchSplit sp;
+  for (const BatchChunk& ch : chunks) sp.n[task_class(tasks[ch.task])]++;
+  uint32_t first = 0;
+  for (int c = 0; c < kBatchClasses; ++c) {
+    sp.first[c] = first;
+    first += sp.n[c];
+    sp.grid[c] = (unsigned)std::min<uint64_t>((uint64_t)std::max(cap[c], 1), sp.n[c]);
+  }
   return sp;
+}
+
+template <int CLS>
+static void launch_class(const BatchTask* d_tasks, const BatchChunk* d_chunks, const BatchSplit& sp,
+                         uint32_t* d_counter, hipStream_t s) {
+  if (sp.n[CLS] > 0)
+    hipLaunchKernelGGL((k_batch<CLS>), dim3(sp.grid[CLS]), dim3(kBatchBlock), 0, s, d_tasks, d_chunks,
+                       sp.first[CLS], sp.n[CLS], d_counter + CLS, nullptr, nullptr);
 }
 
 hipError_t batch_launch(const BatchTask* d_tasks, const BatchChunk* d_chunks, const BatchSplit& sp,
                         uint32_t* d_counter, hipStream_t s) {
   hipLaunchKernelGGL(k_batch_reset, dim3(1), dim3(64), 0, s, d_counter);
-  if (sp.n_main > 0)
-    hipLaunchKernelGGL((k_batch<false>), dim3(sp.grid_main), dim3(kBatchBlock), 0, s, d_tasks, d_chunks, 0u,
-                       sp.n_main, d_counter);
-  if (sp.n_div > 0)
-    hipLaunchKernelGGL((k_batch<true>), dim3(sp.grid_div), dim3(kBatchBlock), 0, s, d_tasks, d_chunks, sp.n_main,
-                       sp.n_div, d_counter + 1);
+  launch_class<0>(d_tasks, d_chunks, sp, d_counter, s);
+  launch_class<1>(d_tasks, d_chunks, sp, d_counter, s);
+  launch_class<2>(d_tasks, d_chunks, sp, d_counter, s);
+  launch_class<3>(d_tasks, d_chunks, sp, d_counter, s);
   return hipGetLastError();
 }
 
@@ -292,13 +327,16 @@ bfp_status bfp_batch_plan_create(const bfp_task* tasks, uint32_t count, bfp_batc
     plan_free(p);
     return BFP_E_HIP;
   }
-  // resident grids: as many blocks as fit on the device at once
-  const int cap_main = batch_resident_blocks(false), cap_div = batch_resident_blocks(true);
-  if (cap_main <= 0 || cap_div <= 0) {
-    plan_free(p);
-    return BFP_E_HIP;
+  // resident grids: as many blocks of each class kernel as fit on the device at once
+  int cap[kBatchClasses];
+  for (int c = 0; c < kBatchClasses; ++c) {
+    cap[c] = batch_resident_blocks(c);
+    if (cap[c] <= 0) {
+      plan_free(p);
+      return BFP_E_HIP;
+    }
   }
-  p->split = batch_split(dt, chunks, cap_main, cap_div);
+  p->split = batch_split(dt, chunks, cap);
   // capture reset + persistent kernel once
   if (hipStreamCreateWithFlags(&p->capture_stream, hipStreamNonBlocking) != hipSuccess) {
     plan_free(p);
@@ -347,7 +385,11 @@ bfp_status bfp_batch_plan_info(const bfp_batch_plan* plan, uint32_t* nchunks, ui
                                uint64_t* words_per_operand) {
   if (!plan) return BFP_E_NULL;
   if (nchunks) *nchunks = plan->nchunks;
-  if (grid) *grid = plan->split.grid_main > plan->split.grid_div ? plan->split.grid_main : plan->split.grid_div;
+  if (grid) {
+    unsigned g = 0;
+    for (int c = 0; c < kBatchClasses; ++c) g = plan->split.grid[c] > g ? plan->split.grid[c] : g;
+    *grid = g;
+  }
   if (words_per_operand) *words_per_operand = plan->words_total;
   return BFP_OK;
 }
@@ -355,3 +397,4 @@ bfp_status bfp_batch_plan_info(const bfp_batch_plan* plan, uint32_t* nchunks, ui
 void bfp_batch_plan_destroy(bfp_batch_plan* plan) { plan_free(plan); }
 
 }  // extern "C"
+

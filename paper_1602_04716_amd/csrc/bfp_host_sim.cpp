@@ -220,6 +220,7 @@ int bfpsim_transpose(int C, int inverse, const uint32_t* in, uint32_t* out) {
 // ---------------------------------------------------------------------------
 #include <deque>
 
+#include "bfp_layout.hpp"
 #include "bfp_sched.hpp"
 
 namespace {
@@ -256,22 +257,36 @@ struct SimServer {
 extern "C" {
 void* simsrv_create(uint64_t budget, int slots) { return new SimServer(budget, slots); }
 void simsrv_destroy(void* p) { delete static_cast<SimServer*>(p); }
-uint32_t simsrv_put(void* p, uint64_t bytes, uint64_t n) {
+// A resident vector of format (5,10) with n elements taking `bytes`; 0 if
+// the arena is full.
+uint64_t simsrv_put(void* p, uint64_t bytes, uint64_t n) {
   auto* s = static_cast<SimServer*>(p);
-  uint32_t h;
-  uint64_t off;
+  uint64_t h, off;
   return s->sched.alloc_resident(bytes, 5, 10, n, &h, &off) ? h : 0;
 }
-int simsrv_free(void* p, uint32_t h) { return static_cast<SimServer*>(p)->sched.free_resident(h) ? 0 : -1; }
-uint64_t simsrv_submit(void* p, uint64_t n, uint64_t c_bytes) {
+int simsrv_free(void* p, uint64_t h) { return static_cast<SimServer*>(p)->sched.free_resident(h) ? 0 : -1; }
+// Arena offset of a live handle, or -1.
+int64_t simsrv_offset(void* p, uint64_t h) {
+  const bfp::Resident* r = static_cast<SimServer*>(p)->sched.resident(h);
+  return r ? (int64_t)r->off : -1;
+}
+// Queue a (5,10) add of the first n elements of a and b with a result of
+// c_bytes; returns the request id, or the negative status of a rejected
+// submission.
+int64_t simsrv_submit(void* p, uint64_t a, uint64_t b, uint64_t n, uint64_t c_bytes) {
   auto* s = static_cast<SimServer*>(p);
   bfp::SchedRequest r;
-  r.id = s->next_id++;
+  r.id = s->next_id;
+  r.e = 5;
+  r.m = 10;
   r.n = n;
   r.c_bytes = c_bytes;
-  s->sched.submit(r);
-  return r.id;
+  const int st = s->sched.submit(r, a, b);
+  if (st != 0) return st;
+  return (int64_t)s->next_id++;
 }
+int simsrv_cancel(void* p, uint64_t id) { return static_cast<SimServer*>(p)->sched.cancel(id); }
+void simsrv_set_timeout(void* p, int64_t ns) { static_cast<SimServer*>(p)->sched.set_queue_timeout(ns); }
 int simsrv_step(void* p) { return static_cast<SimServer*>(p)->sched.step() ? 1 : 0; }
 // The serving worker's split step: collect (returns the batch size), then,
 // after any number of other calls, launch the batch and commit it.
@@ -289,8 +304,22 @@ void simsrv_launch_commit(void* p) {
 void simsrv_release(void* p, int k) { static_cast<SimServer*>(p)->ex.releasable += k; }
 void simsrv_fail_next(void* p) { static_cast<SimServer*>(p)->ex.fail_next = 1; }
 int simsrv_running_ticks(void* p) { return (int)static_cast<SimServer*>(p)->ex.running.size(); }
+// Arena offsets read by the running ticks' requests (a and b of each), up to
+// max; returns the count.
+int simsrv_running_operands(void* p, uint64_t* offs, int max) {
+  auto* s = static_cast<SimServer*>(p);
+  int k = 0;
+  for (const auto& tick : s->ex.running)
+    for (const auto& r : tick) {
+      if (k < max) offs[k] = r.a_off;
+      k++;
+      if (k < max) offs[k] = r.b_off;
+      k++;
+    }
+  return k;
+}
 // completions: ids[i], handles[i], status[i]; returns count
-int simsrv_take(void* p, uint64_t* ids, uint32_t* handles, int32_t* status, int max) {
+int simsrv_take(void* p, uint64_t* ids, uint64_t* handles, int32_t* status, int max) {
   auto* s = static_cast<SimServer*>(p);
   std::vector<bfp::SchedRequest> tmp((size_t)max);
   const size_t k = s->sched.take_completed(tmp.data(), (size_t)max);
@@ -302,7 +331,8 @@ int simsrv_take(void* p, uint64_t* ids, uint32_t* handles, int32_t* status, int 
   return (int)k;
 }
 // used, high_water, capacity, pending, inflight requests, ticks, max_tick_requests,
-// max_inflight_ticks, deferred_budget, admitted, completed
+// max_inflight_ticks, deferred_budget, admitted, completed, deferred_frees,
+// cancelled, timed_out, live vectors, table slots
 void simsrv_stats(void* p, uint64_t* out) {
   auto* s = static_cast<SimServer*>(p);
   const bfp::SchedStats& st = s->sched.stats();
@@ -317,7 +347,17 @@ void simsrv_stats(void* p, uint64_t* out) {
   out[8] = st.deferred_budget;
   out[9] = st.admitted;
   out[10] = st.completed;
+  out[11] = st.deferred_frees;
+  out[12] = st.cancelled;
+  out[13] = st.timed_out;
+  out[14] = s->sched.live_residents();
+  out[15] = s->sched.resident_slots();
 }
+
+// Layout rules as the kernels use them.
+uint64_t simlayout_gpad(uint64_t n) { return bfp::gpad_of(n); }
+uint64_t simlayout_data_words(uint64_t n) { return bfp::data_words(n); }
+uint32_t simlayout_word_mask(uint64_t w, uint64_t n) { return bfp::word_mask(w, n); }
 
 // Arena alone
 void* simarena_create(uint64_t cap) { return new bfp::Arena(cap); }

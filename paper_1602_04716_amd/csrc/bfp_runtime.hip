@@ -10,6 +10,7 @@
 #include "bfp_formats.hpp"
 #include "bfp_int_kernels.hpp"
 #include "bfp_kernels.hpp"
+#include "bfp_layout.hpp"
 
 namespace bfp {
 
@@ -34,15 +35,6 @@ int bits_of(const bfp_format& f) { return 1 + f.e + f.m; }
 int cbytes_of(const bfp_format& f) {
   const int B = bits_of(f);
   return B <= 8 ? 1 : (B <= 16 ? 2 : (B <= 32 ? 4 : 8));
-}
-// Plane stride: whole 64-word (256-byte) tiles, skewed by 256 words when it
-// would be a multiple of 2048 words: planes 8 KiB-multiples apart put every
-// plane of a word group on the same HBM channels (measured: unpack of 2^26
-// elements 10% slower at an 8 MiB stride than at 8 MiB + 1 KiB).
-uint64_t gpad_of(uint64_t n) {
-  const uint64_t g = (n + 31) / 32;
-  const uint64_t gp = (g + 63) / 64 * 64;
-  return gp % 2048 == 0 ? gp + 256 : gp;
 }
 bool aligned16(const void* p) { return (reinterpret_cast<uintptr_t>(p) & 15u) == 0; }
 bool overlap(const void* a, size_t na, const void* b, size_t nb) {

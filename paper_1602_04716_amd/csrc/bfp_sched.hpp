@@ -1,8 +1,8 @@
 // bfp_sched.hpp -- host-side core of the serving loop: device-memory arena
-// (the HBM ledger), request admission and tick building.  Plain C++ with no
-// HIP calls: the executor that turns a tick into device work is a template
-// parameter, so the same core runs with the HIP executor in libbfp and with a
-// fake executor in the CPU tests.
+// (the HBM ledger), resident-vector table, request admission and tick
+// building.  Plain C++ with no HIP calls: the executor that turns a tick into
+// device work is a template parameter, so the same core runs with the HIP
+// executor in libbfp and with a fake executor in the CPU tests.
 //
 // Continuous batching: each tick takes every request admitted since the last
 // launch; up to `Executor::kStreams` ticks are in flight at once (one per
@@ -10,6 +10,14 @@
 // on the other stream before it finishes.  A request is admitted only when a
 // slot is free and the arena can hold its result; otherwise it waits in FIFO
 // order.
+//
+// Lifetimes: every resident vector counts the requests that read or write it
+// (queued, admitted or running).  Freeing a vector that requests still hold
+// retires its handle at once but returns its arena range only when the last
+// of those requests completes, so a later put can never land on memory a
+// running tick still reads.  Handles carry the generation of their table
+// slot, so a handle of a freed vector is rejected even after its slot holds
+// another vector.
 #pragma once
 #include <stdint.h>
 
@@ -17,7 +25,10 @@
 #include <deque>
 #include <map>
 #include <mutex>
+#include <unordered_set>
 #include <vector>
+
+#include "bfp.h"
 
 namespace bfp {
 
@@ -91,6 +102,8 @@ class Arena {
   std::map<uint64_t, uint64_t> live_;  // offset -> size
 };
 
+constexpr uint32_t kNoSlot = 0xFFFFFFFFu;
+
 struct SchedRequest {
   uint64_t id = 0;
   int op = 0;
@@ -100,7 +113,8 @@ struct SchedRequest {
   uint64_t a_off = 0, b_off = 0;  // arena offsets of resident operands
   uint64_t c_off = 0;             // arena offset of the result (set at admission)
   uint64_t c_bytes = 0;
-  uint32_t c_handle = 0;          // result handle (set at admission)
+  uint64_t c_handle = 0;          // result handle (set at admission)
+  uint32_t a_slot = kNoSlot, b_slot = kNoSlot, c_slot = kNoSlot;  // table slots held by the request
   int64_t t_submit = 0, t_admit = 0, t_launch = 0, t_done = 0;
   int status = 0;
 };
@@ -108,14 +122,20 @@ struct SchedRequest {
 struct SchedStats {
   uint64_t submitted = 0, admitted = 0, completed = 0, ticks = 0, max_tick_requests = 0;
   uint64_t max_inflight_ticks = 0, deferred_budget = 0;
+  uint64_t deferred_frees = 0, cancelled = 0, timed_out = 0;
 };
 
-// Resident vectors by handle (operands put by the caller, and results).
+// A resident vector: an operand put by the caller or a request's result.
 struct Resident {
   uint64_t off = 0, bytes = 0, n = 0;
   uint8_t e = 0, m = 0;
-  bool live = false;
+  bool live = false;    // the slot holds a vector whose arena range is allocated
+  bool retired = false; // freed by the caller while requests still hold it
+  uint32_t gen = 1;     // generation of the slot (high half of its handles)
+  uint32_t refs = 0;    // requests (queued, admitted, running) that read or write it
 };
+
+inline uint64_t make_handle(uint32_t slot, uint32_t gen) { return ((uint64_t)gen << 32) | ((uint64_t)slot + 1u); }
 
 template <class Executor>
 class Scheduler {
@@ -127,44 +147,127 @@ class Scheduler {
   // Free each result as soon as its request completes (the completion is
   // still reported, with result handle 0).
   void set_autofree(bool on) { autofree_ = on; }
+  // Requests not launched within `ns` of their submission complete with
+  // BFP_E_TIMEOUT (0: no limit).
+  void set_queue_timeout(int64_t ns) { queue_timeout_ns_ = ns > 0 ? ns : 0; }
 
   // ---- resident vectors (caller holds mutex) ----
-  bool alloc_resident(uint64_t bytes, uint8_t e, uint8_t m, uint64_t n, uint32_t* handle, uint64_t* off) {
+  bool alloc_resident(uint64_t bytes, uint8_t e, uint8_t m, uint64_t n, uint64_t* handle, uint64_t* off) {
     if (!arena_.alloc(bytes, off)) return false;
-    Resident r;
+    uint32_t slot;
+    if (!free_slots_.empty()) {
+      slot = free_slots_.front();
+      free_slots_.pop_front();
+    } else {
+      slot = (uint32_t)res_.size();
+      res_.emplace_back();
+    }
+    Resident& r = res_[slot];
     r.off = *off;
     r.bytes = Arena::round(bytes);
     r.n = n;
     r.e = e;
     r.m = m;
     r.live = true;
-    res_.push_back(r);
-    *handle = (uint32_t)res_.size();  // handles start at 1
+    r.retired = false;
+    r.refs = 0;
+    *handle = make_handle(slot, r.gen);
     return true;
   }
-  const Resident* resident(uint32_t h) const {
-    if (h == 0 || h > res_.size() || !res_[h - 1].live) return nullptr;
-    return &res_[h - 1];
+  // Slot of a live, not retired vector, or kNoSlot.
+  uint32_t slot_of(uint64_t h) const {
+    const uint64_t s1 = h & 0xFFFFFFFFull;
+    if (s1 == 0 || s1 > res_.size()) return kNoSlot;
+    const uint32_t slot = (uint32_t)(s1 - 1);
+    const Resident& r = res_[slot];
+    if (!r.live || r.retired || r.gen != (uint32_t)(h >> 32)) return kNoSlot;
+    return slot;
   }
-  bool free_resident(uint32_t h) {
-    if (h == 0 || h > res_.size() || !res_[h - 1].live) return false;
-    arena_.release(res_[h - 1].off);
-    res_[h - 1].live = false;
+  const Resident* resident(uint64_t h) const {
+    const uint32_t s = slot_of(h);
+    return s == kNoSlot ? nullptr : &res_[s];
+  }
+  // Retire handle h.  Its range goes back to the arena now if no request
+  // holds it, else when the last holder completes.  False if h is not a
+  // live handle.
+  bool free_resident(uint64_t h) {
+    const uint32_t s = slot_of(h);
+    if (s == kNoSlot) return false;
+    Resident& r = res_[s];
+    r.retired = true;
+    if (r.refs == 0) reclaim(s);
+    else stats_.deferred_frees++;
     return true;
   }
+  // Hold vector h for the caller's own use of its memory (for example an
+  // unpack); returns its slot (kNoSlot if h is not live).  Pair with unpin.
+  uint32_t pin(uint64_t h) {
+    const uint32_t s = slot_of(h);
+    if (s != kNoSlot) res_[s].refs++;
+    return s;
+  }
+  void unpin(uint32_t slot) { unref(slot); }
+  size_t resident_slots() const { return res_.size(); }
+  size_t live_residents() const { return arena_.live_count(); }
 
   // ---- requests (caller holds mutex) ----
-  void submit(const SchedRequest& r) {
+  // Queue r (id, op, e, m, round, n and c_bytes set by the caller) on
+  // operands ha and hb.  Checks that both handles are live, of r's format
+  // and at least n long, and that the result could ever fit in the arena;
+  // returns BFP_OK or the error, and on success holds both operands until
+  // the request completes.
+  int submit(SchedRequest r, uint64_t ha, uint64_t hb) {
+    const uint32_t sa = slot_of(ha), sb = slot_of(hb);
+    if (sa == kNoSlot || sb == kNoSlot) return BFP_E_ARG;
+    const Resident& ra = res_[sa];
+    const Resident& rb = res_[sb];
+    if (ra.e != r.e || ra.m != r.m || rb.e != r.e || rb.m != r.m) return BFP_E_FORMAT;
+    if (r.n == 0 || r.n > ra.n || r.n > rb.n) return BFP_E_ARG;  // a prefix of each operand
+    if (Arena::round(r.c_bytes) > arena_.capacity()) return BFP_E_BUDGET;
+    r.a_off = ra.off;
+    r.b_off = rb.off;
+    r.na = ra.n;
+    r.nb = rb.n;
+    r.a_slot = sa;
+    r.b_slot = sb;
+    r.c_slot = kNoSlot;
+    r.c_handle = 0;
+    r.status = 0;
+    res_[sa].refs++;
+    res_[sb].refs++;
+    r.t_submit = now_ns();
     pending_.push_back(r);
-    pending_.back().t_submit = now_ns();
     stats_.submitted++;
+    return BFP_OK;
   }
 
-  // One scheduling pass (caller holds mutex): collect finished ticks, admit,
-  // launch.  Returns true if anything changed.
+  // Withdraw a request that has not been launched: it completes with
+  // BFP_E_CANCELLED and releases what it held.  BFP_E_BUSY if it is on the
+  // device (it then completes normally), BFP_E_ARG if no request with this
+  // id is queued or running.
+  int cancel(uint64_t id) {
+    for (auto it = pending_.begin(); it != pending_.end(); ++it)
+      if (it->id == id) {
+        SchedRequest r = *it;
+        pending_.erase(it);
+        drop(r, BFP_E_CANCELLED);
+        stats_.cancelled++;
+        return BFP_OK;
+      }
+    for (auto it = next_.begin(); it != next_.end(); ++it)
+      if (it->id == id) {
+        SchedRequest r = *it;
+        next_.erase(it);
+        drop(r, BFP_E_CANCELLED);
+        stats_.cancelled++;
+        return BFP_OK;
+      }
+    return launched_.count(id) ? BFP_E_BUSY : BFP_E_ARG;
+  }
+
   // One scheduling pass: completions, FIFO admission, and a launch of the
   // admitted requests on a free stream.  Equivalent to collect(), launching
-  // the returned batch, and commit().
+  // the returned batch, and commit().  Returns true if anything changed.
   bool step() {
     std::vector<SchedRequest> batch;
     bool changed = collect(&batch);
@@ -175,11 +278,11 @@ class Scheduler {
     return changed;
   }
 
-  // Completions and admission; if a stream is free and requests were
-  // admitted, moves them into *batch (stamped with their launch time) and
-  // reserves the stream.  The caller launches the batch on the executor --
-  // without the scheduler's lock if it holds one, since only the scheduling
-  // thread touches the executor -- and then calls commit().
+  // Completions, expiry and admission; if a stream is free and requests
+  // were admitted, moves them into *batch (stamped with their launch time)
+  // and reserves the stream.  The caller launches the batch on the executor
+  // -- without the scheduler's lock if it holds one, since only the
+  // scheduling thread touches the executor -- and then calls commit().
   bool collect(std::vector<SchedRequest>* batch) {
     bool changed = false;
     // completions
@@ -190,27 +293,42 @@ class Scheduler {
       for (auto& r : done) {
         r.t_done = t;
         inflight_reqs_--;
-        if (autofree_ && r.status == 0) {
-          free_resident(r.c_handle);
-          r.c_handle = 0;
-        }
-        completed_.push_back(r);
-        stats_.completed++;
+        launched_.erase(r.id);
+        finish(r);
       }
       done.clear();
       inflight_ticks_--;
     }
+    // expiry: submission times grow along both queues
+    if (queue_timeout_ns_ > 0) {
+      const int64_t limit = now_ns() - queue_timeout_ns_;
+      while (!next_.empty() && next_.front().t_submit < limit) {
+        SchedRequest r = next_.front();
+        next_.erase(next_.begin());
+        drop(r, BFP_E_TIMEOUT);
+        stats_.timed_out++;
+        changed = true;
+      }
+      while (!pending_.empty() && pending_.front().t_submit < limit) {
+        SchedRequest r = pending_.front();
+        pending_.pop_front();
+        drop(r, BFP_E_TIMEOUT);
+        stats_.timed_out++;
+        changed = true;
+      }
+    }
     // admission: FIFO, needs a slot and room for the result
     while (!pending_.empty() && inflight_reqs_ + (int)next_.size() < slots_) {
       SchedRequest& r = pending_.front();
-      uint64_t off;
-      uint32_t h;
+      uint64_t off, h;
       if (!alloc_resident(r.c_bytes, r.e, r.m, r.n, &h, &off)) {
         stats_.deferred_budget++;
         break;
       }
       r.c_off = off;
       r.c_handle = h;
+      r.c_slot = (uint32_t)((h & 0xFFFFFFFFull) - 1);
+      res_[r.c_slot].refs++;  // the result is held until its request completes
       r.t_admit = now_ns();
       next_.push_back(r);
       pending_.pop_front();
@@ -220,7 +338,10 @@ class Scheduler {
     // hand a tick to the caller if a stream is free
     if (!next_.empty() && inflight_ticks_ < Executor::kStreams) {
       const int64_t t = now_ns();
-      for (auto& r : next_) r.t_launch = t;
+      for (auto& r : next_) {
+        r.t_launch = t;
+        launched_.insert(r.id);
+      }
       batch->swap(next_);
       next_.clear();
       inflight_ticks_++;          // the stream is taken until commit() or the tick's completion
@@ -237,13 +358,11 @@ class Scheduler {
     if (st != 0) {
       inflight_ticks_--;
       inflight_reqs_ -= (int)batch->size();
+      const int64_t t = now_ns();
       for (auto& r : *batch) {  // failed launch: release the results, report the error
-        free_resident(r.c_handle);
-        r.c_handle = 0;
-        r.status = st;
-        r.t_done = now_ns();
-        completed_.push_back(r);
-        stats_.completed++;
+        launched_.erase(r.id);
+        r.t_done = t;
+        drop(r, st);
       }
     } else {
       stats_.ticks++;
@@ -271,16 +390,57 @@ class Scheduler {
   const SchedStats& stats() const { return stats_; }
 
  private:
+  void reclaim(uint32_t s) {
+    Resident& r = res_[s];
+    arena_.release(r.off);
+    r.live = false;
+    r.retired = false;
+    r.refs = 0;
+    r.gen = r.gen + 1u ? r.gen + 1u : 1u;  // generation 0 is never issued
+    free_slots_.push_back(s);
+  }
+  void unref(uint32_t s) {
+    if (s == kNoSlot || s >= res_.size()) return;
+    Resident& r = res_[s];
+    if (!r.live || r.refs == 0) return;
+    if (--r.refs == 0 && r.retired) reclaim(s);
+  }
+  // A request that ran: drop its holds on the operands and the result (the
+  // result stays live for the caller unless autofree is on).
+  void finish(SchedRequest& r) {
+    unref(r.a_slot);
+    unref(r.b_slot);
+    if (r.c_slot != kNoSlot) {
+      unref(r.c_slot);
+      if (r.status != 0 || autofree_) {
+        free_resident(r.c_handle);
+        r.c_handle = 0;
+      }
+    }
+    completed_.push_back(r);
+    stats_.completed++;
+  }
+  // A request that did not run (cancelled, expired or a failed launch):
+  // complete it with `status`; its result, if admitted, is freed.
+  void drop(SchedRequest& r, int status) {
+    r.status = status;
+    if (!r.t_done) r.t_done = now_ns();
+    finish(r);
+  }
+
   Executor& ex_;
   Arena arena_;
   int slots_;
   std::mutex mu_;
   std::vector<Resident> res_;
+  std::deque<uint32_t> free_slots_;  // reused oldest first, so a slot's generations advance slowly
   std::deque<SchedRequest> pending_;
   std::vector<SchedRequest> next_;
   std::deque<SchedRequest> completed_;
+  std::unordered_set<uint64_t> launched_;  // ids handed to the executor and not yet completed
   int inflight_reqs_ = 0;
   int inflight_ticks_ = 0;
+  int64_t queue_timeout_ns_ = 0;
   bool autofree_ = false;
   SchedStats stats_;
 };

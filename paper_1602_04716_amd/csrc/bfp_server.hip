@@ -43,7 +43,7 @@ struct HipExecutor {
     std::vector<SchedRequest> reqs;
   };
   uint8_t* base = nullptr;  // arena base (device)
-  int cap_main = 0, cap_div = 0;  // resident blocks of the two persistent kernels
+  int cap[kBatchClasses] = {};  // resident blocks of each class kernel
   Slot slot[kStreams];
   uint64_t seq = 0;
   std::vector<BatchTask> tasks;
@@ -78,9 +78,10 @@ struct HipExecutor {
   }
 
   bool init() {
-    cap_main = batch_resident_blocks(false);
-    cap_div = batch_resident_blocks(true);
-    if (cap_main <= 0 || cap_div <= 0) return false;
+    for (int c = 0; c < kBatchClasses; ++c) {
+      cap[c] = batch_resident_blocks(c);
+      if (cap[c] <= 0) return false;
+    }
     for (Slot& s : slot) {
       if (hipStreamCreateWithFlags(&s.stream, hipStreamNonBlocking) != hipSuccess) return false;
       if (hipEventCreateWithFlags(&s.done, hipEventDisableTiming) != hipSuccess) return false;
@@ -132,7 +133,7 @@ struct HipExecutor {
         hipMemcpyAsync(s->d_chunks, s->h_chunks, chunks.size() * sizeof(BatchChunk), hipMemcpyHostToDevice,
                        s->stream) != hipSuccess)
       return BFP_E_HIP;
-    const BatchSplit split = batch_split(tasks, chunks, cap_main, cap_div);
+    const BatchSplit split = batch_split(tasks, chunks, cap);
     if (batch_launch(s->d_tasks, s->d_chunks, split, s->d_counter, s->stream) != hipSuccess) return BFP_E_HIP;
     if (hipEventRecord(s->done, s->stream) != hipSuccess) return BFP_E_HIP;
     s->busy = true;
@@ -252,12 +253,12 @@ void bfp_server_destroy(bfp_server* s) {
 }
 
 bfp_status bfp_server_put(bfp_server* s, bfp_format f, const void* std_dev, uint64_t n, void* stream,
-                          uint32_t* handle) {
+                          bfp_handle* handle) {
   if (!s || !std_dev || !handle) return BFP_E_NULL;
   if (!bfp_format_supported(f)) return BFP_E_FORMAT;
   if (n == 0 || n > (1ull << 36)) return BFP_E_ARG;
   uint64_t off;
-  uint32_t h;
+  bfp_handle h;
   {
     std::lock_guard<std::mutex> lk(s->sched->mutex());
     if (!s->sched->alloc_resident(bitslice_bytes_of(f.e, f.m, n), f.e, f.m, n, &h, &off)) return BFP_E_BUDGET;
@@ -273,36 +274,39 @@ bfp_status bfp_server_put(bfp_server* s, bfp_format f, const void* std_dev, uint
   return BFP_OK;
 }
 
-bfp_status bfp_server_submit(bfp_server* s, int op, bfp_format f, uint32_t a, uint32_t b, uint64_t n,
+bfp_status bfp_server_submit(bfp_server* s, int op, bfp_format f, bfp_handle a, bfp_handle b, uint64_t n,
                              uint64_t* req_id) {
   if (!s || !req_id) return BFP_E_NULL;
   if (!op_valid(op)) return BFP_E_OP;
   if (!bfp_format_supported(f) || !batch_format_ok(f)) return BFP_E_FORMAT;
+  SchedRequest r;
+  r.op = op;
+  r.e = f.e;
+  r.m = f.m;
+  r.round = f.round;
+  r.n = n;
+  r.c_bytes = n ? bitslice_bytes_of(f.e, f.m, n) : 0;
   {
     std::lock_guard<std::mutex> lk(s->sched->mutex());
-    const Resident* ra = s->sched->resident(a);
-    const Resident* rb = s->sched->resident(b);
-    if (!ra || !rb) return BFP_E_ARG;
-    if (ra->e != f.e || ra->m != f.m || rb->e != f.e || rb->m != f.m) return BFP_E_FORMAT;
-    if (n == 0 || n > ra->n || n > rb->n) return BFP_E_ARG;  // a prefix of each operand
-    const uint64_t cb = bitslice_bytes_of(f.e, f.m, n);
-    if (Arena::round(cb) > s->sched->capacity()) return BFP_E_BUDGET;
-    SchedRequest r;
     r.id = s->next_id.fetch_add(1);
-    r.op = op;
-    r.e = f.e;
-    r.m = f.m;
-    r.round = f.round;
-    r.n = n;
-    r.a_off = ra->off;
-    r.b_off = rb->off;
-    r.na = ra->n;
-    r.nb = rb->n;
-    r.c_bytes = cb;
-    s->sched->submit(r);
+    const int st = s->sched->submit(r, a, b);
+    if (st != BFP_OK) return st;
     *req_id = r.id;
   }
   s->cv.notify_one();
+  return BFP_OK;
+}
+
+bfp_status bfp_server_cancel(bfp_server* s, uint64_t req_id) {
+  if (!s) return BFP_E_NULL;
+  std::lock_guard<std::mutex> lk(s->sched->mutex());
+  return s->sched->cancel(req_id);
+}
+
+bfp_status bfp_server_set_queue_timeout(bfp_server* s, int64_t timeout_ns) {
+  if (!s) return BFP_E_NULL;
+  std::lock_guard<std::mutex> lk(s->sched->mutex());
+  s->sched->set_queue_timeout(timeout_ns);
   return BFP_OK;
 }
 
@@ -370,12 +374,12 @@ bfp_status bfp_server_wait_idle(bfp_server* s, int64_t timeout_ms) {
       std::lock_guard<std::mutex> lk(s->sched->mutex());
       if (s->sched->idle()) return BFP_OK;
     }
-    if (now_ns() > deadline) return BFP_E_ARG;
+    if (now_ns() > deadline) return BFP_E_TIMEOUT;
     std::this_thread::sleep_for(std::chrono::microseconds(50));
   }
 }
 
-bfp_status bfp_server_view(bfp_server* s, uint32_t handle, void** bitslice_dev, uint64_t* n) {
+bfp_status bfp_server_view(bfp_server* s, bfp_handle handle, void** bitslice_dev, uint64_t* n) {
   if (!s || !bitslice_dev || !n) return BFP_E_NULL;
   std::lock_guard<std::mutex> lk(s->sched->mutex());
   const Resident* r = s->sched->resident(handle);
@@ -385,23 +389,29 @@ bfp_status bfp_server_view(bfp_server* s, uint32_t handle, void** bitslice_dev, 
   return BFP_OK;
 }
 
-bfp_status bfp_server_get(bfp_server* s, uint32_t handle, bfp_format f, void* std_dev_out, void* stream) {
+bfp_status bfp_server_get(bfp_server* s, bfp_handle handle, bfp_format f, void* std_dev_out, void* stream) {
   if (!s || !std_dev_out) return BFP_E_NULL;
-  void* p;
-  uint64_t n;
-  bfp_status st = bfp_server_view(s, handle, &p, &n);
-  if (st != BFP_OK) return st;
+  uint32_t slot;
+  uint64_t off, n;
   {
     std::lock_guard<std::mutex> lk(s->sched->mutex());
     const Resident* r = s->sched->resident(handle);
-    if (!r || r->e != f.e || r->m != f.m) return BFP_E_FORMAT;
+    if (!r) return BFP_E_ARG;
+    if (r->e != f.e || r->m != f.m) return BFP_E_FORMAT;
+    off = r->off;
+    n = r->n;
+    slot = s->sched->pin(handle);  // a concurrent free waits for the unpack
   }
-  st = bfp_unpack(f, p, std_dev_out, n, stream);
+  bfp_status st = bfp_unpack(f, static_cast<uint8_t*>(s->arena) + off, std_dev_out, n, stream);
   if (st == BFP_OK && hipStreamSynchronize((hipStream_t)stream) != hipSuccess) st = BFP_E_HIP;
+  {
+    std::lock_guard<std::mutex> lk(s->sched->mutex());
+    s->sched->unpin(slot);
+  }
   return st;
 }
 
-bfp_status bfp_server_free(bfp_server* s, uint32_t handle) {
+bfp_status bfp_server_free(bfp_server* s, bfp_handle handle) {
   if (!s) return BFP_E_NULL;
   std::lock_guard<std::mutex> lk(s->sched->mutex());
   return s->sched->free_resident(handle) ? BFP_OK : BFP_E_ARG;
@@ -423,6 +433,11 @@ bfp_status bfp_server_stats_get(bfp_server* s, bfp_server_stats* out) {
   out->deferred_budget = st.deferred_budget;
   out->pending = s->sched->pending();
   out->inflight = (uint64_t)s->sched->inflight_requests();
+  out->deferred_frees = st.deferred_frees;
+  out->cancelled = st.cancelled;
+  out->timed_out = st.timed_out;
+  out->live_vectors = s->sched->live_residents();
+  out->table_slots = s->sched->resident_slots();
   return BFP_OK;
 }
 

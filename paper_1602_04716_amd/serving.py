@@ -52,6 +52,12 @@ class Server:
     def free(self, handle: int):
         bfp.bfp_server_free(self.h, handle)
 
+    def cancel(self, req_id: int):
+        bfp.bfp_server_cancel(self.h, req_id)
+
+    def set_queue_timeout(self, timeout_ns: int):
+        bfp.bfp_server_set_queue_timeout(self.h, timeout_ns)
+
     def get(self, handle: int, f, out_dev):
         bfp.bfp_server_get(self.h, handle, f, out_dev)
 
@@ -83,22 +89,28 @@ class Server:
             pass
 
 
-def build_pool(server: Server, formats, n: int, seed: int, device, sample_log2: int = 18):
+def build_pool(server: Server, formats, n: int, seed: int, device, sample_log2: int = 18, host_out=None):
     """Two resident operands of n elements per format, values from the sweep
     recipe (a 2^sample_log2-element draw repeated to length n: the circuits'
-    cost does not depend on the values)."""
+    cost does not depend on the values).  If host_out is a dict, it receives
+    host_out[(e, m)] = (xa, xb): the draws put, element i of an operand being
+    x[i % len(x)]."""
     import torch
     pool = {}
     for i, (e, m) in enumerate(formats):
         f = bfp.fmt(e, m)
         hs = []
+        xs = []
         for j in range(2):
             k = min(n, 1 << sample_log2)
             x = inputs.sweep_operands(e, m, k, seed * 100 + 2 * i + j)
             reps = (n + k - 1) // k
             t = torch.from_numpy(np.tile(x, reps)[:n].copy()).to(device)
             hs.append(server.put(f, t))
+            xs.append(x)
         pool[(e, m)] = (hs[0], hs[1], n)
+        if host_out is not None:
+            host_out[(e, m)] = (xs[0], xs[1])
     torch.cuda.synchronize()
     return pool
 
@@ -186,7 +198,7 @@ def run_native(server: Server, pool, reqs, rate=None, rnd: int = 0, seed: int = 
     while len(comp) < n_req:
         got = server.poll()
         for c in got:
-            comp[c.req_id] = (c.status, c.result, c.t_submit_ns, c.t_done_ns, c.t_launch_ns)
+            comp[c.req_id] = (c.status, c.result, c.t_submit_ns, c.t_done_ns, c.t_launch_ns, c.t_admit_ns)
         if not got:
             if time.perf_counter() > deadline:
                 raise RuntimeError("serving stalled: %d of %d complete, stats %s" % (len(comp), n_req,
@@ -201,7 +213,15 @@ def run_native(server: Server, pool, reqs, rate=None, rnd: int = 0, seed: int = 
     window = (t_last - t_first) / 1e9
     elements = sum(reqs[k][2] for k in range(skip, n_req))
     bad = sum(1 for r in ids if comp[r][0] != 0)
+    # where the time goes: queued (submit -> launch: waiting for a slot, the
+    # budget or a free stream) and on the device (launch -> completion seen)
+    queue = np.array([(comp[r][4] - comp[r][2]) / 1e3 for r in meas])
+    dev = np.array([(comp[r][3] - comp[r][4]) / 1e3 for r in meas])
+    slow = lat >= np.percentile(lat, 99)
     return {"requests": len(meas), "errors": bad, "elements": elements, "window_s": window,
             "requests_per_s": len(meas) / window, "elements_per_s": elements / window,
             "p50_us": float(np.percentile(lat, 50)), "p99_us": float(np.percentile(lat, 99)),
-            "mean_us": float(lat.mean()), "rate": rate}
+            "mean_us": float(lat.mean()), "rate": rate,
+            "queue_p50_us": float(np.percentile(queue, 50)), "queue_p99_us": float(np.percentile(queue, 99)),
+            "device_p50_us": float(np.percentile(dev, 50)), "device_p99_us": float(np.percentile(dev, 99)),
+            "slowest1pct_queue_us": float(queue[slow].mean()), "slowest1pct_device_us": float(dev[slow].mean())}
