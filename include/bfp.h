@@ -298,6 +298,23 @@ bfp_status bfp_batch_plan_info(const bfp_batch_plan* plan, uint32_t* nchunks, ui
  * runs to finish first. */
 void bfp_batch_plan_destroy(bfp_batch_plan* plan);
 
+/* For callers that cannot allocate -- code under HIP graph capture, tight
+ * serving loops, harnesses that forbid hipMalloc: the batched launch of
+ * bfp_batch_plan_create + bfp_batch_run in one call that allocates nothing.
+ * `tasks_dev` is an array of `count` bfp_task in DEVICE memory (8-byte
+ * aligned, caller-owned, read on `stream`).  A one-block kernel checks every
+ * task as bfp_batch_plan_create does, writes the descriptors and the chunk
+ * index into a static device array of the library (about 1.7 MB per device,
+ * held until the process ends), and the persistent class kernels then run the
+ * chunks in task order.  The status of the check (BFP_OK, or the error of the
+ * first invalid task: BFP_E_FORMAT, BFP_E_OP, BFP_E_ARG, BFP_E_NULL,
+ * BFP_E_ALIGN) is written to *status_dev (device int32) on `stream`; with any
+ * invalid task nothing is computed.  Host-side errors: BFP_E_NULL, BFP_E_ARG
+ * (count 0 or above 16384 tasks), BFP_E_ALIGN, BFP_E_HIP.  Every call on one
+ * device shares that device's array: calls that overlap on one device (two
+ * streams, or two threads) race and must be serialised by the caller. */
+bfp_status bfp_batch_run_noalloc(const bfp_task* tasks_dev, uint32_t count, int32_t* status_dev, void* stream);
+
 /* ---- serving loop ---------------------------------------------------------- */
 /* A request loop over device-resident bitslice vectors (not in the paper;
  * it serves the Section 4 operations).  The server owns one device arena of

@@ -128,6 +128,7 @@ _SIGS = {
     "bfp_batch_plan_info": (ctypes.c_int, [ctypes.c_void_p, ctypes.POINTER(ctypes.c_uint32),
                                            ctypes.POINTER(ctypes.c_uint32), ctypes.POINTER(ctypes.c_uint64)]),
     "bfp_batch_plan_destroy": (None, [ctypes.c_void_p]),
+    "bfp_batch_run_noalloc": (ctypes.c_int, [ctypes.c_void_p, ctypes.c_uint32, ctypes.c_void_p, ctypes.c_void_p]),
     "bfp_server_create": (ctypes.c_int, [ctypes.c_uint64, ctypes.c_int32, ctypes.POINTER(ctypes.c_void_p)]),
     "bfp_server_put": (ctypes.c_int, [ctypes.c_void_p, bfp_format, ctypes.c_void_p, ctypes.c_uint64,
                                       ctypes.c_void_p, ctypes.POINTER(ctypes.c_uint64)]),
@@ -382,6 +383,24 @@ def bfp_batch_plan_create(tasks) -> int:
     h = ctypes.c_void_p()
     _check(lib().bfp_batch_plan_create(arr, len(tasks), ctypes.byref(h)), "bfp_batch_plan_create")
     return h.value
+
+
+def task_table(tasks, device="cuda"):
+    """A device array of bfp_task for bfp_batch_run_noalloc: tasks as for
+    bfp_batch_plan_create, (a, b, c, n, format, op)."""
+    import torch
+    arr = (bfp_task * len(tasks))()
+    for i, (a, b, c, n, f, op) in enumerate(tasks):
+        arr[i] = bfp_task(_ptr(a), _ptr(b), _ptr(c), n, f, _op(op))
+    host = torch.frombuffer(bytearray(bytes(arr)), dtype=torch.uint8)
+    return host.to(device)
+
+
+def bfp_batch_run_noalloc(tasks_dev, count: int, status_dev, stream=None):
+    """Run `count` tasks from a device task table (task_table) without any
+    allocation; the check's status lands in status_dev (a device int32)."""
+    _check(lib().bfp_batch_run_noalloc(_ptr(tasks_dev), count, _ptr(status_dev), _stream(stream)),
+           "bfp_batch_run_noalloc")
 
 
 def bfp_batch_run(plan: int, stream=None):

@@ -398,3 +398,163 @@ void bfp_batch_plan_destroy(bfp_batch_plan* plan) { plan_free(plan); }
 
 }  // extern "C"
 
+// ---------------------------------------------------------------------------
+// Allocation-free batched launch: descriptors built on the device into a
+// static scratch array, for callers that cannot allocate.
+// ---------------------------------------------------------------------------
+namespace bfp {
+namespace {
+
+constexpr uint32_t kNoallocMaxTasks = 16384;
+constexpr size_t kNoallocTasksOff = 256;  // after the BatchIndex header
+constexpr size_t kNoallocPrefixOff = kNoallocTasksOff + sizeof(BatchTask) * kNoallocMaxTasks;
+constexpr size_t kNoallocPrefixWords = kNoallocMaxTasks + 1;  // per class
+constexpr size_t kNoallocBytes = kNoallocPrefixOff + kBatchClasses * sizeof(uint64_t) * kNoallocPrefixWords;
+static_assert(sizeof(BatchIndex) <= kNoallocTasksOff, "index header must fit before the tasks");
+static_assert(kNoallocPrefixOff % 256 == 0, "prefix arrays 256-byte aligned");
+// Chunk counters must stay below 2^32 (uint32 counters).
+constexpr uint64_t kNoallocMaxChunks = 0xFFF00000ull;
+
+// Index header, task table and the class kernels' chunk prefix arrays: about
+// 1.7 MB per device, held until the process ends.  In host code this name
+// is a stand-in, not a device address: host code uses the address from
+// hipGetSymbolAddress (noalloc_device).
+static __device__ __align__(256) unsigned char scratch[kNoallocBytes];
+
+// First invalid task's error, checked in the same order as
+// bfp_batch_plan_create checks a task on the host.
+__device__ int32_t task_error(const bfp_task& t) {
+  if (t.f.pad != 0 || t.f.round > 1 || format_index(t.f.e, t.f.m) < 0) return BFP_E_FORMAT;
+  if (t.op != BFP_ADD && t.op != BFP_SUB && t.op != BFP_MUL && t.op != BFP_DIV) return BFP_E_OP;
+  if (t.n == 0 || t.n > (1ull << 36)) return BFP_E_ARG;
+  if (!t.a || !t.b || !t.c) return BFP_E_NULL;
+  if (((uintptr_t)t.a | (uintptr_t)t.b | (uintptr_t)t.c) & 15u) return BFP_E_ALIGN;
+  return BFP_OK;
+}
+
+// One block: validate the tasks, write their descriptors and each class's
+// exclusive chunk prefix (block scan in tiles of 1024 tasks with a running
+// carry), reset the counters, and report the status.  Any invalid task
+// leaves every total 0, so nothing runs.
+__global__ void __launch_bounds__(1024) k_noalloc_setup(const bfp_task* in, uint32_t count, unsigned char* scr,
+                                                        int32_t* status_out) {
+  BatchIndex* idx = reinterpret_cast<BatchIndex*>(scr);
+  BatchTask* tasks = reinterpret_cast<BatchTask*>(scr + kNoallocTasksOff);
+  uint64_t* prefix = reinterpret_cast<uint64_t*>(scr + kNoallocPrefixOff);  // [class][count + 1]
+  __shared__ uint64_t s_scan[kBatchClasses][1024];
+  __shared__ uint64_t s_carry[kBatchClasses];
+  __shared__ uint32_t s_bad;
+  const uint32_t tid = threadIdx.x;
+  if (tid < kBatchClasses) s_carry[tid] = 0;
+  if (tid == 0) s_bad = count;
+  __syncthreads();
+  for (uint32_t base = 0; base < count; base += 1024) {
+    const uint32_t i = base + tid;
+    uint64_t cnt[kBatchClasses] = {};
+    if (i < count) {
+      const bfp_task t = in[i];
+      BatchTask bt;
+      if (task_error(t) != BFP_OK || !make_batch_task(t.a, t.n, t.b, t.n, t.c, t.n, t.f, t.op, &bt)) {
+        atomicMin(&s_bad, i);
+      } else {
+        tasks[i] = bt;
+        const int opc = t.op == BFP_MUL ? 1 : (t.op == BFP_DIV ? 2 : 0);
+        cnt[variant_class(t.f.m, opc)] = (bt.words + kChunkWords - 1) / kChunkWords;
+      }
+    }
+#pragma unroll
+    for (int c = 0; c < kBatchClasses; ++c) s_scan[c][tid] = cnt[c];
+    __syncthreads();
+    for (uint32_t d = 1; d < 1024; d <<= 1) {  // inclusive Hillis-Steele scan
+      uint64_t x[kBatchClasses];
+#pragma unroll
+      for (int c = 0; c < kBatchClasses; ++c) x[c] = tid >= d ? s_scan[c][tid - d] : 0;
+      __syncthreads();
+#pragma unroll
+      for (int c = 0; c < kBatchClasses; ++c) s_scan[c][tid] += x[c];
+      __syncthreads();
+    }
+    if (i < count) {
+#pragma unroll
+      for (int c = 0; c < kBatchClasses; ++c) prefix[c * kNoallocPrefixWords + i] = s_carry[c] + s_scan[c][tid] - cnt[c];
+    }
+    __syncthreads();
+    if (tid < kBatchClasses) s_carry[tid] += s_scan[tid][1023];
+    __syncthreads();
+  }
+  if (tid == 0) {
+    int32_t st = BFP_OK;
+    if (s_bad < count) {
+      st = task_error(in[s_bad]);
+      if (st == BFP_OK) st = BFP_E_FORMAT;  // a task the batch kernels do not compile
+    }
+    for (int c = 0; c < kBatchClasses; ++c) {
+      prefix[c * kNoallocPrefixWords + count] = s_carry[c];
+      if (s_carry[c] >= kNoallocMaxChunks && st == BFP_OK) st = BFP_E_ARG;
+    }
+    for (int c = 0; c < kBatchClasses; ++c) {
+      idx->counter[c] = 0u;
+      idx->total[c] = st == BFP_OK ? s_carry[c] : 0;
+    }
+    idx->ntasks = count;
+    idx->status = st;
+    *status_out = st;
+  }
+}
+
+struct NoallocDevice {
+  unsigned char* ptr = nullptr;  // device address of `scratch` on this device
+  int cap[kBatchClasses] = {};
+  bool ready = false;
+};
+std::mutex g_noalloc_mu;
+NoallocDevice g_noalloc[64];
+
+// Scratch address and resident grids of the current device, set up once per
+// device with that device current.
+bool noalloc_device(NoallocDevice* out) {
+  int dev = 0;
+  if (hipGetDevice(&dev) != hipSuccess || dev < 0 || dev >= 64) return false;
+  std::lock_guard<std::mutex> lk(g_noalloc_mu);
+  NoallocDevice& d = g_noalloc[dev];
+  if (!d.ready) {
+    void* p = nullptr;
+    if (hipGetSymbolAddress(&p, HIP_SYMBOL(scratch)) != hipSuccess || !p) return false;
+    for (int c = 0; c < kBatchClasses; ++c) {
+      d.cap[c] = batch_resident_blocks(c);
+      if (d.cap[c] <= 0) return false;
+    }
+    d.ptr = static_cast<unsigned char*>(p);
+    d.ready = true;
+  }
+  *out = d;
+  return true;
+}
+
+template <int CLS>
+void launch_indexed(const NoallocDevice& d, hipStream_t s) {
+  BatchIndex* idx = reinterpret_cast<BatchIndex*>(d.ptr);
+  const BatchTask* tasks = reinterpret_cast<const BatchTask*>(d.ptr + kNoallocTasksOff);
+  const uint64_t* prefix = reinterpret_cast<const uint64_t*>(d.ptr + kNoallocPrefixOff) + CLS * kNoallocPrefixWords;
+  hipLaunchKernelGGL((k_batch<CLS>), dim3(d.cap[CLS]), dim3(kBatchBlock), 0, s, tasks, nullptr, 0u, 0u,
+                     &idx->counter[CLS], idx, prefix);
+}
+
+}  // namespace
+}  // namespace bfp
+
+extern "C" bfp_status bfp_batch_run_noalloc(const bfp_task* tasks_dev, uint32_t count, int32_t* status_dev,
+                                            void* stream) {
+  if (!tasks_dev || !status_dev) return BFP_E_NULL;
+  if (count == 0 || count > kNoallocMaxTasks) return BFP_E_ARG;
+  if (((uintptr_t)tasks_dev & 7u) || ((uintptr_t)status_dev & 3u)) return BFP_E_ALIGN;
+  NoallocDevice d;
+  if (!noalloc_device(&d)) return BFP_E_HIP;
+  hipStream_t s = (hipStream_t)stream;
+  hipLaunchKernelGGL(k_noalloc_setup, dim3(1), dim3(1024), 0, s, tasks_dev, count, d.ptr, status_dev);
+  launch_indexed<0>(d, s);
+  launch_indexed<1>(d, s);
+  launch_indexed<2>(d, s);
+  launch_indexed<3>(d, s);
+  return hipGetLastError() == hipSuccess ? BFP_OK : BFP_E_HIP;
+}
