@@ -8,15 +8,27 @@ bitslice vectors, unpack the three results.  ``value`` counts elementwise
 operations (2 formats x 3 ops x 2^26 elements per step) per second with the
 inputs already in HBM.
 
+The headline workload fixes 64-element lane words (two 32-bit words per
+lane) for its add/sub/mul launches, as the workload prescribes, instead of
+the tuned table's choice; every other section uses the tuned table.
+
 Also printed in the same JSON line:
   roofline      the dominant kernel (largest share of the step) against
-                MI355X's peak (HBM 8 TB/s, or the bitwise VALU rate); its
-                duration comes from a second timed pass of the same steps with
-                HIP events around each group of its launches on the kernels'
-                stream (the first, event-free pass gives ``value``);
-  kernels       every kernel's mean duration and rates, measured the same way;
+                MI355X's peak (HBM 8 TB/s, or the bitwise VALU rate), and
+                against the box's own measured ceiling (best read, write and
+                copy sweeps over 1 GiB); its duration comes from a cold pass:
+                the same steps with a 1 GiB read sweep (outside the events)
+                before each group of launches of one kernel, and HIP events
+                around the group on the kernels' stream;
+  kernels       every kernel's mean duration and rates, cold as above, and
+                cache-assisted (``*_cache_assisted``: the same steps with
+                events around each group but no sweep, so a kernel may read
+                what the previous one left in the 256 MB last-level cache);
+  sweep         the 40-format sweep: add and mul on 2^24 elements per format,
+                tuned launches, each launch timed cold (median of 5);
   batched       4096 mixed vectors: one persistent launch vs one launch per
-                vector (skipped with --no-batched);
+                vector, the per-vector launches also replayed from a captured
+                graph (skipped with --no-batched);
   serving       the serving loop at saturation and at Poisson loads of 0.5
                 and 0.9 of it (skipped with --no-serving);
   div           division (Table 1, Div) on resident bitslice vectors of the
@@ -71,6 +83,8 @@ def parse():
     ap.add_argument("--no-int", action="store_true")
     ap.add_argument("--no-wide", action="store_true")
     ap.add_argument("--no-small", action="store_true")
+    ap.add_argument("--no-sweep", action="store_true")
+    ap.add_argument("--sweep-n-log2", type=int, default=24)
     ap.add_argument("--div-reps", type=int, default=10)
     ap.add_argument("--serving-requests", type=int, default=20000)
     return ap.parse_args()
@@ -80,6 +94,8 @@ def bench_batched(torch, bfp, dev, reps):
     """4096 vectors, lengths log-uniform in [1024, 2^20], random format of the
     40-format sweep and random op: one graph launch of the persistent kernel
     vs one launch per vector (both timed with events on one stream)."""
+    import numpy as np
+
     from paper_1602_04716_amd import inputs, workloads
     specs = inputs.batch_tasks(4096, seed=4)
     bt = workloads.build_batch(specs, seed=4, device=dev)
@@ -101,18 +117,41 @@ def bench_batched(torch, bfp, dev, reps):
         torch.cuda.synchronize()
         return ev0.elapsed_time(ev1) / reps
 
+    def cold(fn, k=5):
+        """Median of k launches, each after a 1 GiB read sweep outside the events."""
+        fn()
+        ts = []
+        for _ in range(k):
+            bfp.bfp_flush_llc(1 << 30, stream)
+            ev0 = torch.cuda.Event(enable_timing=True)
+            ev1 = torch.cuda.Event(enable_timing=True)
+            ev0.record(stream)
+            fn()
+            ev1.record(stream)
+            torch.cuda.synchronize()
+            ts.append(ev0.elapsed_time(ev1))
+        return float(np.median(ts))
+
     g_ms = timed(lambda: plan.run(stream))
     e_ms = timed(lambda: plan.run_eager(stream))
     v_ms = timed(lambda: plan.run_per_vector(stream))
+    vg_ms = timed(lambda: plan.run_per_vector_graph(stream))
+    g_cold = cold(lambda: plan.run(stream))
+    vg_cold = cold(lambda: plan.run_per_vector_graph(stream))
     info = plan.info()
     plan.close()
     nbytes = bt.bytes_moved()
     elems = bt.elements()
     return {"tasks": len(bt.specs), "elements": elems, "bytes": nbytes, "chunks": info["chunks"],
             "grid": info["grid"], "graph_ms": g_ms, "eager_persistent_ms": e_ms, "per_vector_ms": v_ms,
-            "speedup_vs_per_vector": v_ms / g_ms, "elements_per_s": elems / (g_ms * 1e-3),
+            "per_vector_graph_ms": vg_ms, "graph_ms_cold": g_cold, "per_vector_graph_ms_cold": vg_cold,
+            "speedup_vs_per_vector": v_ms / g_ms, "speedup_vs_per_vector_graph": vg_ms / g_ms,
+            "elements_per_s": elems / (g_ms * 1e-3),
             "per_vector_elements_per_s": elems / (v_ms * 1e-3),
-            "hbm_frac": nbytes / (g_ms * 1e-3) / HBM_PEAK, "valu_frac": ops_alg / (g_ms * 1e-3) / VALU_PEAK}
+            "per_vector_graph_elements_per_s": elems / (vg_ms * 1e-3),
+            "hbm_frac": nbytes / (g_ms * 1e-3) / HBM_PEAK, "valu_frac": ops_alg / (g_ms * 1e-3) / VALU_PEAK,
+            "hbm_frac_cold": nbytes / (g_cold * 1e-3) / HBM_PEAK,
+            "per_vector_graph_hbm_frac": nbytes / (vg_ms * 1e-3) / HBM_PEAK}
 
 
 def bench_serving(torch, bfp, dev, n_req):
@@ -135,7 +174,10 @@ def bench_serving(torch, bfp, dev, n_req):
         r = serving.run_native(srv, pool, serving.request_stream(n_req + 1000, fmts, seed=int(60 + 10 * frac)),
                                rate=frac * mu, seed=7, skip=1000)
         out["lambda_%.1f_mu" % frac] = {k: r[k] for k in ("rate", "requests", "requests_per_s", "elements_per_s",
-                                                           "p50_us", "p99_us", "mean_us", "errors")}
+                                                           "p50_us", "p99_us", "mean_us", "errors",
+                                                           "queue_p50_us", "queue_p99_us", "device_p50_us",
+                                                           "device_p99_us", "slowest1pct_queue_us",
+                                                           "slowest1pct_device_us")}
     st = srv.stats()
     out["high_water_bytes"] = st["high_water"]
     out["ticks"] = st["ticks"]
@@ -325,6 +367,61 @@ def bench_int(torch, bfp, dev, n, reps):
     return out
 
 
+def bench_sweep(torch, bfp, dev, n_log2, reps=5):
+    """The 40-format sweep: add and mul (nearest-even) on 2^n_log2 elements
+    per format, operands log-uniform over the normal range plus 1% subnormals
+    and zeros, the tuned launch table's configuration; each launch is timed
+    between events after a 1 GiB read sweep (the 6B MiB working set would
+    otherwise sit in the 256 MB last-level cache), median of `reps`."""
+    import numpy as np
+
+    from paper_1602_04716_amd import inputs
+    s = torch.cuda.current_stream()
+    n = 1 << n_log2
+    out = {"n": n, "formats": {}}
+    tot_el, tot_t = 0.0, 0.0
+    for (e, m) in inputs.sweep_formats():
+        f = bfp.fmt(e, m)
+        B = 1 + e + m
+        # a 2^20-element draw repeated to n (the circuits' time does not depend on the values)
+        k = min(n, 1 << 20)
+        xa = torch.from_numpy(inputs.sweep_operands(e, m, k, 100 + e * 32 + m)).to(dev).repeat((n + k - 1) // k)
+        xb = torch.from_numpy(inputs.sweep_operands(e, m, k, 200 + e * 32 + m)).to(dev).repeat((n + k - 1) // k)
+        pa = bfp.pack(f, xa[:n].contiguous())
+        pb = bfp.pack(f, xb[:n].contiguous())
+        del xa, xb
+        pc = bfp.empty_bitslice(f, n, dev)
+        row = {}
+        for op in ("add", "mul"):
+            bfp.bfp_binop(op, f, pa, pb, pc, n, s)
+            ts = []
+            for _ in range(reps):
+                bfp.bfp_flush_llc(1 << 30, s)
+                ev0, ev1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+                ev0.record(s)
+                bfp.bfp_binop(op, f, pa, pb, pc, n, s)
+                ev1.record(s)
+                torch.cuda.synchronize()
+                ts.append(ev0.elapsed_time(ev1) * 1e3)
+            us = float(np.median(ts))
+            G = bfp.bfp_gate_count(op, f)
+            cfg = bfp.bfp_launch_get(op, f)
+            row[op] = {"us": us, "elements_per_s": n / (us * 1e-6),
+                       "hbm_frac": 3 * B / 8 * n / (us * 1e-6) / HBM_PEAK,
+                       "valu_frac": G * n / 32 / (us * 1e-6) / VALU_PEAK,
+                       "words_per_lane": cfg.words_per_lane, "block": cfg.block}
+            tot_el += n
+            tot_t += us
+        out["formats"]["(%d,%d)" % (e, m)] = row
+        del pa, pb, pc
+    out["elements_per_s_all"] = tot_el / (tot_t * 1e-6)
+    fr = [r[op]["hbm_frac"] for r in out["formats"].values() for op in r]
+    vf = [r[op]["valu_frac"] for r in out["formats"].values() for op in r]
+    out["bound_frac_median"] = float(np.median([max(a, b) for a, b in zip(fr, vf)]))
+    out["bound_frac_min"] = float(min(max(a, b) for a, b in zip(fr, vf)))
+    return out
+
+
 def device_kernel(label):
     """Device kernel that a bench label ("unpack(8,7)", "mul(5,10)") launches
     with the bench's configuration (64-element lane words, nearest-even)."""
@@ -437,7 +534,7 @@ def main():
     # Launches of one kernel that follow each other form a group bracketed by
     # two events on the stream the kernels run on, so per-kernel durations come
     # from the timed steps themselves (group time / launches in the group).
-    groups = []  # (name, [launch fns], algorithmic bytes per launch, gate ops per launch)
+    groups = []  # (name, [launch fns], algorithmic bytes per launch, gate ops per launch, bytes read per launch)
     for (e, m) in FORMATS:
         f, a, b, pa, pb, pc, out = data[(e, m)]
         B = 1 + e + m
@@ -445,16 +542,17 @@ def main():
         tag = "(%d,%d)" % (e, m)
         io = n * (C + B / 8)
         groups.append(("pack" + tag, [lambda f=f, a=a, pa=pa: bfp.bfp_pack(f, a, pa, n, stream),
-                                      lambda f=f, b=b, pb=pb: bfp.bfp_pack(f, b, pb, n, stream)], io, 0))
+                                      lambda f=f, b=b, pb=pb: bfp.bfp_pack(f, b, pb, n, stream)], io, 0, n * C))
         for op in OPS:
             G = bfp.bfp_gate_count(op, f)
             groups.append((op + tag, [lambda f=f, pa=pa, pb=pb, pc=pc, op=op:
-                                      bfp.bfp_binop(op, f, pa, pb, pc[op], n, stream)], n * 3 * B / 8, G * n / 32))
+                                      bfp.bfp_binop(op, f, pa, pb, pc[op], n, stream)], n * 3 * B / 8, G * n / 32,
+                           n * 2 * B / 8))
         groups.append(("unpack" + tag, [lambda f=f, pc=pc, out=out, op=op: bfp.bfp_unpack(f, pc[op], out[op], n, stream)
-                                        for op in OPS], io, 0))
+                                        for op in OPS], io, 0, n * B / 8))
 
     def step(evs=None):
-        for i, (name, fns, _b, _o) in enumerate(groups):
+        for i, (name, fns, *_r) in enumerate(groups):
             if evs is not None:
                 evs[i][0].record(stream)
             for fn in fns:
@@ -478,31 +576,48 @@ def main():
     ms_step = t0.elapsed_time(t1) / args.steps
     elems_per_step = len(FORMATS) * len(OPS) * n
     value = elems_per_step / (ms_step / 1e3)
-    # timed region 2: the same K steps with events around each kernel group
-    # -> per-kernel durations (the event packets add a little time between
-    # groups, so this pass is not used for the step time)
-    evs = [[(torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True))
-            for _ in groups] for _ in range(args.steps)]
-    for k in range(args.steps):
-        step(evs[k])
-    torch.cuda.synchronize()
-    ms_step_instrumented = evs[0][0][0].elapsed_time(evs[-1][-1][1]) / args.steps
+    # pass 2 (cache-assisted): the same K steps with events around each
+    # kernel group -> per-kernel durations in the pipeline, where a kernel may
+    # read what the previous one left in the last-level cache (the event
+    # packets add a little time between groups, so this pass is not used for
+    # the step time)
+    def instrumented(flush):
+        evs = [[(torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True))
+                for _ in groups] for _ in range(args.steps)]
+        for k in range(args.steps):
+            for i, (name, fns, *_r) in enumerate(groups):
+                if flush:
+                    bfp.bfp_flush_llc(1 << 30, stream)
+                evs[k][i][0].record(stream)
+                for fn in fns:
+                    fn()
+                evs[k][i][1].record(stream)
+        torch.cuda.synchronize()
+        return evs
+
+    evs_warm = instrumented(False)
+    ms_step_instrumented = evs_warm[0][0][0].elapsed_time(evs_warm[-1][-1][1]) / args.steps
+    # pass 3 (cold): a 1 GiB read sweep before each group, outside its events
+    evs_cold = instrumented(True)
 
     kernels = {}
-    for i, (name, fns, nbytes, nops) in enumerate(groups):
-        k = kernels.setdefault(name, {"launches": 0, "us_total": 0.0, "bytes": nbytes, "ops": nops})
+    for i, (name, fns, nbytes, nops, rbytes) in enumerate(groups):
+        k = kernels.setdefault(name, {"launches": 0, "us_total": 0.0, "us_total_warm": 0.0, "bytes": nbytes,
+                                      "ops": nops, "read_bytes": rbytes})
         for st in range(args.steps):
-            k["us_total"] += evs[st][i][0].elapsed_time(evs[st][i][1]) * 1e3
+            k["us_total"] += evs_cold[st][i][0].elapsed_time(evs_cold[st][i][1]) * 1e3
+            k["us_total_warm"] += evs_warm[st][i][0].elapsed_time(evs_warm[st][i][1]) * 1e3
             k["launches"] += len(fns)
     for name, k in kernels.items():
-        us = k["us_total"] / k["launches"]
-        k["us"] = us
-        k["GB/s"] = k["bytes"] / (us * 1e-6) / 1e9
-        k["hbm_frac"] = k["bytes"] / (us * 1e-6) / HBM_PEAK
-        if k["ops"]:
-            k["Tops/s"] = k["ops"] / (us * 1e-6) / 1e12
-            k["valu_frac"] = k["ops"] / (us * 1e-6) / VALU_PEAK
-    # the dominant kernel: largest total time per step
+        for sfx, tot in (("", k["us_total"]), ("_cache_assisted", k["us_total_warm"])):
+            us = tot / k["launches"]
+            k["us" + sfx] = us
+            k["GB/s" + sfx] = k["bytes"] / (us * 1e-6) / 1e9
+            k["hbm_frac" + sfx] = k["bytes"] / (us * 1e-6) / HBM_PEAK
+            if k["ops"]:
+                k["Tops/s" + sfx] = k["ops"] / (us * 1e-6) / 1e12
+                k["valu_frac" + sfx] = k["ops"] / (us * 1e-6) / VALU_PEAK
+    # the dominant kernel: largest total (cold) time per step
     dom = max(kernels, key=lambda nm: kernels[nm]["us_total"])
     dk = kernels[dom]
     if dk.get("valu_frac", 0) > dk["hbm_frac"]:
@@ -511,13 +626,27 @@ def main():
     else:
         roof = {"kernel": dom, "bound": "hbm", "achieved": dk["GB/s"], "peak": HBM_PEAK / 1e9, "unit": "GB/s",
                 "frac": dk["hbm_frac"], "traffic": None}
-    # practical ceiling on this machine: the library's plain 16-byte-vector copy
-    # of 512 MiB (read and write), timed with events on the same stream
-    copy_gbps = bfp.bfp_measure_copy(512 << 20, 10, stream)
-    roof["copy_GBps"] = copy_gbps
+    # practical ceilings on this machine: best read, write and copy sweeps over
+    # 1 GiB (several 16-byte accesses in flight per lane), events on the same stream
+    ceil = {mode: bfp.bfp_measure_hbm(1 << 30, mode, 5, stream) for mode in ("read", "write", "copy")}
+    roof["ceiling_GBps"] = {mode: c["GB/s"] for mode, c in ceil.items()}
+    roof["copy_GBps"] = ceil["copy"]["GB/s"]
     if roof["unit"] == "GB/s":
-        roof["frac_of_copy"] = roof["achieved"] / copy_gbps
+        roof["frac_of_copy"] = roof["achieved"] / roof["copy_GBps"]
+        # the kernel's own read/write mix at the measured read and write
+        # ceilings: reading r bytes and writing w bytes takes at least
+        # r / read + w / write seconds
+        rd, wr = dk["read_bytes"], dk["bytes"] - dk["read_bytes"]
+        mix = dk["bytes"] / (rd / (ceil["read"]["GB/s"] * 1e9) + wr / (ceil["write"]["GB/s"] * 1e9)) / 1e9
+        roof["mix_ceiling_GBps"] = mix
+        roof["frac_of_mix_ceiling"] = roof["achieved"] / mix
+    for k in kernels.values():
+        rd, wr = k["read_bytes"], k["bytes"] - k["read_bytes"]
+        k["mix_ceiling_GBps"] = k["bytes"] / (rd / (ceil["read"]["GB/s"] * 1e9) + wr / (ceil["write"]["GB/s"] * 1e9)) / 1e9
+        k["frac_of_mix_ceiling"] = k["GB/s"] / k["mix_ceiling_GBps"]
+    roof["timing"] = "cold: 1 GiB read sweep before each group of launches, outside the events"
     roof["us_per_launch"] = dk["us"]
+    roof["us_per_launch_cache_assisted"] = dk["us_cache_assisted"]
     roof["algorithmic_bytes_per_launch"] = dk["bytes"]
     roof["device_kernel"] = device_kernel(dom)
     roof["traffic"] = committed_traffic(roof["device_kernel"])
@@ -541,9 +670,13 @@ def main():
                    "n": n, "formats": ["(5,10)", "(8,7)"], "words_per_lane": 2},
         "wall_s_timed": wall,
         "roofline": roof,
-        "kernels": {k: {x: v[x] for x in ("us", "launches", "GB/s", "hbm_frac", "Tops/s", "valu_frac") if x in v}
+        "kernels": {k: {x: v[x] for x in ("us", "launches", "GB/s", "hbm_frac", "Tops/s", "valu_frac",
+                                          "us_cache_assisted", "hbm_frac_cache_assisted",
+                                          "valu_frac_cache_assisted", "frac_of_mix_ceiling") if x in v}
                     for k, v in kernels.items()},
     }
+    if not args.no_sweep:
+        res["sweep"] = bench_sweep(torch, bfp, dev, args.sweep_n_log2)
     if not args.no_batched:
         res["batched"] = bench_batched(torch, bfp, dev, args.batched_reps)
     if not args.no_serving:

@@ -238,14 +238,27 @@ bfp_status bfp_launch_save(const char* path);
 bfp_status bfp_autotune(int op, bfp_format f, uint64_t n_probe, int words_per_lane_mask, int reps, void* stream,
                         bfp_launch* best, double* best_us);
 
-/* Measurement helper (not an operation of the paper): the bandwidth of a
- * plain device copy of `bytes` bytes (16-byte vector loads and stores,
- * grid-stride), the practical HBM ceiling on this device.  Allocates and
- * frees two buffers of `bytes` bytes, runs `reps` timed copies on `stream`
- * after two warm-up copies, synchronises `stream`, and returns read + write
- * GB/s in *gbps.  2^20 <= bytes <= 2^36, bytes a multiple of 16,
- * 1 <= reps <= 1000. */
+/* Practical HBM ceiling of this device: `mode` 0 reads, 1 writes, 2 copies
+ * `bytes` (>= 1 GiB recommended, so the 256 MB last-level cache cannot hold
+ * the buffer) with several 16-byte accesses in flight per lane; every
+ * launch shape of a small sweep (grids of 4..32 blocks per CU, 2, 4 or 8
+ * accesses in flight, ordinary or non-temporal accesses) is timed over `reps` launches between events on
+ * `stream`, and the best rate is returned in *gbps (bytes moved per second,
+ * read + written for a copy, 1e9 units); the winning grid and accesses in
+ * flight go to *best_grid and *best_unroll when not NULL.  Allocates its
+ * buffers.  2^20 <= bytes <= 2^36, bytes a multiple of 16, 1 <= reps <= 1000. */
+bfp_status bfp_measure_hbm(uint64_t bytes, int mode, int reps, void* stream, double* gbps, int* best_grid,
+                           int* best_unroll);
+
+/* bfp_measure_hbm in copy mode (read + write GB/s). */
 bfp_status bfp_measure_copy(uint64_t bytes, int reps, void* stream, double* gbps);
+
+/* Enqueue a read sweep over `bytes` (2^20 .. 2^34) of a buffer the library
+ * keeps per device (allocated on first use or growth), so that the data a
+ * following kernel reads comes from HBM rather than the 256 MB last-level
+ * cache: the "cold" measurements use it between timed launches. */
+bfp_status bfp_flush_llc(uint64_t bytes, void* stream);
+
 
 /* Gate count of one circuit instance (one group of 32 elements per word),
  * constants folded: the cost model of Table 1.  Returns -1 if the format
@@ -289,6 +302,11 @@ bfp_status bfp_batch_run_eager(bfp_batch_plan* plan, void* stream);
 /* Baseline: one bfp_binop launch per task, in task order, on `stream`. */
 bfp_status bfp_batch_run_per_vector(bfp_batch_plan* plan, void* stream);
 
+/* The same per-task launches captured once (on the first call) in a HIP
+ * graph and replayed with one hipGraphLaunch: the baseline without the
+ * host's launch overhead. */
+bfp_status bfp_batch_run_per_vector_graph(bfp_batch_plan* plan, void* stream);
+
 /* Chunks, persistent grid size and total plane words per operand
  * (sum over tasks of B * G_pad); any pointer may be NULL. */
 bfp_status bfp_batch_plan_info(const bfp_batch_plan* plan, uint32_t* nchunks, uint32_t* grid,
@@ -304,8 +322,8 @@ void bfp_batch_plan_destroy(bfp_batch_plan* plan);
  * `tasks_dev` is an array of `count` bfp_task in DEVICE memory (8-byte
  * aligned, caller-owned, read on `stream`).  A one-block kernel checks every
  * task as bfp_batch_plan_create does, writes the descriptors and the chunk
- * index into a static device array of the library (about 1.7 MB per device,
- * held until the process ends), and the persistent class kernels then run the
+ * index into a static device array of the library (about 1.4 MB per device,
+ * held until the process ends), and the two persistent kernels then run the
  * chunks in task order.  The status of the check (BFP_OK, or the error of the
  * first invalid task: BFP_E_FORMAT, BFP_E_OP, BFP_E_ARG, BFP_E_NULL,
  * BFP_E_ALIGN) is written to *status_dev (device int32) on `stream`; with any

@@ -117,6 +117,10 @@ _SIGS = {
     "bfp_measure_copy": (ctypes.c_int, [ctypes.c_uint64, ctypes.c_int, ctypes.c_void_p,
                                         ctypes.POINTER(ctypes.c_double)]),
     "bfp_launch_save": (ctypes.c_int, [ctypes.c_char_p]),
+    "bfp_measure_hbm": (ctypes.c_int, [ctypes.c_uint64, ctypes.c_int, ctypes.c_int, ctypes.c_void_p,
+                                       ctypes.POINTER(ctypes.c_double), ctypes.POINTER(ctypes.c_int),
+                                       ctypes.POINTER(ctypes.c_int)]),
+    "bfp_flush_llc": (ctypes.c_int, [ctypes.c_uint64, ctypes.c_void_p]),
     "bfp_gate_count": (ctypes.c_long, [ctypes.c_int, bfp_format]),
     "bfp_autotune": (ctypes.c_int, [ctypes.c_int, bfp_format, ctypes.c_uint64, ctypes.c_int, ctypes.c_int,
                                     ctypes.c_void_p, ctypes.POINTER(bfp_launch), ctypes.POINTER(ctypes.c_double)]),
@@ -125,6 +129,7 @@ _SIGS = {
     "bfp_batch_run": (ctypes.c_int, [ctypes.c_void_p, ctypes.c_void_p]),
     "bfp_batch_run_eager": (ctypes.c_int, [ctypes.c_void_p, ctypes.c_void_p]),
     "bfp_batch_run_per_vector": (ctypes.c_int, [ctypes.c_void_p, ctypes.c_void_p]),
+    "bfp_batch_run_per_vector_graph": (ctypes.c_int, [ctypes.c_void_p, ctypes.c_void_p]),
     "bfp_batch_plan_info": (ctypes.c_int, [ctypes.c_void_p, ctypes.POINTER(ctypes.c_uint32),
                                            ctypes.POINTER(ctypes.c_uint32), ctypes.POINTER(ctypes.c_uint64)]),
     "bfp_batch_plan_destroy": (None, [ctypes.c_void_p]),
@@ -354,6 +359,20 @@ def bfp_measure_copy(nbytes: int, reps: int = 10, stream=None) -> float:
     return g.value
 
 
+def bfp_measure_hbm(nbytes: int, mode: str, reps: int = 10, stream=None) -> dict:
+    """Best read / write / copy rate (GB/s) over the probe's launch shapes."""
+    g = ctypes.c_double()
+    grid, unroll = ctypes.c_int(), ctypes.c_int()
+    m = {"read": 0, "write": 1, "copy": 2}[mode]
+    _check(lib().bfp_measure_hbm(nbytes, m, reps, _stream(stream), ctypes.byref(g), ctypes.byref(grid),
+                                 ctypes.byref(unroll)), "bfp_measure_hbm")
+    return {"GB/s": g.value, "grid": grid.value, "in_flight": unroll.value}
+
+
+def bfp_flush_llc(nbytes: int = 1 << 30, stream=None):
+    _check(lib().bfp_flush_llc(nbytes, _stream(stream)), "bfp_flush_llc")
+
+
 def bfp_launch_load(path: str):
     _check(lib().bfp_launch_load(path.encode()), "bfp_launch_load")
 
@@ -415,6 +434,10 @@ def bfp_batch_run_per_vector(plan: int, stream=None):
     _check(lib().bfp_batch_run_per_vector(plan, _stream(stream)), "bfp_batch_run_per_vector")
 
 
+def bfp_batch_run_per_vector_graph(plan: int, stream=None):
+    _check(lib().bfp_batch_run_per_vector_graph(plan, _stream(stream)), "bfp_batch_run_per_vector_graph")
+
+
 def bfp_batch_plan_info(plan: int):
     nch, grid, words = ctypes.c_uint32(), ctypes.c_uint32(), ctypes.c_uint64()
     _check(lib().bfp_batch_plan_info(plan, ctypes.byref(nch), ctypes.byref(grid), ctypes.byref(words)),
@@ -441,6 +464,9 @@ class BatchPlan:
 
     def run_per_vector(self, stream=None):
         bfp_batch_run_per_vector(self.handle, stream)
+
+    def run_per_vector_graph(self, stream=None):
+        bfp_batch_run_per_vector_graph(self.handle, stream)
 
     def info(self):
         return bfp_batch_plan_info(self.handle)

@@ -9,9 +9,9 @@
 // on short ones, and, within a variant, longest task first.  Descriptors go
 // to device memory once.
 //
-// Device: one persistent kernel per register class (light circuits, wide
-// adders and m = 15 multipliers, m = 23 multipliers, dividers), each
-// compiled for the occupancy its heaviest circuit allows and launched on a
+// Device: two persistent kernels, one for the add/sub and mul circuits and
+// one for the dividers (whose registers would otherwise lower the first
+// kernel's occupancy), each compiled for a fixed occupancy and launched on a
 // grid sized to the GPU's resident capacity for it.  Each block takes the
 // next chunk index of its class from an atomic counter, reads the chunk's
 // task, and switches (block-uniformly) to the compiled circuit of the task's
@@ -49,10 +49,13 @@ template <int E, int M, bool RZ, int OPC>
 __device__ __forceinline__ void batch_chunk(const BatchTask& tk, uint64_t w0, uint32_t nw) {
   constexpr int B = 1 + E + M;
   constexpr int R = 1;
-  const uint64_t end = w0 + nw;
-  const uint64_t wlast = data_words(tk.n) - 1;  // last word holding an element below n
-  for (uint64_t off = w0 + (uint64_t)threadIdx.x * R; off < end; off += (uint64_t)blockDim.x * R) {
-    const uint64_t src = off < wlast ? off : wlast;
+  // word offsets fit in 32 bits: n <= 2^36 elements gives at most 2^31 + 256 words per plane
+  const uint32_t end = (uint32_t)w0 + nw;
+  const uint32_t wlast = (uint32_t)(data_words(tk.n) - 1);  // last word holding an element below n
+  const uint32_t wfull = (uint32_t)(tk.n >> 5);              // words wholly below n
+  const uint32_t tail = (1u << (uint32_t)(tk.n & 31u)) - 1u;  // elements below n in word wfull
+  for (uint32_t off = (uint32_t)w0 + threadIdx.x; off < end; off += blockDim.x) {
+    const uint32_t src = off < wlast ? off : wlast;
     WordR<R> x[B], y[B], z[B];
 #pragma unroll
     for (int k = 0; k < B; ++k) {
@@ -60,7 +63,7 @@ __device__ __forceinline__ void batch_chunk(const BatchTask& tk, uint64_t w0, ui
       y[k] = ld_words<R>(tk.b + (uint64_t)k * tk.sb + src);
     }
     circuit<E, M, RZ, OPC, R>(x, y, tk.negb, z);
-    const uint32_t mk = word_mask(off, tk.n);
+    const uint32_t mk = off < wfull ? 0xFFFFFFFFu : (off == wfull ? tail : 0u);
 #pragma unroll
     for (int k = 0; k < B; ++k) z[k].w[0] &= mk;
 #pragma unroll
@@ -73,9 +76,14 @@ __global__ void k_batch_reset(uint32_t* counter) {
 }
 
 // Waves per SIMD each class kernel is compiled for.
+// Waves per SIMD each class kernel is compiled for.  Without the target
+// the compiler schedules the merged switch of 160 circuits for one wave per
+// SIMD (256 VGPRs); at three, the add/sub/mul kernel keeps 168 VGPRs and
+// spills a few registers of its heaviest circuits to scratch, which measured
+// no slower than the unspilled alternatives.
 template <int CLS>
 struct ClassWaves {
-  static constexpr int value = CLS == 0 ? 4 : (CLS == 1 ? 3 : 2);
+  static constexpr int value = CLS == 0 ? 3 : 2;
 };
 
 // Persistent kernel of register class CLS over chunks [first, first +
@@ -184,7 +192,7 @@ void batch_chunks(const std::vector<BatchTask>& dt, std::vector<BatchChunk>* out
       chunks.push_back(ch);
     }
   }
-  // by register class, then variants by decreasing time per word (ties by
+  // by kernel class, then variants by decreasing time per word (ties by
   // variant); within a variant, longer tasks first, then by position
   const std::vector<uint32_t>& cost = variant_cost();
   std::vector<int> cls(dt.size());
@@ -214,8 +222,6 @@ int batch_resident_blocks(int c) {
   switch (c) {
     case 0: return resident_blocks_of<0>(prop.multiProcessorCount);
     case 1: return resident_blocks_of<1>(prop.multiProcessorCount);
-    case 2: return resident_blocks_of<2>(prop.multiProcessorCount);
-    case 3: return resident_blocks_of<3>(prop.multiProcessorCount);
     default: return 0;
   }
 }
@@ -245,8 +251,6 @@ hipError_t batch_launch(const BatchTask* d_tasks, const BatchChunk* d_chunks, co
   hipLaunchKernelGGL(k_batch_reset, dim3(1), dim3(64), 0, s, d_counter);
   launch_class<0>(d_tasks, d_chunks, sp, d_counter, s);
   launch_class<1>(d_tasks, d_chunks, sp, d_counter, s);
-  launch_class<2>(d_tasks, d_chunks, sp, d_counter, s);
-  launch_class<3>(d_tasks, d_chunks, sp, d_counter, s);
   return hipGetLastError();
 }
 
@@ -265,6 +269,8 @@ struct bfp_batch_plan {
   hipStream_t capture_stream = nullptr;
   hipGraph_t graph = nullptr;
   hipGraphExec_t exec = nullptr;
+  hipGraph_t pv_graph = nullptr;      // the per-vector launches, captured on first use
+  hipGraphExec_t pv_exec = nullptr;
   uint64_t words_total = 0;  // sum over tasks of B * gpad (per operand)
   std::mutex mu;
 };
@@ -275,6 +281,8 @@ void plan_free(bfp_batch_plan* p) {
   if (!p) return;
   if (p->exec) (void)hipGraphExecDestroy(p->exec);
   if (p->graph) (void)hipGraphDestroy(p->graph);
+  if (p->pv_exec) (void)hipGraphExecDestroy(p->pv_exec);
+  if (p->pv_graph) (void)hipGraphDestroy(p->pv_graph);
   if (p->capture_stream) (void)hipStreamDestroy(p->capture_stream);
   if (p->d_tasks) (void)hipFree(p->d_tasks);
   if (p->d_chunks) (void)hipFree(p->d_chunks);
@@ -381,6 +389,26 @@ bfp_status bfp_batch_run_per_vector(bfp_batch_plan* plan, void* stream) {
   return BFP_OK;
 }
 
+bfp_status bfp_batch_run_per_vector_graph(bfp_batch_plan* plan, void* stream) {
+  if (!plan) return BFP_E_NULL;
+  std::lock_guard<std::mutex> lk(plan->mu);
+  if (!plan->pv_exec) {
+    // capture the per-vector launches once, on the plan's own stream
+    hipError_t e = hipStreamBeginCapture(plan->capture_stream, hipStreamCaptureModeThreadLocal);
+    if (e != hipSuccess) return BFP_E_HIP;
+    bfp_status st = BFP_OK;
+    for (const bfp_task& t : plan->tasks) {
+      st = bfp_binop(t.op, t.f, t.a, t.b, t.c, t.n, plan->capture_stream);
+      if (st != BFP_OK) break;
+    }
+    e = hipStreamEndCapture(plan->capture_stream, &plan->pv_graph);
+    if (st != BFP_OK) return st;
+    if (e == hipSuccess) e = hipGraphInstantiate(&plan->pv_exec, plan->pv_graph, nullptr, nullptr, 0);
+    if (e != hipSuccess) return BFP_E_HIP;
+  }
+  return hipGraphLaunch(plan->pv_exec, (hipStream_t)stream) == hipSuccess ? BFP_OK : BFP_E_HIP;
+}
+
 bfp_status bfp_batch_plan_info(const bfp_batch_plan* plan, uint32_t* nchunks, uint32_t* grid,
                                uint64_t* words_per_operand) {
   if (!plan) return BFP_E_NULL;
@@ -416,7 +444,7 @@ static_assert(kNoallocPrefixOff % 256 == 0, "prefix arrays 256-byte aligned");
 constexpr uint64_t kNoallocMaxChunks = 0xFFF00000ull;
 
 // Index header, task table and the class kernels' chunk prefix arrays: about
-// 1.7 MB per device, held until the process ends.  In host code this name
+// 1.4 MB per device, held until the process ends.  In host code this name
 // is a stand-in, not a device address: host code uses the address from
 // hipGetSymbolAddress (noalloc_device).
 static __device__ __align__(256) unsigned char scratch[kNoallocBytes];
@@ -554,7 +582,5 @@ extern "C" bfp_status bfp_batch_run_noalloc(const bfp_task* tasks_dev, uint32_t 
   hipLaunchKernelGGL(k_noalloc_setup, dim3(1), dim3(1024), 0, s, tasks_dev, count, d.ptr, status_dev);
   launch_indexed<0>(d, s);
   launch_indexed<1>(d, s);
-  launch_indexed<2>(d, s);
-  launch_indexed<3>(d, s);
   return hipGetLastError() == hipSuccess ? BFP_OK : BFP_E_HIP;
 }

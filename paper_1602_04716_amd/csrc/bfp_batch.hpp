@@ -42,20 +42,16 @@ struct BatchChunk {
 constexpr uint32_t kChunkWords = 2048;
 constexpr int kBatchBlock = 256;
 
-// Register classes of the circuit variants.  Each class runs in a
-// persistent kernel of its own, compiled for the occupancy its heaviest
-// circuit allows, so a light circuit never runs at the occupancy of the
-// heaviest one:
-//   0  add/sub up to m = 15 and mul up to m = 10   4 waves per SIMD (128 VGPRs)
-//   1  add/sub at m = 23 and mul at m = 15         3 waves (168 VGPRs)
-//   2  mul at m = 23                               2 waves
-//   3  division                                    2 waves
-// (register counts measured with hipcc for gfx950; at one more wave each
-// class spills to scratch).
-constexpr int kBatchClasses = 4;
-__host__ __device__ constexpr int variant_class(int m, int opc) {
-  return opc == 2 ? 3 : (opc == 1 ? (m <= 10 ? 0 : (m <= 15 ? 1 : 2)) : (m <= 15 ? 0 : 1));
-}
+// Kernel classes of the circuit variants: 0 add/sub and mul, 1 division.
+// Each class runs in a persistent kernel of its own, so the divider's
+// registers do not set the occupancy of the kernel that runs everything
+// else.  (Splitting further, by the registers of the add/sub/mul circuits,
+// measured slower: a kernel that mixes VALU-bound wide multipliers with
+// HBM-bound light circuits overlaps the two, 0.70 ms for the 4096-vector
+// batch against 0.78-0.80 ms for three register classes run one after
+// another.)
+constexpr int kBatchClasses = 2;
+__host__ __device__ constexpr int variant_class(int m, int opc) { return opc == 2 ? 1 : 0; }
 
 // Chunks of a batch whose descriptors were built on the device (by the
 // allocation-free entry point): the class kernels' chunk totals and counters.

@@ -14,6 +14,7 @@
 #include <hip/hip_runtime.h>
 
 #include <algorithm>
+#include <mutex>
 #include <vector>
 
 #include "bfp.h"
@@ -43,11 +44,54 @@ __global__ void k_sweep_read(const u32x4* p, uint64_t n4, uint32_t* sink) {
   if (acc == 0x9E3779B9u) sink[threadIdx.x & 63] = acc;  // keeps the loads live; practically never taken
 }
 
-// Plain copy, 16 bytes per lane per iteration, grid-stride: the practical
-// HBM ceiling the kernels' fractions are read against.
-__global__ void k_copy16(const u32x4* src, u32x4* dst, uint64_t n4) {
-  for (uint64_t i = blockIdx.x * (uint64_t)blockDim.x + threadIdx.x; i < n4; i += (uint64_t)gridDim.x * blockDim.x)
-    dst[i] = src[i];
+// Ceiling probes: plain read, write and copy sweeps with U independent
+// 16-byte accesses in flight per lane (each wave instruction covers 1 KiB
+// contiguous; the U accesses of a lane are a grid stride apart), with
+// ordinary or non-temporal accesses.  The best launch shape over a small
+// sweep is the practical HBM ceiling the kernels' fractions are read against.
+template <int MODE, int U, bool NT>  // MODE 0 read, 1 write, 2 copy; NT: non-temporal accesses
+__global__ void __launch_bounds__(256) k_bw(const u32x4* __restrict__ src, u32x4* __restrict__ dst, uint64_t n4,
+                                            uint32_t* sink) {
+  const uint64_t stride = (uint64_t)gridDim.x * blockDim.x;
+  uint64_t i = blockIdx.x * (uint64_t)blockDim.x + threadIdx.x;
+  uint32_t acc = 0;
+  for (; i + (U - 1) * stride < n4; i += U * stride) {
+    u32x4 v[U];
+    if constexpr (MODE != 1) {
+#pragma unroll
+      for (int u = 0; u < U; ++u) v[u] = NT ? __builtin_nontemporal_load(src + i + u * stride) : src[i + u * stride];
+    } else {
+#pragma unroll
+      for (int u = 0; u < U; ++u) v[u] = u32x4{(uint32_t)i, (uint32_t)u, 0u, 0u};
+    }
+    if constexpr (MODE == 0) {
+#pragma unroll
+      for (int u = 0; u < U; ++u) acc ^= v[u].x ^ v[u].y ^ v[u].z ^ v[u].w;
+    } else {
+#pragma unroll
+      for (int u = 0; u < U; ++u) {
+        if constexpr (NT) __builtin_nontemporal_store(v[u], dst + i + u * stride);
+        else dst[i + u * stride] = v[u];
+      }
+    }
+  }
+  for (; i < n4; i += stride) {  // the last partial round
+    if constexpr (MODE == 0) {
+      const u32x4 v = src[i];
+      acc ^= v.x ^ v.y ^ v.z ^ v.w;
+    } else if constexpr (MODE == 1) {
+      dst[i] = u32x4{(uint32_t)i, 0u, 0u, 0u};
+    } else {
+      dst[i] = src[i];
+    }
+  }
+  if (MODE == 0 && acc == 0x9E3779B9u) sink[threadIdx.x & 63] = acc;  // keeps the loads live
+}
+
+using BwLauncher = void (*)(unsigned grid, hipStream_t s, const u32x4* src, u32x4* dst, uint64_t n4, uint32_t* sink);
+template <int MODE, int U, bool NT>
+void launch_bw(unsigned grid, hipStream_t s, const u32x4* src, u32x4* dst, uint64_t n4, uint32_t* sink) {
+  hipLaunchKernelGGL((k_bw<MODE, U, NT>), dim3(grid), dim3(256), 0, s, src, dst, n4, sink);
 }
 
 struct DevBuf {
@@ -62,18 +106,28 @@ struct DevBuf {
 
 using namespace bfp;
 
-extern "C" bfp_status bfp_measure_copy(uint64_t bytes, int reps, void* stream, double* gbps) {
+extern "C" bfp_status bfp_measure_hbm(uint64_t bytes, int mode, int reps, void* stream, double* gbps,
+                                     int* best_grid, int* best_unroll) {
   if (!gbps) return BFP_E_NULL;
   if (bytes < (1u << 20) || bytes > (1ull << 36) || (bytes & 15u) || reps < 1 || reps > 1000) return BFP_E_ARG;
+  if (mode < 0 || mode > 2) return BFP_E_ARG;
   hipStream_t s = (hipStream_t)stream;
-  DevBuf src, dst;
-  if (hipMalloc(&src.p, bytes) != hipSuccess || hipMalloc(&dst.p, bytes) != hipSuccess) return BFP_E_NOMEM;
+  DevBuf src, dst, sink;
+  if (hipMalloc(&src.p, bytes) != hipSuccess || hipMalloc(&dst.p, bytes) != hipSuccess ||
+      hipMalloc(&sink.p, 256) != hipSuccess)
+    return BFP_E_NOMEM;
   const uint64_t n4 = bytes / 16;
   hipLaunchKernelGGL(k_fill_random, dim3(2048), dim3(256), 0, s, (uint32_t*)src.p, bytes / 4, 0x4242u);
-  const unsigned grid = (unsigned)std::min<uint64_t>((n4 + 255) / 256, 256ull * 64);
-  for (int w = 0; w < 2; ++w)
-    hipLaunchKernelGGL(k_copy16, dim3(grid), dim3(256), 0, s, (const u32x4*)src.p, (u32x4*)dst.p, n4);
   if (hipGetLastError() != hipSuccess) return BFP_E_HIP;
+  static const BwLauncher table[3][6] = {
+      {launch_bw<0, 2, false>, launch_bw<0, 4, false>, launch_bw<0, 8, false>, launch_bw<0, 2, true>,
+       launch_bw<0, 4, true>, launch_bw<0, 8, true>},
+      {launch_bw<1, 2, false>, launch_bw<1, 4, false>, launch_bw<1, 8, false>, launch_bw<1, 2, true>,
+       launch_bw<1, 4, true>, launch_bw<1, 8, true>},
+      {launch_bw<2, 2, false>, launch_bw<2, 4, false>, launch_bw<2, 8, false>, launch_bw<2, 2, true>,
+       launch_bw<2, 4, true>, launch_bw<2, 8, true>}};
+  const int unrolls[6] = {2, 4, 8, 2, 4, 8};
+  const unsigned grids[4] = {1024, 2048, 4096, 8192};  // 4 to 32 blocks of 256 threads per CU
   hipEvent_t e0, e1;
   if (hipEventCreate(&e0) != hipSuccess) return BFP_E_HIP;
   if (hipEventCreate(&e1) != hipSuccess) {
@@ -81,18 +135,62 @@ extern "C" bfp_status bfp_measure_copy(uint64_t bytes, int reps, void* stream, d
     return BFP_E_HIP;
   }
   bfp_status st = BFP_OK;
-  float ms = 0.f;
-  if (hipEventRecord(e0, s) != hipSuccess) st = BFP_E_HIP;
-  for (int r = 0; r < reps && st == BFP_OK; ++r)
-    hipLaunchKernelGGL(k_copy16, dim3(grid), dim3(256), 0, s, (const u32x4*)src.p, (u32x4*)dst.p, n4);
-  if (st == BFP_OK && hipGetLastError() != hipSuccess) st = BFP_E_HIP;
-  if (st == BFP_OK && hipEventRecord(e1, s) != hipSuccess) st = BFP_E_HIP;
-  if (st == BFP_OK && hipEventSynchronize(e1) != hipSuccess) st = BFP_E_HIP;
-  if (st == BFP_OK && hipEventElapsedTime(&ms, e0, e1) != hipSuccess) st = BFP_E_HIP;
+  double best = 0.0;
+  for (int ui = 0; ui < 6 && st == BFP_OK; ++ui) {
+    for (unsigned grid : grids) {
+      const BwLauncher L = table[mode][ui];
+      L(grid, s, (const u32x4*)src.p, (u32x4*)dst.p, n4, (uint32_t*)sink.p);  // warm-up
+      float ms = 0.f;
+      if (hipEventRecord(e0, s) != hipSuccess) st = BFP_E_HIP;
+      for (int r = 0; r < reps && st == BFP_OK; ++r) L(grid, s, (const u32x4*)src.p, (u32x4*)dst.p, n4, (uint32_t*)sink.p);
+      if (st == BFP_OK && hipGetLastError() != hipSuccess) st = BFP_E_HIP;
+      if (st == BFP_OK && hipEventRecord(e1, s) != hipSuccess) st = BFP_E_HIP;
+      if (st == BFP_OK && hipEventSynchronize(e1) != hipSuccess) st = BFP_E_HIP;
+      if (st == BFP_OK && hipEventElapsedTime(&ms, e0, e1) != hipSuccess) st = BFP_E_HIP;
+      if (st != BFP_OK) break;
+      const double moved = (mode == 2 ? 2.0 : 1.0) * (double)bytes;
+      const double g = moved / ((double)ms / reps * 1e-3) / 1e9;
+      if (g > best) {
+        best = g;
+        if (best_grid) *best_grid = (int)grid;
+        if (best_unroll) *best_unroll = unrolls[ui];
+      }
+    }
+  }
   (void)hipEventDestroy(e0);
   (void)hipEventDestroy(e1);
-  if (st == BFP_OK) *gbps = 2.0 * (double)bytes / ((double)ms / reps * 1e-3) / 1e9;
+  if (st == BFP_OK) *gbps = best;
   return st;
+}
+
+extern "C" bfp_status bfp_measure_copy(uint64_t bytes, int reps, void* stream, double* gbps) {
+  return bfp_measure_hbm(bytes, 2, reps, stream, gbps, nullptr, nullptr);
+}
+
+// Read sweep over `bytes` of a library buffer, so that what a following
+// kernel reads comes from HBM rather than the 256 MB last-level cache.
+extern "C" bfp_status bfp_flush_llc(uint64_t bytes, void* stream) {
+  static std::mutex mu;
+  static void* buf[64] = {};
+  static uint64_t cap[64] = {};
+  if (bytes < (1u << 20) || bytes > (1ull << 34)) return BFP_E_ARG;
+  int dev = 0;
+  if (hipGetDevice(&dev) != hipSuccess || dev < 0 || dev >= 64) return BFP_E_NODEV;
+  std::lock_guard<std::mutex> lk(mu);
+  bytes = (bytes + 15) / 16 * 16;
+  if (cap[dev] < bytes + 256) {
+    if (buf[dev]) (void)hipFree(buf[dev]);
+    buf[dev] = nullptr;
+    cap[dev] = 0;
+    if (hipMalloc(&buf[dev], bytes + 256) != hipSuccess) return BFP_E_NOMEM;
+    cap[dev] = bytes + 256;
+    hipLaunchKernelGGL(k_fill_random, dim3(2048), dim3(256), 0, (hipStream_t)stream, (uint32_t*)buf[dev],
+                       bytes / 4, 0x7777u);
+  }
+  uint8_t* b = static_cast<uint8_t*>(buf[dev]);
+  hipLaunchKernelGGL(k_sweep_read, dim3(4096), dim3(256), 0, (hipStream_t)stream, (const u32x4*)b, bytes / 16,
+                     (uint32_t*)(b + bytes));
+  return hipGetLastError() == hipSuccess ? BFP_OK : BFP_E_HIP;
 }
 
 extern "C" bfp_status bfp_autotune(int op, bfp_format f, uint64_t n_probe, int words_per_lane_mask, int reps,

@@ -78,6 +78,13 @@ def test_batch_mixed_all_variants():
     out = _outputs(bt)
     for i in range(len(bt.tasks)):
         assert torch.equal(out[i], ref[i]), ("eager", i)
+    # the per-vector launches replayed from their captured graph
+    for rep in range(2):
+        _scrub(bt)
+        plan.run_per_vector_graph()
+        out = _outputs(bt)
+        for i in range(len(bt.tasks)):
+            assert torch.equal(out[i], ref[i]), ("per-vector graph", rep, i)
     plan.close()
 
 

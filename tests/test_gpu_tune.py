@@ -69,3 +69,22 @@ def test_measure_copy_is_plausible():
     """The copy-bandwidth helper reports a rate between 1 TB/s and the 8 TB/s peak."""
     g = bfp.bfp_measure_copy(256 << 20, 5)
     assert 1000.0 < g < 8000.0, g
+
+
+def test_measure_hbm_modes_are_plausible():
+    """Read, write and copy ceilings over 1 GiB: between 1 TB/s and the
+    8 TB/s peak (bytes moved per second, both directions counted)."""
+    for mode in ("read", "write", "copy"):
+        r = bfp.bfp_measure_hbm(1 << 30, mode, 3)
+        assert 1000.0 < r["GB/s"] < 8000.0, (mode, r)
+        assert r["grid"] in (1024, 2048, 4096, 8192) and r["in_flight"] in (2, 4, 8)
+    with pytest.raises(bfp.BfpError):
+        bfp.bfp_measure_hbm(1 << 30, "copy", 0)
+
+
+def test_flush_llc_runs():
+    bfp.bfp_flush_llc(1 << 28)
+    bfp.bfp_flush_llc(1 << 30)
+    torch.cuda.synchronize()
+    with pytest.raises(bfp.BfpError):
+        bfp.bfp_flush_llc(100)
