@@ -26,28 +26,78 @@ import re
 import sqlite3
 
 PKG = os.path.dirname(os.path.abspath(__file__))
-KERNEL_SOURCES = ["bfp_word.hpp", "bfp_circuits.hpp", "bfp_transpose.hpp", "bfp_kernels.hpp",
-                  "bfp_ops.hpp", "bfp_runtime.hip", "bfp_batch.hip"]
+FLUSH_KERNEL = "k_sweep_read"  # the cache flush that precedes each cold group in bench.py
 CALIB_BYTES = 256 * 1024 * 1024  # read and written by the calibration kernel
 CALIB_PATTERN = "direct_copy_kernel"
 
 
 def source_hash() -> str:
+    """Hash of every library source (csrc/ and include/) and of the build
+    flags: a committed counter figure is current only for the code it was
+    taken with."""
+    from . import build
     h = hashlib.sha256()
-    for f in KERNEL_SOURCES:
+    srcs = sorted(os.listdir(os.path.join(PKG, "csrc")))
+    for f in srcs:
         with open(os.path.join(PKG, "csrc", f), "rb") as fp:
-            h.update(fp.read())
+            h.update(f.encode() + b"\0" + fp.read())
+    for f in sorted(os.listdir(build.INCLUDE)):
+        with open(os.path.join(build.INCLUDE, f), "rb") as fp:
+            h.update(f.encode() + b"\0" + fp.read())
+    h.update(" ".join(build.HIP_FLAGS + build.CXX_FLAGS).replace(build.ROOT, "").encode())
     return h.hexdigest()[:16]
 
 
 def short_name(n: str) -> str:
-    return re.sub(r"\(.*", "", n.replace("void ", "")).strip()
+    n = n.replace("void ", "").replace("(anonymous namespace)::", "")
+    return re.sub(r"\(.*", "", n).strip()
 
 
 def trace_stats(db: str):
     c = sqlite3.connect(db).cursor()
     return [(short_name(r[0]), r[1], r[3], r[2], r[4])
             for r in c.execute("select name, total_calls, total_duration, average, percentage from top_kernels")]
+
+
+def dispatches(db: str):
+    """Every kernel dispatch in start order: (short name, duration us, grid size)."""
+    c = sqlite3.connect(db).cursor()
+    return [(short_name(r[0]), (r[2] - r[1]) / 1e3, r[3])
+            for r in c.execute("select name, start, end, grid_x from kernels order by start")]
+
+
+def cold_average(db: str, kernel: str):
+    """Durations (us) of `kernel`'s dispatches that run right after the
+    cache flush: each run of back-to-back dispatches of the kernel after a
+    flush is one cold run (bench.py's cold groups, and its back-to-back
+    measurement of the dominant kernel, the longest run).  Only dispatches at
+    the grid size most cold ones have (the bench's main workload) count."""
+    import collections as _c
+    runs, other = [], []
+    prev = None  # last dispatch that was not `kernel`
+    cur = None
+    for name, us, grid in dispatches(db):
+        if name.endswith(kernel) or name == kernel:
+            if prev is not None and FLUSH_KERNEL in prev:
+                if cur is None:
+                    cur = []
+                    runs.append(cur)
+                cur.append((us, grid))
+            else:
+                other.append(us)
+        else:
+            prev = name
+            cur = None
+    cold = [x for r in runs for x in r]
+    grid = _c.Counter(g for _u, g in cold).most_common(1)[0][0] if cold else None
+    runs = [[u for u, g in r if g == grid] for r in runs]
+    runs = [r for r in runs if r]
+    avg = lambda v: sum(v) / len(v) if v else float("nan")
+    longest = max(runs, key=len) if runs else []
+    return {"cold_grid": grid, "cold_dispatches": sum(len(r) for r in runs),
+            "cold_avg_us": avg([u for r in runs for u in r]),
+            "longest_run": len(longest), "longest_run_avg_us": avg(longest),
+            "other_dispatches": len(other), "other_avg_us": avg(other)}
 
 
 def counter_per_dispatch(db: str):
@@ -81,6 +131,14 @@ def summarize(trace_db, fetch_db, write_db, kernel, out, commands):
               "| kernel | calls | avg us | total us | % |", "|---|---|---|---|---|"]
     for (n, calls, avg, tot, pct) in stats:
         lines.append("| `%s` | %d | %.2f | %.1f | %.1f |" % (n, calls, avg, tot, pct))
+    ca = cold_average(trace_db, kernel)
+    lines += ["", "## `%s`: dispatches after the bench's cache flush, and the others" % kernel, "",
+              "| dispatches | count | avg us |", "|---|---|---|",
+              "| longest back-to-back run after a flush (the bench's roofline measurement) | %d | %.2f |"
+              % (ca["longest_run"], ca["longest_run_avg_us"]),
+              "| every run after a flush (cold groups and the run above) | %d | %.2f |"
+              % (ca["cold_dispatches"], ca["cold_avg_us"]),
+              "| in the pipeline and elsewhere | %d | %.2f |" % (ca["other_dispatches"], ca["other_avg_us"])]
     lines += ["", "## HBM bytes per dispatch (FETCH_SIZE, WRITE_SIZE)", "",
               "Calibration: the int32->float32 copy of 2^26 elements reads and writes 262144 KiB; its "
               "FETCH_SIZE reads %.1f KiB and WRITE_SIZE %.1f KiB, so the factors are %.4f (fetch) and "
@@ -100,9 +158,10 @@ def summarize(trace_db, fetch_db, write_db, kernel, out, commands):
     if chosen:
         with open(out + ".traffic.txt", "w") as fp:
             fp.write("kernel %s\nsource_hash %s\nfetch_bytes_per_launch %.0f\nwrite_bytes_per_launch %.0f\n"
-                     "traffic_bytes_per_launch %.0f\n" % (chosen[0], source_hash(), chosen[1], chosen[2],
-                                                         chosen[1] + chosen[2]))
-    return chosen
+                     "traffic_bytes_per_launch %.0f\nback_to_back_avg_us %.3f\n" % (
+                         chosen[0], source_hash(), chosen[1], chosen[2], chosen[1] + chosen[2],
+                         ca["longest_run_avg_us"]))
+    return chosen, ca
 
 
 def read_traffic(path: str):
@@ -181,10 +240,55 @@ def valu_summary(trace_db, pmc_db, n, out, commands):
         fp.write("\n".join(lines) + "\n")
 
 
+def sq_summary(trace_db, pmc_db, kernels, out, commands):
+    """Per-dispatch averages of the SQ counters of one --pmc pass for the
+    chosen kernels, with derived figures: VMEM instructions issued, the
+    fraction of wave lifetime spent waiting on issued instructions
+    (SQ_WAIT_INST_ANY / SQ_WAVE_CYCLES) and the mean number of resident waves
+    (SQ_WAVE_CYCLES / SQ_BUSY_CYCLES)."""
+    stats = {k: avg for (k, calls, avg, tot, pct) in trace_stats(trace_db)}
+    c = sqlite3.connect(pmc_db).cursor()
+    vals = collections.defaultdict(lambda: collections.defaultdict(list))
+    for name, cname, val in c.execute("select kernel_name, counter_name, value from counters_collection"):
+        vals[short_name(name)][cname].append(val)
+    lines = ["# rocprofv3 SQ counters: %s" % os.path.basename(out), "",
+             "Kernel sources hash: `%s`" % source_hash(), "",
+             "Commands (run from the repository root on one MI355X):", ""]
+    for k, v in commands.items():
+        lines.append("- %s: `%s`" % (k, v))
+    names = sorted({cn for k in kernels for cn in vals.get(k, {})})
+    lines += ["", "Per-dispatch averages (counters summed over the device):", "",
+              "| kernel | dispatches | " + " | ".join(names) + " | wait / wave cycles | waves resident | trace avg us |",
+              "|---|---|" + "---|" * len(names) + "---|---|---|"]
+    for k in kernels:
+        if k not in vals:
+            continue
+        d = vals[k]
+        avg = {cn: sum(v) / len(v) for cn, v in d.items()}
+        nd = max(len(v) for v in d.values())
+        wait = avg.get("SQ_WAIT_INST_ANY", 0) / avg["SQ_WAVE_CYCLES"] if avg.get("SQ_WAVE_CYCLES") else float("nan")
+        res = avg["SQ_WAVE_CYCLES"] / avg["SQ_BUSY_CYCLES"] if avg.get("SQ_BUSY_CYCLES") else float("nan")
+        lines.append("| `%s` | %d | " % (k, nd) + " | ".join("%.4g" % avg.get(cn, float("nan")) for cn in names)
+                     + " | %.2f | %.1f | %.2f |" % (wait, res, stats.get(k, float("nan"))))
+    with open(out + ".md", "w") as fp:
+        fp.write("\n".join(lines) + "\n")
+
+
 def main(argv=None):
     import sys
     if argv is None:
         argv = sys.argv[1:]
+    if argv and argv[0] == "sq":
+        ap = argparse.ArgumentParser()
+        ap.add_argument("--trace", required=True)
+        ap.add_argument("--pmc", required=True)
+        ap.add_argument("--kernel", action="append", required=True)
+        ap.add_argument("--out", required=True)
+        ap.add_argument("--command-trace", default="")
+        ap.add_argument("--command-pmc", default="")
+        a = ap.parse_args(argv[1:])
+        sq_summary(a.trace, a.pmc, a.kernel, a.out, {"trace": a.command_trace, "SQ counters": a.command_pmc})
+        return
     if argv and argv[0] == "valu":
         ap = argparse.ArgumentParser()
         ap.add_argument("--trace", required=True)
