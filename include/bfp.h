@@ -406,6 +406,14 @@ bfp_status bfp_server_cancel(bfp_server* s, uint64_t req_id);
  * request on the device always runs to completion. */
 bfp_status bfp_server_set_queue_timeout(bfp_server* s, int64_t timeout_ns);
 
+/* Largest tick: the worker launches the admitted requests in FIFO order up
+ * to `max_bytes` of operand and result planes per tick (a, b and c of each
+ * request; at least one request per tick), so that a backlog runs as a
+ * sequence of bounded launches that complete their requests progressively
+ * and alternate between the two streams.  The default is 4 GiB; 0 puts
+ * every admitted request in the next tick. */
+bfp_status bfp_server_set_tick_limit(bfp_server* s, uint64_t max_bytes);
+
 /* Move up to `max` completions (oldest first) to `out`; *count is set. */
 bfp_status bfp_server_poll(bfp_server* s, bfp_completion* out, uint32_t max, uint32_t* count);
 

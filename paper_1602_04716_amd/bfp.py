@@ -141,6 +141,7 @@ _SIGS = {
                                          ctypes.c_uint64, ctypes.c_uint64, ctypes.POINTER(ctypes.c_uint64)]),
     "bfp_server_cancel": (ctypes.c_int, [ctypes.c_void_p, ctypes.c_uint64]),
     "bfp_server_set_queue_timeout": (ctypes.c_int, [ctypes.c_void_p, ctypes.c_int64]),
+    "bfp_server_set_tick_limit": (ctypes.c_int, [ctypes.c_void_p, ctypes.c_uint64]),
     "bfp_server_poll": (ctypes.c_int, [ctypes.c_void_p, ctypes.POINTER(bfp_completion), ctypes.c_uint32,
                                        ctypes.POINTER(ctypes.c_uint32)]),
     "bfp_server_wait_idle": (ctypes.c_int, [ctypes.c_void_p, ctypes.c_int64]),
@@ -503,6 +504,10 @@ def bfp_server_submit(server: int, op, f, a: int, b: int, n: int) -> int:
 
 def bfp_server_cancel(server: int, req_id: int):
     _check(lib().bfp_server_cancel(server, req_id), "bfp_server_cancel")
+
+
+def bfp_server_set_tick_limit(server: int, max_bytes: int):
+    _check(lib().bfp_server_set_tick_limit(server, max_bytes), "bfp_server_set_tick_limit")
 
 
 def bfp_server_set_queue_timeout(server: int, timeout_ns: int):

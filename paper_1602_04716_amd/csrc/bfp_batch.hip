@@ -181,9 +181,28 @@ int task_class(const BatchTask& t) {
 }
 
 void batch_chunks(const std::vector<BatchTask>& dt, std::vector<BatchChunk>* out) {
+  // tasks by kernel class, then variants by decreasing time per word (ties
+  // by variant); within a variant, longer tasks first, then by position; each
+  // task's chunks follow in word order (sorting the tasks, not the chunks,
+  // keeps the host's share of a serving tick small)
+  const std::vector<uint32_t>& cost = variant_cost();
+  std::vector<uint32_t> order(dt.size());
+  std::vector<int> cls(dt.size());
+  for (uint32_t i = 0; i < (uint32_t)dt.size(); ++i) {
+    order[i] = i;
+    cls[i] = task_class(dt[i]);
+  }
+  std::sort(order.begin(), order.end(), [&](uint32_t x, uint32_t y) {
+    const uint32_t vx = dt[x].variant, vy = dt[y].variant;
+    if (cls[x] != cls[y]) return cls[x] < cls[y];
+    if (cost[vx] != cost[vy]) return cost[vx] > cost[vy];
+    if (vx != vy) return vx < vy;
+    if (dt[x].words != dt[y].words) return dt[x].words > dt[y].words;
+    return x < y;
+  });
   std::vector<BatchChunk>& chunks = *out;
   chunks.clear();
-  for (uint32_t i = 0; i < (uint32_t)dt.size(); ++i) {
+  for (uint32_t i : order) {
     for (uint64_t w = 0; w < dt[i].words; w += kChunkWords) {
       BatchChunk ch;
       ch.w0 = w;
@@ -192,20 +211,6 @@ void batch_chunks(const std::vector<BatchTask>& dt, std::vector<BatchChunk>* out
       chunks.push_back(ch);
     }
   }
-  // by kernel class, then variants by decreasing time per word (ties by
-  // variant); within a variant, longer tasks first, then by position
-  const std::vector<uint32_t>& cost = variant_cost();
-  std::vector<int> cls(dt.size());
-  for (size_t i = 0; i < dt.size(); ++i) cls[i] = task_class(dt[i]);
-  std::stable_sort(chunks.begin(), chunks.end(), [&](const BatchChunk& x, const BatchChunk& y) {
-    const uint32_t vx = dt[x.task].variant, vy = dt[y.task].variant;
-    if (cls[x.task] != cls[y.task]) return cls[x.task] < cls[y.task];
-    if (cost[vx] != cost[vy]) return cost[vx] > cost[vy];
-    if (vx != vy) return vx < vy;
-    if (dt[x.task].words != dt[y.task].words) return dt[x.task].words > dt[y.task].words;
-    if (x.task != y.task) return x.task < y.task;
-    return x.w0 < y.w0;
-  });
 }
 
 template <int CLS>

@@ -287,6 +287,7 @@ int64_t simsrv_submit(void* p, uint64_t a, uint64_t b, uint64_t n, uint64_t c_by
 }
 int simsrv_cancel(void* p, uint64_t id) { return static_cast<SimServer*>(p)->sched.cancel(id); }
 void simsrv_set_timeout(void* p, int64_t ns) { static_cast<SimServer*>(p)->sched.set_queue_timeout(ns); }
+void simsrv_set_tick_limit(void* p, uint64_t bytes) { static_cast<SimServer*>(p)->sched.set_tick_limit(bytes); }
 int simsrv_step(void* p) { return static_cast<SimServer*>(p)->sched.step() ? 1 : 0; }
 // The serving worker's split step: collect (returns the batch size), then,
 // after any number of other calls, launch the batch and commit it.

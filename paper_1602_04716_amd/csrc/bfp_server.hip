@@ -303,6 +303,13 @@ bfp_status bfp_server_cancel(bfp_server* s, uint64_t req_id) {
   return s->sched->cancel(req_id);
 }
 
+bfp_status bfp_server_set_tick_limit(bfp_server* s, uint64_t max_bytes) {
+  if (!s) return BFP_E_NULL;
+  std::lock_guard<std::mutex> lk(s->sched->mutex());
+  s->sched->set_tick_limit(max_bytes);
+  return BFP_OK;
+}
+
 bfp_status bfp_server_set_queue_timeout(bfp_server* s, int64_t timeout_ns) {
   if (!s) return BFP_E_NULL;
   std::lock_guard<std::mutex> lk(s->sched->mutex());

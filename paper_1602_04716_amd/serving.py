@@ -55,6 +55,9 @@ class Server:
     def cancel(self, req_id: int):
         bfp.bfp_server_cancel(self.h, req_id)
 
+    def set_tick_limit(self, max_bytes: int):
+        bfp.bfp_server_set_tick_limit(self.h, max_bytes)
+
     def set_queue_timeout(self, timeout_ns: int):
         bfp.bfp_server_set_queue_timeout(self.h, timeout_ns)
 

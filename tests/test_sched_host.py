@@ -25,6 +25,7 @@ def L():
         "simsrv_offset": (I64, [VP, U64]),
         "simsrv_submit": (I64, [VP, U64, U64, U64, U64]), "simsrv_step": (ctypes.c_int, [VP]),
         "simsrv_cancel": (ctypes.c_int, [VP, U64]), "simsrv_set_timeout": (None, [VP, I64]),
+        "simsrv_set_tick_limit": (None, [VP, U64]),
         "simsrv_collect": (ctypes.c_int, [VP]), "simsrv_launch_commit": (None, [VP]),
         "simsrv_release": (None, [VP, ctypes.c_int]), "simsrv_fail_next": (None, [VP]),
         "simsrv_running_ticks": (ctypes.c_int, [VP]),
@@ -486,3 +487,26 @@ def test_layout_prefix_reads_stay_inside_operands(L):
         for w in range(max(0, n // 32 - 2), n // 32 + 3):
             want = sum(1 << j for j in range(32) if 32 * w + j < n)
             assert L.simlayout_word_mask(w, n) == want
+
+
+def test_tick_limit_splits_backlog_in_fifo_order(L):
+    """With a tick limit, a backlog of admitted requests goes out as several
+    ticks in FIFO order, each within the limit (a request larger than the
+    limit goes alone)."""
+    s = L.simsrv_create(1 << 30, 1000)
+    _, submit = submitter(L, s)
+    L.simsrv_set_tick_limit(s, 3 * 3 * 4096)          # three requests of 4096-byte results
+    ids = [submit(10, 4096) for _ in range(7)] + [submit(10, 65536)] + [submit(10, 4096)]
+    sizes = []
+    done = []
+    for _ in range(40):
+        n = L.simsrv_collect(s)
+        if n:
+            sizes.append(n)
+            L.simsrv_launch_commit(s)
+        else:
+            L.simsrv_release(s, 1)
+        done += [d[0] for d in take(L, s)]
+    assert sizes == [3, 3, 1, 1, 1], sizes
+    assert done == ids
+    L.simsrv_destroy(s)
