@@ -8,6 +8,19 @@
 #include "bfp_circuits.hpp"
 #include "bfp_formats.hpp"
 
+// A build may narrow the formats and integer widths it instantiates (the
+// sanitizer builds of the tests do, to keep their compile time short); the
+// calls return -1 for the others.
+#ifndef BFP_SIM_FORMATS
+#define BFP_SIM_FORMATS(X) BFP_FOR_EACH_FORMAT(X)
+#endif
+#ifndef BFP_SIM_WIDE_FORMATS
+#define BFP_SIM_WIDE_FORMATS(X) BFP_FOR_EACH_WIDE_FORMAT(X)
+#endif
+#ifndef BFP_SIM_INT_K
+#define BFP_SIM_INT_K(X) BFP_FOR_EACH_INT_K(X)
+#endif
+
 namespace {
 
 template <class W>
@@ -79,7 +92,7 @@ int bfpsim_binop(int op, int e, int m, int mode, int wbits, const uint32_t* a, c
     }                                                                                    \
     return 0;                                                                            \
   }
-  BFP_FOR_EACH_FORMAT(BFP_SIM_CASE)
+  BFP_SIM_FORMATS(BFP_SIM_CASE)
 #undef BFP_SIM_CASE
   return -1;
 }
@@ -98,7 +111,7 @@ int bfpsim_binop64(int op, int e, int m, int mode, int wbits, const uint64_t* a,
     }                                                                                    \
     return 0;                                                                            \
   }
-  BFP_FOR_EACH_WIDE_FORMAT(BFP_SIM_CASE)
+  BFP_SIM_WIDE_FORMATS(BFP_SIM_CASE)
 #undef BFP_SIM_CASE
   return -1;
 }
@@ -107,8 +120,8 @@ int bfpsim_binop64(int op, int e, int m, int mode, int wbits, const uint64_t* a,
 long bfpsim_gate_count(int op, int e, int m, int mode) {
 #define BFP_GC_CASE(EE, MM) \
   if (e == EE && m == MM) return (long)(mode ? gates<EE, MM, true>(op) : gates<EE, MM, false>(op));
-  BFP_FOR_EACH_FORMAT(BFP_GC_CASE)
-  BFP_FOR_EACH_WIDE_FORMAT(BFP_GC_CASE)
+  BFP_SIM_FORMATS(BFP_GC_CASE)
+  BFP_SIM_WIDE_FORMATS(BFP_GC_CASE)
 #undef BFP_GC_CASE
   return -1;
 }
@@ -174,7 +187,7 @@ int bfpsim_int_binop(int op, int k, int kind, int wbits, const uint32_t* a, cons
     BFP_SIM_INT_OPK(KK, 1, 0) BFP_SIM_INT_OPK(KK, 1, 1) BFP_SIM_INT_OPK(KK, 1, 2)                    \
     BFP_SIM_INT_OPK(KK, 2, 0) BFP_SIM_INT_OPK(KK, 2, 1) BFP_SIM_INT_OPK(KK, 2, 2)                    \
   }
-  BFP_FOR_EACH_INT_K(BFP_SIM_INT_CASE)
+  BFP_SIM_INT_K(BFP_SIM_INT_CASE)
 #undef BFP_SIM_INT_CASE
 #undef BFP_SIM_INT_OPK
   return -1;
@@ -189,7 +202,7 @@ long bfpsim_int_gate_count(int op, int k, int kind) {
     BFP_GC_INT_OPK(KK, 1, 0) BFP_GC_INT_OPK(KK, 1, 1) BFP_GC_INT_OPK(KK, 1, 2)             \
     BFP_GC_INT_OPK(KK, 2, 0) BFP_GC_INT_OPK(KK, 2, 1) BFP_GC_INT_OPK(KK, 2, 2)             \
   }
-  BFP_FOR_EACH_INT_K(BFP_GC_INT_CASE)
+  BFP_SIM_INT_K(BFP_GC_INT_CASE)
 #undef BFP_GC_INT_CASE
 #undef BFP_GC_INT_OPK
   return -1;

@@ -21,10 +21,13 @@
 #pragma once
 #include <stdint.h>
 
+#include <atomic>
 #include <chrono>
+#include <condition_variable>
 #include <deque>
 #include <map>
 #include <mutex>
+#include <thread>
 #include <unordered_set>
 #include <vector>
 
@@ -461,5 +464,40 @@ class Scheduler {
   bool autofree_ = false;
   SchedStats stats_;
 };
+
+// The serving worker: one scheduling pass after another until `stop` --
+// completions, expiry and admission under the scheduler's lock, the launch
+// of a collected tick without it (only this thread touches the executor, so
+// submitters and pollers proceed meanwhile), then the commit under the lock.
+// Sleeps on `cv` (about 2 ms at most) when nothing is queued or running.
+template <class Executor>
+void serve_loop(Scheduler<Executor>& sched, Executor& ex, const std::atomic<bool>& stop,
+                std::condition_variable& cv) {
+  std::unique_lock<std::mutex> lk(sched.mutex());
+  std::vector<SchedRequest> batch;
+  while (!stop.load()) {
+    bool changed = sched.collect(&batch);
+    if (!batch.empty()) {
+      lk.unlock();
+      const int st = ex.launch(batch);
+      lk.lock();
+      sched.commit(&batch, st);
+      changed = true;
+    }
+    if (sched.idle()) {
+      // a system-clock deadline: the wait is a bounded nap (submissions and
+      // stop notify `cv`), and libstdc++ waits on it with
+      // pthread_cond_timedwait, which ThreadSanitizer follows (a steady-clock
+      // wait_for goes through pthread_cond_clockwait, which the sanitizer of
+      // this toolchain does not intercept)
+      cv.wait_until(lk, std::chrono::system_clock::now() + std::chrono::milliseconds(2));
+    } else if (!changed) {
+      // ticks in flight: release the lock briefly so callers can submit/poll
+      lk.unlock();
+      std::this_thread::yield();
+      lk.lock();
+    }
+  }
+}
 
 }  // namespace bfp

@@ -181,28 +181,7 @@ namespace {
 
 void worker_loop(bfp_server* s) {
   (void)hipSetDevice(s->device);
-  std::unique_lock<std::mutex> lk(s->sched->mutex());
-  std::vector<SchedRequest> batch;
-  while (!s->stop.load()) {
-    bool changed = s->sched->collect(&batch);
-    if (!batch.empty()) {
-      // launch without the lock: submitters and pollers proceed meanwhile;
-      // only this thread touches the executor
-      lk.unlock();
-      const int st = s->ex.launch(batch);
-      lk.lock();
-      s->sched->commit(&batch, st);
-      changed = true;
-    }
-    if (s->sched->idle()) {
-      s->cv.wait_for(lk, std::chrono::milliseconds(2));
-    } else if (!changed) {
-      // ticks in flight: release the lock briefly so callers can submit/poll
-      lk.unlock();
-      std::this_thread::yield();
-      lk.lock();
-    }
-  }
+  serve_loop(*s->sched, s->ex, s->stop, s->cv);
 }
 
 uint64_t bitslice_bytes_of(uint8_t e, uint8_t m, uint64_t n) {
