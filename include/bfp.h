@@ -203,13 +203,15 @@ bfp_status bfp_int_binop(int op, int k, int kind, const void* a, const void* b, 
 /* ---- launch configuration (autotuning) ------------------------------------ */
 
 /* One kernel variant: words per lane per plane (1: W = 32 elements,
- * 2: W = 64), threads per block, and blocks per compute unit for the
- * grid-stride grid (0: one thread per work item, no stride loop). */
+ * 2: W = 64, 4: W = 128, the last for formats of at most 10 bits), threads
+ * per block, blocks per compute unit for the grid-stride grid (0: one
+ * thread per work item, no stride loop), and units per loop step (2: a lane
+ * runs two independent circuit instances a grid stride apart). */
 typedef struct {
-  int32_t words_per_lane; /* 1 or 2 */
+  int32_t words_per_lane; /* 1, 2 or 4 */
   int32_t block;          /* 64, 128, 256 or 512 */
   int32_t blocks_per_cu;  /* 0 or 1..64 */
-  int32_t pad;            /* must be 0 */
+  int32_t unroll;         /* 0 or 1 (one unit per step) or 2 */
 } bfp_launch;
 
 /* Current configuration used for (op, f) by bfp_binop (op BFP_SUB shares
@@ -220,14 +222,16 @@ bfp_status bfp_launch_get(int op, bfp_format f, bfp_launch* out);
 bfp_status bfp_launch_set(int op, bfp_format f, const bfp_launch* cfg);
 
 /* Load / save the whole table as text, one line per entry:
- * "op e m round words_per_lane block blocks_per_cu".  Lines starting with
- * '#' are comments.  Unknown formats are skipped on load. */
+ * "op e m round words_per_lane block blocks_per_cu unroll" (a missing unroll
+ * column reads as 1).  Lines starting with '#' are comments.  Unknown
+ * formats are skipped on load. */
 bfp_status bfp_launch_load(const char* path);
 bfp_status bfp_launch_save(const char* path);
 
-/* Autotune bfp_binop for (op, f): time every words_per_lane allowed by
- * `words_per_lane_mask` (bit 0: 1 word, bit 1: 2 words) x block
- * {64,128,256,512} x blocks_per_cu {0,4,8} on a probe vector of n_probe
+/* Autotune bfp_binop for (op, f): time every compiled words_per_lane
+ * allowed by `words_per_lane_mask` (bit 0: 1 word, bit 1: 2 words, bit 2:
+ * 4 words) x unroll {1,2} x block {64,128,256,512} x blocks_per_cu {0,4,8}
+ * on a probe vector of n_probe
  * random elements (median of `reps` runs, each after a 512 MiB read sweep
  * that clears the last-level cache), install the fastest with
  * bfp_launch_set and return it in *best (and its median microseconds in

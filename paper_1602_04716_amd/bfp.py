@@ -36,11 +36,11 @@ class bfp_format(ctypes.Structure):
 
 class bfp_launch(ctypes.Structure):
     _fields_ = [("words_per_lane", ctypes.c_int32), ("block", ctypes.c_int32),
-                ("blocks_per_cu", ctypes.c_int32), ("pad", ctypes.c_int32)]
+                ("blocks_per_cu", ctypes.c_int32), ("unroll", ctypes.c_int32)]
 
     def __repr__(self):
-        return "bfp_launch(words_per_lane=%d, block=%d, blocks_per_cu=%d)" % (
-            self.words_per_lane, self.block, self.blocks_per_cu)
+        return "bfp_launch(words_per_lane=%d, block=%d, blocks_per_cu=%d, unroll=%d)" % (
+            self.words_per_lane, self.block, self.blocks_per_cu, max(1, self.unroll))
 
 
 class bfp_task(ctypes.Structure):
@@ -348,8 +348,8 @@ def bfp_launch_get(op, f) -> bfp_launch:
     return out
 
 
-def bfp_launch_set(op, f, words_per_lane: int, block: int, blocks_per_cu: int):
-    cfg = bfp_launch(words_per_lane, block, blocks_per_cu, 0)
+def bfp_launch_set(op, f, words_per_lane: int, block: int, blocks_per_cu: int, unroll: int = 1):
+    cfg = bfp_launch(words_per_lane, block, blocks_per_cu, unroll)
     _check(lib().bfp_launch_set(_op(op), f, ctypes.byref(cfg)), "bfp_launch_set")
 
 
@@ -382,7 +382,7 @@ def bfp_launch_save(path: str):
     _check(lib().bfp_launch_save(path.encode()), "bfp_launch_save")
 
 
-def bfp_autotune(op, f, n_probe: int = 1 << 24, words_per_lane_mask: int = 3, reps: int = 7, stream=None):
+def bfp_autotune(op, f, n_probe: int = 1 << 24, words_per_lane_mask: int = 7, reps: int = 7, stream=None):
     """Returns (best bfp_launch, median microseconds); installs the best."""
     best = bfp_launch()
     us = ctypes.c_double()

@@ -108,32 +108,61 @@ __device__ __forceinline__ void mask_padding(WordR<R>* z, uint64_t off, uint64_t
 }
 
 // c = a op b on resident bitslice vectors of n elements: every word of every
-// plane (padding words of c are zero).
-template <int E, int M, bool RZ, int OPC, int R>
+// plane (padding words of c are zero).  A lane takes U units of R adjacent
+// words per loop step, the units a grid stride apart: R widens each plane
+// load (4, 8 or 16 bytes per lane), U puts independent loads and circuit
+// instances side by side; both trade registers for bytes in flight.  A unit
+// past the end reads the step's first unit again and is not stored.
+template <int E, int M, bool RZ, int OPC, int R, int U>
 __device__ __forceinline__ void binop_body(const uint32_t* a, const uint32_t* b, uint32_t* c, uint64_t gpad,
                                            uint64_t n, uint32_t negb) {
   constexpr int B = 1 + E + M;
+  constexpr int RU = R * U;
   const uint64_t nt = gpad / R;
   const uint64_t stride = (uint64_t)gridDim.x * blockDim.x;
-  for (uint64_t t = (uint64_t)blockIdx.x * blockDim.x + threadIdx.x; t < nt; t += stride) {
-    const uint64_t off = t * R;
-    WordR<R> x[B], y[B], z[B];
+  for (uint64_t t = (uint64_t)blockIdx.x * blockDim.x + threadIdx.x; t < nt; t += stride * U) {
+    uint64_t off[U];
+    bool ok[U];
 #pragma unroll
-    for (int k = 0; k < B; ++k) {
-      x[k] = ld_words<R>(a + (uint64_t)k * gpad + off);
-      y[k] = ld_words<R>(b + (uint64_t)k * gpad + off);
+    for (int u = 0; u < U; ++u) {
+      const uint64_t tu = t + (uint64_t)u * stride;
+      ok[u] = tu < nt;
+      off[u] = (ok[u] ? tu : t) * R;
     }
-    circuit<E, M, RZ, OPC, R>(x, y, negb, z);
-    mask_padding<OPC, R, B>(z, off, n);
+    WordR<RU> x[B], y[B], z[B];
 #pragma unroll
-    for (int k = 0; k < B; ++k) st_words<R>(c + (uint64_t)k * gpad + off, z[k]);
+    for (int k = 0; k < B; ++k)
+#pragma unroll
+      for (int u = 0; u < U; ++u) {
+        const WordR<R> xa = ld_words<R>(a + (uint64_t)k * gpad + off[u]);
+        const WordR<R> yb = ld_words<R>(b + (uint64_t)k * gpad + off[u]);
+#pragma unroll
+        for (int r = 0; r < R; ++r) {
+          x[k].w[u * R + r] = xa.w[r];
+          y[k].w[u * R + r] = yb.w[r];
+        }
+      }
+    circuit<E, M, RZ, OPC, RU>(x, y, negb, z);
+#pragma unroll
+    for (int u = 0; u < U; ++u) {
+      WordR<R> zu[B];
+#pragma unroll
+      for (int k = 0; k < B; ++k)
+#pragma unroll
+        for (int r = 0; r < R; ++r) zu[k].w[r] = z[k].w[u * R + r];
+      mask_padding<OPC, R, B>(zu, off[u], n);
+      if (ok[u]) {
+#pragma unroll
+        for (int k = 0; k < B; ++k) st_words<R>(c + (uint64_t)k * gpad + off[u], zu[k]);
+      }
+    }
   }
 }
 
-template <int E, int M, bool RZ, int OPC, int R>
+template <int E, int M, bool RZ, int OPC, int R, int U>
 __global__ void __launch_bounds__(512) k_binop(const uint32_t* a, const uint32_t* b, uint32_t* c,
                                                uint64_t gpad, uint64_t n, uint32_t negb) {
-  binop_body<E, M, RZ, OPC, R>(a, b, c, gpad, n, negb);
+  binop_body<E, M, RZ, OPC, R, U>(a, b, c, gpad, n, negb);
 }
 
 // Load the 32 R standard elements starting at element e0 (C bytes each) as
@@ -384,11 +413,19 @@ using ChainLauncher = hipError_t (*)(const void* a, uint32_t alpha, const void* 
                                      uint64_t gpad, uint64_t n, uint32_t negb1, uint32_t negb2, unsigned grid,
                                      unsigned block, hipStream_t s);
 
-constexpr int kMaxWordsPerLane = 2;  // R in {1, 2}
+// Launch shapes of the elementwise kernels: R words per lane in {1, 2, 4}
+// (index 0, 1, 2) and U units per loop step in {1, 2} (index 0, 1).
+constexpr int kWordChoices = 3;
+constexpr int kUnrollChoices = 2;
+constexpr int r_index(int r) { return r == 1 ? 0 : (r == 2 ? 1 : (r == 4 ? 2 : -1)); }
+
+// Four words per lane are compiled for the formats of at most 10 bits,
+// whose circuits leave the registers for them.
+constexpr bool four_words_ok(int e, int m) { return 1 + e + m <= 10; }
 
 struct Registry {
-  // [e][m][opclass][rz][R-1]
-  BinopLauncher binop[kMaxE + 1][kMaxM + 1][kOpClasses][2][kMaxWordsPerLane] = {};
+  // [e][m][opclass][rz][r_index(R)][U-1]
+  BinopLauncher binop[kMaxE + 1][kMaxM + 1][kOpClasses][2][kWordChoices][kUnrollChoices] = {};
   StdLauncher std_op[kMaxE + 1][kMaxM + 1][kOpClasses][2] = {};
   // two-op chains: [e][m][opclass of op1][opclass of op2][rz], op classes
   // 0 (add/sub) and 1 (mul)
@@ -398,10 +435,10 @@ struct Registry {
 };
 Registry& registry();
 
-template <int E, int M, bool RZ, int OPC, int R>
+template <int E, int M, bool RZ, int OPC, int R, int U>
 hipError_t launch_binop(const void* a, const void* b, void* c, uint64_t gpad, uint64_t n, uint32_t negb, unsigned grid,
                         unsigned block, hipStream_t s) {
-  hipLaunchKernelGGL((k_binop<E, M, RZ, OPC, R>), dim3(grid), dim3(block), 0, s,
+  hipLaunchKernelGGL((k_binop<E, M, RZ, OPC, R, U>), dim3(grid), dim3(block), 0, s,
                      static_cast<const uint32_t*>(a), static_cast<const uint32_t*>(b),
                      static_cast<uint32_t*>(c), gpad, n, negb);
   return hipGetLastError();
@@ -425,26 +462,30 @@ hipError_t launch_binop_std_w(const void* a, const void* b, void* c, uint64_t n,
   return hipGetLastError();
 }
 
+template <int E, int M, int OPC, bool RZ>
+void register_shapes() {
+  Registry& r = registry();
+  auto& L = r.binop[E][M][OPC][RZ ? 1 : 0];
+  L[0][0] = launch_binop<E, M, RZ, OPC, 1, 1>;
+  L[1][0] = launch_binop<E, M, RZ, OPC, 2, 1>;
+  L[0][1] = launch_binop<E, M, RZ, OPC, 1, 2>;
+  if constexpr (four_words_ok(E, M)) L[2][0] = launch_binop<E, M, RZ, OPC, 4, 1>;
+}
+
 template <int E, int M>
 void register_format() {
   Registry& r = registry();
   r.max_block[E][M] = 512;
-  r.binop[E][M][0][0][0] = launch_binop<E, M, false, 0, 1>;
-  r.binop[E][M][0][1][0] = launch_binop<E, M, true, 0, 1>;
-  r.binop[E][M][1][0][0] = launch_binop<E, M, false, 1, 1>;
-  r.binop[E][M][1][1][0] = launch_binop<E, M, true, 1, 1>;
-  r.binop[E][M][0][0][1] = launch_binop<E, M, false, 0, 2>;
-  r.binop[E][M][0][1][1] = launch_binop<E, M, true, 0, 2>;
-  r.binop[E][M][1][0][1] = launch_binop<E, M, false, 1, 2>;
-  r.binop[E][M][1][1][1] = launch_binop<E, M, true, 1, 2>;
+  register_shapes<E, M, 0, false>();
+  register_shapes<E, M, 0, true>();
+  register_shapes<E, M, 1, false>();
+  register_shapes<E, M, 1, true>();
+  register_shapes<E, M, 2, false>();
+  register_shapes<E, M, 2, true>();
   r.std_op[E][M][0][0] = launch_binop_std<E, M, false, 0>;
   r.std_op[E][M][0][1] = launch_binop_std<E, M, true, 0>;
   r.std_op[E][M][1][0] = launch_binop_std<E, M, false, 1>;
   r.std_op[E][M][1][1] = launch_binop_std<E, M, true, 1>;
-  r.binop[E][M][2][0][0] = launch_binop<E, M, false, 2, 1>;
-  r.binop[E][M][2][1][0] = launch_binop<E, M, true, 2, 1>;
-  r.binop[E][M][2][0][1] = launch_binop<E, M, false, 2, 2>;
-  r.binop[E][M][2][1][1] = launch_binop<E, M, true, 2, 2>;
   r.std_op[E][M][2][0] = launch_binop_std<E, M, false, 2>;
   r.std_op[E][M][2][1] = launch_binop_std<E, M, true, 2>;
 }
@@ -456,8 +497,8 @@ void register_wide_format() {
   Registry& r = registry();
   r.max_block[E][M] = 512;
 #define BFP_WIDE_REG(OPC)                                           \
-  r.binop[E][M][OPC][0][0] = launch_binop<E, M, false, OPC, 1>;    \
-  r.binop[E][M][OPC][1][0] = launch_binop<E, M, true, OPC, 1>;     \
+  r.binop[E][M][OPC][0][0][0] = launch_binop<E, M, false, OPC, 1, 1>; \
+  r.binop[E][M][OPC][1][0][0] = launch_binop<E, M, true, OPC, 1, 1>;  \
   r.std_op[E][M][OPC][0] = launch_binop_std_w<E, M, false, OPC>;   \
   r.std_op[E][M][OPC][1] = launch_binop_std_w<E, M, true, OPC>;
   BFP_WIDE_REG(0)

@@ -28,7 +28,7 @@ constexpr uint64_t kMaxN = 1ull << 36;
 bool format_ok(const bfp_format& f) {
   if (f.pad != 0 || (f.round != BFP_RNE && f.round != BFP_RZ)) return false;
   if (f.e < 2 || f.e > kMaxE || f.m < 1 || f.m > kMaxM) return false;
-  return registry().binop[f.e][f.m][0][0][0] != nullptr;
+  return registry().binop[f.e][f.m][0][0][0][0] != nullptr;
 }
 
 int bits_of(const bfp_format& f) { return 1 + f.e + f.m; }
@@ -84,11 +84,11 @@ void cfg_init_locked() {
           bfp_launch& c = g_cfg[o][e][m][r];
           const int B = 1 + e + m;
           const bool valu_heavy = (o == 1 && m >= 15) || (o == 2 && m >= 10);
-          const bool one_word_only = !registry().binop[e][m][o][r][1];
+          const bool one_word_only = !registry().binop[e][m][o][r][1][0];
           c.words_per_lane = (B <= 8 || valu_heavy || one_word_only) ? 1 : 2;
           c.block = B <= 8 ? 128 : 256;  // within every format's max_block
           c.blocks_per_cu = 0;
-          c.pad = 0;
+          c.unroll = 1;
         }
   g_cfg_init = true;
 }
@@ -100,8 +100,8 @@ bfp_launch cfg_get(int opc, const bfp_format& f) {
 }
 
 bool cfg_valid(const bfp_launch& c) {
-  if (c.pad != 0) return false;
-  if (c.words_per_lane != 1 && c.words_per_lane != 2) return false;
+  if (c.unroll < 0 || c.unroll > 2) return false;
+  if (c.words_per_lane != 1 && c.words_per_lane != 2 && c.words_per_lane != 4) return false;
   if (c.block != 64 && c.block != 128 && c.block != 256 && c.block != 512) return false;
   if (c.blocks_per_cu < 0 || c.blocks_per_cu > 64) return false;
   return true;
@@ -297,9 +297,11 @@ bfp_status bfp_binop(int op, bfp_format f, const void* a, const void* b, void* c
   if ((c != a && overlap(c, bytes, a, bytes)) || (c != b && overlap(c, bytes, b, bytes))) return BFP_E_ALIAS;
   const int opc = opclass_of(op);
   const bfp_launch cfg = cfg_get(opc, f);
-  BinopLauncher L = registry().binop[f.e][f.m][opc][f.round][cfg.words_per_lane - 1];
+  const int U = cfg.unroll > 1 ? 2 : 1;
+  BinopLauncher L = registry().binop[f.e][f.m][opc][f.round][r_index(cfg.words_per_lane)][U - 1];
   if (!L) return BFP_E_FORMAT;
-  const unsigned grid = grid_for(gpad / cfg.words_per_lane, cfg.block, cfg.blocks_per_cu);
+  const uint64_t units = gpad / cfg.words_per_lane;
+  const unsigned grid = grid_for((units + U - 1) / U, cfg.block, cfg.blocks_per_cu);
   const uint32_t negb = op == BFP_SUB ? 0xFFFFFFFFu : 0u;
   return hip_status(L(a, b, c, gpad, n, negb, grid, (unsigned)cfg.block, (hipStream_t)stream));
 }
@@ -366,7 +368,9 @@ bfp_status bfp_launch_set(int op, bfp_format f, const bfp_launch* cfg) {
   if (!cfg) return BFP_E_NULL;
   if (!cfg_valid(*cfg)) return BFP_E_ARG;
   // the wide formats have one-word kernels only, compiled for blocks of at most 256
-  if (!registry().binop[f.e][f.m][opclass_of(op)][f.round][cfg->words_per_lane - 1]) return BFP_E_ARG;
+  if (!registry().binop[f.e][f.m][opclass_of(op)][f.round][r_index(cfg->words_per_lane)]
+                       [cfg->unroll > 1 ? 1 : 0])
+    return BFP_E_ARG;
   if (cfg->block > registry().max_block[f.e][f.m]) return BFP_E_ARG;
   std::lock_guard<std::mutex> lk(g_cfg_mu);
   cfg_init_locked();
@@ -382,8 +386,9 @@ bfp_status bfp_launch_load(const char* path) {
   bfp_status st = BFP_OK;
   while (fgets(line, sizeof line, fp)) {
     if (line[0] == '#' || line[0] == '\n') continue;
-    int op, e, m, r, wpl, block, bpc;
-    if (sscanf(line, "%d %d %d %d %d %d %d", &op, &e, &m, &r, &wpl, &block, &bpc) != 7) {
+    int op, e, m, r, wpl, block, bpc, unroll = 1;
+    const int got = sscanf(line, "%d %d %d %d %d %d %d %d", &op, &e, &m, &r, &wpl, &block, &bpc, &unroll);
+    if (got != 7 && got != 8) {  // the unroll column may be absent (one unit per step)
       st = BFP_E_ARG;
       break;
     }
@@ -397,7 +402,7 @@ bfp_status bfp_launch_load(const char* path) {
     c.words_per_lane = wpl;
     c.block = block;
     c.blocks_per_cu = bpc;
-    c.pad = 0;
+    c.unroll = unroll;
     const bfp_status s2 = bfp_launch_set(op, f, &c);
     if (s2 != BFP_OK) {
       st = s2;
@@ -412,7 +417,7 @@ bfp_status bfp_launch_save(const char* path) {
   if (!path) return BFP_E_NULL;
   FILE* fp = fopen(path, "w");
   if (!fp) return BFP_E_ARG;
-  fprintf(fp, "# op e m round words_per_lane block blocks_per_cu\n");
+  fprintf(fp, "# op e m round words_per_lane block blocks_per_cu unroll\n");
   {
     std::lock_guard<std::mutex> lk(g_cfg_mu);
     cfg_init_locked();
@@ -420,11 +425,11 @@ bfp_status bfp_launch_save(const char* path) {
       for (int e = 0; e <= kMaxE; ++e)
         for (int m = 0; m <= kMaxM; ++m)
           for (int r = 0; r < 2; ++r) {
-            if (!registry().binop[e][m][0][0][0]) continue;
+            if (!registry().binop[e][m][0][0][0][0]) continue;
             const bfp_launch& c = g_cfg[o][e][m][r];
             const int op = o == 1 ? BFP_MUL : (o == 2 ? BFP_DIV : BFP_ADD);
-            fprintf(fp, "%d %d %d %d %d %d %d\n", op, e, m, r, c.words_per_lane, c.block,
-                    c.blocks_per_cu);
+            fprintf(fp, "%d %d %d %d %d %d %d %d\n", op, e, m, r, c.words_per_lane, c.block,
+                    c.blocks_per_cu, c.unroll > 1 ? 2 : 1);
           }
   }
   fclose(fp);

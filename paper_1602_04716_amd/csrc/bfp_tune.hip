@@ -1,7 +1,9 @@
 // bfp_tune.hip -- autotuning of bfp_binop's launch configuration.
 //
-// For one (op, format, rounding mode) every candidate
-//   words_per_lane in {1, 2}      (W = 32 or 64 elements per lane word)
+// For one (op, format, rounding mode) every compiled candidate
+//   words_per_lane in {1, 2, 4}   (W = 32, 64 or 128 elements per lane word;
+//                                   4 for formats of at most 10 bits)
+//   unroll         in {1, 2}      (units per lane per loop step)
 //   block          in {64, 128, 256, 512}
 //   blocks_per_cu  in {0, 4, 8}   (0: one thread per slice; else a
 //                                   grid-stride loop of that depth)
@@ -198,7 +200,7 @@ extern "C" bfp_status bfp_autotune(int op, bfp_format f, uint64_t n_probe, int w
   if (!op_valid(op)) return BFP_E_OP;
   if (!bfp_format_supported(f)) return BFP_E_FORMAT;
   if (n_probe == 0 || n_probe > (1ull << 30)) return BFP_E_ARG;
-  if ((words_per_lane_mask & 3) == 0) return BFP_E_ARG;
+  if ((words_per_lane_mask & 7) == 0) return BFP_E_ARG;
   if (reps < 1 || reps > 1000) return BFP_E_ARG;
   hipStream_t s = (hipStream_t)stream;
   const size_t vec_bytes = bfp_bitslice_bytes(f, n_probe);
@@ -228,41 +230,44 @@ extern "C" bfp_status bfp_autotune(int op, bfp_format f, uint64_t n_probe, int w
   bfp_launch best_cfg = saved;
   std::vector<float> ts;
   bool any = false;
-  for (int wpl = 1; wpl <= 2 && st == BFP_OK; ++wpl) {
-    if (!(words_per_lane_mask & wpl)) continue;
-    if (!registry().binop[f.e][f.m][opclass_of(op)][f.round][wpl - 1]) continue;  // not compiled
-    any = true;
-    for (int blk : blocks) {
-      if (blk > registry().max_block[f.e][f.m]) continue;  // not compiled for such blocks
-      for (int bpc : bpcs) {
-        bfp_launch cfg;
-        cfg.words_per_lane = wpl;
-        cfg.block = blk;
-        cfg.blocks_per_cu = bpc;
-        cfg.pad = 0;
-        st = bfp_launch_set(op, f, &cfg);
-        if (st != BFP_OK) break;
-        ts.clear();
-        for (int r = 0; r <= reps && st == BFP_OK; ++r) {
-          hipLaunchKernelGGL(k_sweep_read, dim3(4096), dim3(256), 0, s, (const u32x4*)sweep.p, sweep_bytes / 16,
-                             (uint32_t*)sink.p);
-          if (hipEventRecord(e0, s) != hipSuccess) st = BFP_E_HIP;
-          if (st == BFP_OK) st = bfp_binop(op, f, a.p, b.p, c.p, n_probe, stream);
-          if (st == BFP_OK && hipEventRecord(e1, s) != hipSuccess) st = BFP_E_HIP;
-          if (st == BFP_OK && hipEventSynchronize(e1) != hipSuccess) st = BFP_E_HIP;
-          float ms = 0.f;
-          if (st == BFP_OK && hipEventElapsedTime(&ms, e0, e1) != hipSuccess) st = BFP_E_HIP;
-          if (r > 0) ts.push_back(ms);  // first run warms the code path
+  for (int wi = 0; wi < kWordChoices && st == BFP_OK; ++wi) {
+    const int wpl = 1 << wi;
+    if (!(words_per_lane_mask & (1 << wi))) continue;
+    for (int unroll = 1; unroll <= kUnrollChoices && st == BFP_OK; ++unroll) {
+      if (!registry().binop[f.e][f.m][opclass_of(op)][f.round][wi][unroll - 1]) continue;  // not compiled
+      any = true;
+      for (int blk : blocks) {
+        if (blk > registry().max_block[f.e][f.m]) continue;  // not compiled for such blocks
+        for (int bpc : bpcs) {
+          bfp_launch cfg;
+          cfg.words_per_lane = wpl;
+          cfg.block = blk;
+          cfg.blocks_per_cu = bpc;
+          cfg.unroll = unroll;
+          st = bfp_launch_set(op, f, &cfg);
+          if (st != BFP_OK) break;
+          ts.clear();
+          for (int r = 0; r <= reps && st == BFP_OK; ++r) {
+            hipLaunchKernelGGL(k_sweep_read, dim3(4096), dim3(256), 0, s, (const u32x4*)sweep.p,
+                               sweep_bytes / 16, (uint32_t*)sink.p);
+            if (hipEventRecord(e0, s) != hipSuccess) st = BFP_E_HIP;
+            if (st == BFP_OK) st = bfp_binop(op, f, a.p, b.p, c.p, n_probe, stream);
+            if (st == BFP_OK && hipEventRecord(e1, s) != hipSuccess) st = BFP_E_HIP;
+            if (st == BFP_OK && hipEventSynchronize(e1) != hipSuccess) st = BFP_E_HIP;
+            float ms = 0.f;
+            if (st == BFP_OK && hipEventElapsedTime(&ms, e0, e1) != hipSuccess) st = BFP_E_HIP;
+            if (r > 0) ts.push_back(ms);  // first run warms the code path
+          }
+          if (st != BFP_OK) break;
+          std::nth_element(ts.begin(), ts.begin() + ts.size() / 2, ts.end());
+          const double med = ts[ts.size() / 2] * 1e3;
+          if (med < best) {
+            best = med;
+            best_cfg = cfg;
+          }
         }
         if (st != BFP_OK) break;
-        std::nth_element(ts.begin(), ts.begin() + ts.size() / 2, ts.end());
-        const double med = ts[ts.size() / 2] * 1e3;
-        if (med < best) {
-          best = med;
-          best_cfg = cfg;
-        }
       }
-      if (st != BFP_OK) break;
     }
   }
   (void)hipEventDestroy(e0);

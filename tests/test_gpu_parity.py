@@ -53,8 +53,16 @@ def _operands(e, m, n, seed):
     return a.astype(dt), b.astype(dt)
 
 
-def _set_wpl(op, f, wpl):
-    bfp.bfp_launch_set(op, f, wpl, 256, 0)
+def _set_wpl(op, f, wpl, unroll=1):
+    bfp.bfp_launch_set(op, f, wpl, 256, 0, unroll)
+
+
+def _shapes(e, m):
+    """(words per lane, units per step) pairs compiled for the format."""
+    sh = [(1, 1), (2, 1), (1, 2)]
+    if 1 + e + m <= 10:
+        sh.append((4, 1))
+    return sh
 
 
 @pytest.mark.parametrize("e,m", FORMATS)
@@ -82,8 +90,8 @@ def test_binop_bitslice(e, m):
         for op in OPS:
             want = oracle.binop(op, e, m, mode, a, b, nthreads=8)
             want_planes = oracle.pack(e, m, want)
-            for wpl in (1, 2):
-                _set_wpl(op, f, wpl)
+            for wpl, unroll in _shapes(e, m):
+                _set_wpl(op, f, wpl, unroll)
                 pc = bfp.empty_bitslice(f, NPAR)
                 bfp.bfp_binop(op, f, pa, pb, pc, NPAR)
                 got = _host(pc)
@@ -91,8 +99,8 @@ def test_binop_bitslice(e, m):
                     res = oracle.unpack(e, m, got, NPAR).astype(np.uint32)
                     bad = np.flatnonzero(res != want)
                     k = bad[0] if bad.size else -1
-                    pytest.fail("(%d,%d) %s mode %d wpl %d: %d bad elements, e.g. a=%#x b=%#x got=%#x want=%#x"
-                                % (e, m, op, mode, wpl, bad.size, a[k], b[k], res[k], want[k]))
+                    pytest.fail("(%d,%d) %s mode %d wpl %d unroll %d: %d bad elements, e.g. a=%#x b=%#x got=%#x "
+                                "want=%#x" % (e, m, op, mode, wpl, unroll, bad.size, a[k], b[k], res[k], want[k]))
             _set_wpl(op, f, 1)
             out = bfp.unpack(f, pc, NPAR)
             assert np.array_equal(_host(out).astype(np.uint32), want)

@@ -26,33 +26,43 @@ def test_autotune_installs_measured_best(e, m, op):
     best, us = bfp.bfp_autotune(op, f, 1 << 20, 3, 2)
     assert us > 0
     cur = bfp.bfp_launch_get(op, f)
-    assert (cur.words_per_lane, cur.block, cur.blocks_per_cu) == (best.words_per_lane, best.block, best.blocks_per_cu)
+    assert (cur.words_per_lane, cur.block, cur.blocks_per_cu, cur.unroll) == \
+        (best.words_per_lane, best.block, best.blocks_per_cu, best.unroll)
     assert best.words_per_lane in (1, 2) and best.block in (64, 128, 256, 512) and best.blocks_per_cu in (0, 4, 8)
+    assert best.unroll in (1, 2)
     best1, _ = bfp.bfp_autotune(op, f, 1 << 18, 1, 1)
     assert best1.words_per_lane == 1
     bfp.bfp_launch_set(op, f, old.words_per_lane, old.block, old.blocks_per_cu)
 
 
-def test_every_candidate_configuration_is_exact():
-    """All 24 launch variants give identical, oracle-exact results (ragged n)."""
-    e, m = 6, 7
+@pytest.mark.parametrize("e,m", [(6, 7), (4, 3)])
+def test_every_candidate_configuration_is_exact(e, m):
+    """Every compiled launch variant (words per lane 1, 2 and, at most 10
+    bits, 4; units per step 1 and 2; 4 block sizes; 3 grid depths) gives
+    identical, oracle-exact results (ragged n)."""
     n = 300000 + 5
     a = inputs.sweep_operands(e, m, n, 1)
     b = inputs.sweep_operands(e, m, n, 2)
     f = bfp.fmt(e, m)
     pa, pb = bfp.pack(f, torch.from_numpy(a).cuda()), bfp.pack(f, torch.from_numpy(b).cuda())
-    for op in ("mul", "div"):
+    shapes = [(1, 1), (2, 1), (1, 2)] + ([(4, 1)] if 1 + e + m <= 10 else [])
+    for op in ("add", "mul", "div"):
         want = oracle.binop(op, e, m, 0, a, b, nthreads=8)
         old = bfp.bfp_launch_get(op, f)
-        for wpl in (1, 2):
+        for wpl, unroll in shapes:
             for blk in (64, 128, 256, 512):
                 for bpc in (0, 4, 8):
-                    bfp.bfp_launch_set(op, f, wpl, blk, bpc)
+                    bfp.bfp_launch_set(op, f, wpl, blk, bpc, unroll)
                     pc = bfp.empty_bitslice(f, n)
                     bfp.bfp_binop(op, f, pa, pb, pc, n)
                     got = bfp.unpack(f, pc, n).cpu().numpy().astype(np.uint32)
-                    assert np.array_equal(got, want), (op, wpl, blk, bpc)
-        bfp.bfp_launch_set(op, f, old.words_per_lane, old.block, old.blocks_per_cu)
+                    assert np.array_equal(got, want), (op, wpl, unroll, blk, bpc)
+        with pytest.raises(bfp.BfpError):
+            bfp.bfp_launch_set(op, f, 2, 256, 0, 2)      # two words and two units: not compiled
+        if 1 + e + m > 10:
+            with pytest.raises(bfp.BfpError):
+                bfp.bfp_launch_set(op, f, 4, 256, 0)     # four words only up to 10 bits
+        bfp.bfp_launch_set(op, f, old.words_per_lane, old.block, old.blocks_per_cu, max(1, old.unroll))
 
 
 def test_autotune_errors():
