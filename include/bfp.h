@@ -269,6 +269,28 @@ bfp_status bfp_flush_llc(uint64_t bytes, void* stream);
  * is not compiled. */
 long bfp_gate_count(int op, bfp_format f);
 
+/* Launch configuration of the two-op chain kernels for (op1, op2, f) (ops
+ * share entries by class: add/sub, mul) and of the integer kernels for
+ * (op, k, kind): block and blocks_per_cu are free, words_per_lane is the
+ * compiled one (1 for chains; 2, or 1 for the multipliers from k = 13, for
+ * integers) and unroll 1.  Default: 256-thread blocks, one thread per work
+ * item.  Errors: BFP_E_OP, BFP_E_FORMAT, BFP_E_NULL, BFP_E_ARG. */
+bfp_status bfp_chain_launch_get(int op1, int op2, bfp_format f, bfp_launch* out);
+bfp_status bfp_chain_launch_set(int op1, int op2, bfp_format f, const bfp_launch* cfg);
+bfp_status bfp_int_launch_get(int op, int k, int kind, bfp_launch* out);
+bfp_status bfp_int_launch_set(int op, int k, int kind, const bfp_launch* cfg);
+
+/* Autotune bfp_chain2 for (op1, op2, f), or bfp_int_binop for (op, k,
+ * kind), as bfp_autotune does bfp_binop: every block {64,128,256,512} x
+ * blocks_per_cu {0,4,8}, median of `reps` cold runs on n_probe random
+ * elements; installs and returns the fastest.  bfp_launch_save writes these
+ * entries too ("chain ..." and "int ..." lines) and bfp_launch_load reads
+ * them. */
+bfp_status bfp_autotune_chain(int op1, int op2, bfp_format f, uint64_t n_probe, int reps, void* stream,
+                              bfp_launch* best, double* best_us);
+bfp_status bfp_autotune_int(int op, int k, int kind, uint64_t n_probe, int reps, void* stream, bfp_launch* best,
+                            double* best_us);
+
 /* ---- batched persistent launch --------------------------------------------- */
 /* Many vectors of uneven length and mixed formats in one persistent kernel,
  * captured once in a HIP graph.  (Not in the paper, whose operations act on

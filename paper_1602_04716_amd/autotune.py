@@ -11,7 +11,9 @@ before every run and installs the fastest; the table is saved for
 ``bfp.lib()`` to load.  The printed JSON lines are the format-sweep
 measurement: elements/s, achieved HBM GB/s (3B/8 bytes per element) and
 bitwise VALU rate (gate count / 32 per element) of the tuned kernel, and the
-fraction of each peak.
+fraction of each peak.  The two-op chain kernels (``bfp_autotune_chain``) and
+the k-bit integer kernels (``bfp_autotune_int``) are tuned after them over
+block size and grid depth, and saved in the same table.
 """
 from __future__ import annotations
 
@@ -48,6 +50,29 @@ def tune(formats, ops=("add", "mul", "div"), modes=(0, 1), n=1 << 24, reps=7, ma
     return out
 
 
+def tune_chains(formats, modes=(0, 1), n=1 << 24, reps=5, log=print):
+    """Block and grid depth of the two-op chain kernels, per format, op-class
+    pair and mode (sub shares add's entries)."""
+    for (e, m) in formats:
+        for o1 in ("add", "mul"):
+            for o2 in ("add", "mul"):
+                for r in modes:
+                    best, us = bfp.bfp_autotune_chain(o1, o2, bfp.fmt(e, m, r), n, reps)
+                    log(json.dumps({"kind": "chain", "op1": o1, "op2": o2, "e": e, "m": m, "round": r,
+                                    "block": best.block, "blocks_per_cu": best.blocks_per_cu, "us": us}))
+
+
+def tune_ints(ks=range(1, 33), n=1 << 24, reps=5, log=print):
+    """Block and grid depth of the k-bit integer kernels, per k, op and kind."""
+    for k in ks:
+        for op in ("add", "sub", "mul"):
+            for kind in ("wrap", "satu", "sats"):
+                best, us = bfp.bfp_autotune_int(op, k, kind, n, reps)
+                log(json.dumps({"kind": "int", "op": op, "k": k, "int_kind": kind, "block": best.block,
+                                "blocks_per_cu": best.blocks_per_cu, "words_per_lane": best.words_per_lane,
+                                "us": us}))
+
+
 def main(argv=None):
     ap = argparse.ArgumentParser()
     ap.add_argument("--n-log2", type=int, default=24)
@@ -55,6 +80,8 @@ def main(argv=None):
     ap.add_argument("--out", default=bfp.TUNE_TABLE)
     ap.add_argument("--formats", default="", help="comma list like 5:10,8:7; default all 44")
     ap.add_argument("--ops", default="add,mul,div", help="op classes to tune (sub shares add's entry)")
+    ap.add_argument("--no-chains", action="store_true")
+    ap.add_argument("--no-ints", action="store_true")
     a = ap.parse_args(argv)
     import torch
     assert torch.cuda.is_available()
@@ -63,7 +90,12 @@ def main(argv=None):
     fmts = inputs.sweep_formats() + inputs.wide_formats()
     if a.formats:
         fmts = [tuple(int(x) for x in s.split(":")) for s in a.formats.split(",")]
-    tune(fmts, ops=tuple(a.ops.split(",")), n=1 << a.n_log2, reps=a.reps, log=lambda s: print(s, flush=True))
+    log = lambda s: print(s, flush=True)
+    tune(fmts, ops=tuple(a.ops.split(",")), n=1 << a.n_log2, reps=a.reps, log=log)
+    if not a.no_chains:
+        tune_chains([f for f in fmts if f in inputs.sweep_formats()], n=1 << a.n_log2, log=log)
+    if not a.no_ints:
+        tune_ints(n=1 << a.n_log2, log=log)
     if a.out:
         os.makedirs(os.path.dirname(a.out), exist_ok=True)
         bfp.bfp_launch_save(a.out)

@@ -117,6 +117,16 @@ _SIGS = {
     "bfp_measure_copy": (ctypes.c_int, [ctypes.c_uint64, ctypes.c_int, ctypes.c_void_p,
                                         ctypes.POINTER(ctypes.c_double)]),
     "bfp_launch_save": (ctypes.c_int, [ctypes.c_char_p]),
+    "bfp_chain_launch_get": (ctypes.c_int, [ctypes.c_int, ctypes.c_int, bfp_format, ctypes.POINTER(bfp_launch)]),
+    "bfp_chain_launch_set": (ctypes.c_int, [ctypes.c_int, ctypes.c_int, bfp_format, ctypes.POINTER(bfp_launch)]),
+    "bfp_int_launch_get": (ctypes.c_int, [ctypes.c_int, ctypes.c_int, ctypes.c_int, ctypes.POINTER(bfp_launch)]),
+    "bfp_int_launch_set": (ctypes.c_int, [ctypes.c_int, ctypes.c_int, ctypes.c_int, ctypes.POINTER(bfp_launch)]),
+    "bfp_autotune_chain": (ctypes.c_int, [ctypes.c_int, ctypes.c_int, bfp_format, ctypes.c_uint64, ctypes.c_int,
+                                          ctypes.c_void_p, ctypes.POINTER(bfp_launch),
+                                          ctypes.POINTER(ctypes.c_double)]),
+    "bfp_autotune_int": (ctypes.c_int, [ctypes.c_int, ctypes.c_int, ctypes.c_int, ctypes.c_uint64, ctypes.c_int,
+                                        ctypes.c_void_p, ctypes.POINTER(bfp_launch),
+                                        ctypes.POINTER(ctypes.c_double)]),
     "bfp_measure_hbm": (ctypes.c_int, [ctypes.c_uint64, ctypes.c_int, ctypes.c_int, ctypes.c_void_p,
                                        ctypes.POINTER(ctypes.c_double), ctypes.POINTER(ctypes.c_int),
                                        ctypes.POINTER(ctypes.c_int)]),
@@ -351,6 +361,43 @@ def bfp_launch_get(op, f) -> bfp_launch:
 def bfp_launch_set(op, f, words_per_lane: int, block: int, blocks_per_cu: int, unroll: int = 1):
     cfg = bfp_launch(words_per_lane, block, blocks_per_cu, unroll)
     _check(lib().bfp_launch_set(_op(op), f, ctypes.byref(cfg)), "bfp_launch_set")
+
+
+def bfp_chain_launch_get(op1, op2, f) -> bfp_launch:
+    out = bfp_launch()
+    _check(lib().bfp_chain_launch_get(_op(op1), _op(op2), f, ctypes.byref(out)), "bfp_chain_launch_get")
+    return out
+
+
+def bfp_chain_launch_set(op1, op2, f, block: int, blocks_per_cu: int):
+    cfg = bfp_launch(1, block, blocks_per_cu, 1)
+    _check(lib().bfp_chain_launch_set(_op(op1), _op(op2), f, ctypes.byref(cfg)), "bfp_chain_launch_set")
+
+
+def bfp_int_launch_get(op, k: int, kind) -> bfp_launch:
+    out = bfp_launch()
+    _check(lib().bfp_int_launch_get(_op(op), k, _kind(kind), ctypes.byref(out)), "bfp_int_launch_get")
+    return out
+
+
+def bfp_int_launch_set(op, k: int, kind, block: int, blocks_per_cu: int):
+    cur = bfp_int_launch_get(op, k, kind)
+    cfg = bfp_launch(cur.words_per_lane, block, blocks_per_cu, 1)
+    _check(lib().bfp_int_launch_set(_op(op), k, _kind(kind), ctypes.byref(cfg)), "bfp_int_launch_set")
+
+
+def bfp_autotune_chain(op1, op2, f, n_probe: int = 1 << 24, reps: int = 7, stream=None):
+    best, us = bfp_launch(), ctypes.c_double()
+    _check(lib().bfp_autotune_chain(_op(op1), _op(op2), f, n_probe, reps, _stream(stream), ctypes.byref(best),
+                                    ctypes.byref(us)), "bfp_autotune_chain")
+    return best, us.value
+
+
+def bfp_autotune_int(op, k: int, kind, n_probe: int = 1 << 24, reps: int = 7, stream=None):
+    best, us = bfp_launch(), ctypes.c_double()
+    _check(lib().bfp_autotune_int(_op(op), k, _kind(kind), n_probe, reps, _stream(stream), ctypes.byref(best),
+                                  ctypes.byref(us)), "bfp_autotune_int")
+    return best, us.value
 
 
 def bfp_measure_copy(nbytes: int, reps: int = 10, stream=None) -> float:

@@ -33,19 +33,19 @@ __global__ void __launch_bounds__(512) k_ibinop(const uint32_t* a, const uint32_
   }
 }
 
-using IntLauncher = hipError_t (*)(const void* a, const void* b, void* c, uint64_t gpad, unsigned block,
-                                   hipStream_t s);
+using IntLauncher = hipError_t (*)(const void* a, const void* b, void* c, uint64_t gpad, unsigned grid,
+                                   unsigned block, hipStream_t s);
 
 struct IntRegistry {
   IntLauncher op[kMaxIntBits + 1][3][3] = {};  // [k][op][kind]
+  int words[kMaxIntBits + 1][3] = {};          // words per lane compiled for [k][op]
 };
 IntRegistry& int_registry();
 
 template <int K, int OP, int KIND>
-hipError_t launch_ibinop(const void* a, const void* b, void* c, uint64_t gpad, unsigned block, hipStream_t s) {
+hipError_t launch_ibinop(const void* a, const void* b, void* c, uint64_t gpad, unsigned grid, unsigned block,
+                         hipStream_t s) {
   constexpr int R = int_words_per_lane<K, OP>();
-  const uint64_t items = gpad / R;
-  const unsigned grid = (unsigned)((items + block - 1) / block);
   hipLaunchKernelGGL((k_ibinop<K, OP, KIND, R>), dim3(grid > 0 ? grid : 1), dim3(block), 0, s,
                      static_cast<const uint32_t*>(a), static_cast<const uint32_t*>(b), static_cast<uint32_t*>(c),
                      gpad);
@@ -56,6 +56,7 @@ template <int K>
 void register_int() {
   IntRegistry& r = int_registry();
 #define BFP_INT_REG(OP)                                        \
+  r.words[K][OP] = int_words_per_lane<K, OP>();            \
   r.op[K][OP][kIntWrap] = launch_ibinop<K, OP, kIntWrap>; \
   r.op[K][OP][kIntSatU] = launch_ibinop<K, OP, kIntSatU>; \
   r.op[K][OP][kIntSatS] = launch_ibinop<K, OP, kIntSatS>;

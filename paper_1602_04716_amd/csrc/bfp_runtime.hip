@@ -93,6 +93,25 @@ void cfg_init_locked() {
   g_cfg_init = true;
 }
 
+// Chain kernels [e][m][opclass 1][opclass 2][round] and integer kernels
+// [k][op][kind]: block and grid depth (their words per lane are fixed).
+bfp_launch g_chain_cfg[kMaxE + 1][kMaxM + 1][2][2][2];
+bfp_launch g_int_cfg[kMaxIntBits + 1][3][3];
+bool g_aux_init = false;
+
+void aux_init_locked() {
+  if (g_aux_init) return;
+  for (auto& a : g_chain_cfg)
+    for (auto& b : a)
+      for (auto& c : b)
+        for (auto& d : c)
+          for (auto& x : d) x = bfp_launch{1, 256, 0, 1};
+  for (int k = 0; k <= kMaxIntBits; ++k)
+    for (int o = 0; o < 3; ++o)
+      for (int kd = 0; kd < 3; ++kd) g_int_cfg[k][o][kd] = bfp_launch{int_registry().words[k][o], 256, 0, 1};
+  g_aux_init = true;
+}
+
 bfp_launch cfg_get(int opc, const bfp_format& f) {
   std::lock_guard<std::mutex> lk(g_cfg_mu);
   cfg_init_locked();
@@ -149,8 +168,14 @@ bfp_status chain_impl(int op1, int op2, bfp_format f, const void* a, uint32_t al
   const void* in[3] = {a, b, c};
   for (const void* p : in)
     if (p && p != d && overlap(d, bytes, p, bytes)) return BFP_E_ALIAS;
-  const unsigned block = 256;
-  const unsigned grid = grid_for(gpad, (int)block, 0);
+  bfp_launch cfg;
+  {
+    std::lock_guard<std::mutex> lk(g_cfg_mu);
+    aux_init_locked();
+    cfg = g_chain_cfg[f.e][f.m][opclass_of(op1)][opclass_of(op2)][f.round];
+  }
+  const unsigned block = (unsigned)cfg.block;
+  const unsigned grid = grid_for(gpad, (int)block, cfg.blocks_per_cu);
   const uint32_t alpha_b = alpha & (uint32_t)((1ull << bits_of(f)) - 1u);
   const uint32_t negb1 = op1 == BFP_SUB ? 0xFFFFFFFFu : 0u, negb2 = op2 == BFP_SUB ? 0xFFFFFFFFu : 0u;
   return hip_status(L(a, alpha_b, b, c, d, gpad, n, negb1, negb2, grid, block, (hipStream_t)stream));
@@ -281,7 +306,14 @@ bfp_status bfp_int_binop(int op, int k, int kind, const void* a, const void* b, 
   if ((c != a && overlap(c, bytes, a, bytes)) || (c != b && overlap(c, bytes, b, bytes))) return BFP_E_ALIAS;
   IntLauncher L = int_registry().op[k][op][kind];
   if (!L) return BFP_E_FORMAT;
-  return hip_status(L(a, b, c, gpad, 256u, (hipStream_t)stream));
+  bfp_launch cfg;
+  {
+    std::lock_guard<std::mutex> lk(g_cfg_mu);
+    aux_init_locked();
+    cfg = g_int_cfg[k][op][kind];
+  }
+  const unsigned grid = grid_for(gpad / cfg.words_per_lane, cfg.block, cfg.blocks_per_cu);
+  return hip_status(L(a, b, c, gpad, grid, (unsigned)cfg.block, (hipStream_t)stream));
 }
 
 bfp_status bfp_binop(int op, bfp_format f, const void* a, const void* b, void* c, uint64_t n, void* stream) {
@@ -378,6 +410,48 @@ bfp_status bfp_launch_set(int op, bfp_format f, const bfp_launch* cfg) {
   return BFP_OK;
 }
 
+bfp_status bfp_chain_launch_get(int op1, int op2, bfp_format f, bfp_launch* out) {
+  if (!chain_op_ok(op1) || !chain_op_ok(op2)) return BFP_E_OP;
+  if (!format_ok(f) || !registry().chain[f.e][f.m][0][0][0]) return BFP_E_FORMAT;
+  if (!out) return BFP_E_NULL;
+  std::lock_guard<std::mutex> lk(g_cfg_mu);
+  aux_init_locked();
+  *out = g_chain_cfg[f.e][f.m][opclass_of(op1)][opclass_of(op2)][f.round];
+  return BFP_OK;
+}
+
+bfp_status bfp_chain_launch_set(int op1, int op2, bfp_format f, const bfp_launch* cfg) {
+  if (!chain_op_ok(op1) || !chain_op_ok(op2)) return BFP_E_OP;
+  if (!format_ok(f) || !registry().chain[f.e][f.m][0][0][0]) return BFP_E_FORMAT;
+  if (!cfg) return BFP_E_NULL;
+  if (!cfg_valid(*cfg) || cfg->words_per_lane != 1 || cfg->unroll > 1) return BFP_E_ARG;
+  std::lock_guard<std::mutex> lk(g_cfg_mu);
+  aux_init_locked();
+  g_chain_cfg[f.e][f.m][opclass_of(op1)][opclass_of(op2)][f.round] = *cfg;
+  return BFP_OK;
+}
+
+bfp_status bfp_int_launch_get(int op, int k, int kind, bfp_launch* out) {
+  if (op != BFP_ADD && op != BFP_SUB && op != BFP_MUL) return BFP_E_OP;
+  if (!int_bits_ok(k) || kind < BFP_INT_WRAP || kind > BFP_INT_SAT_S) return BFP_E_FORMAT;
+  if (!out) return BFP_E_NULL;
+  std::lock_guard<std::mutex> lk(g_cfg_mu);
+  aux_init_locked();
+  *out = g_int_cfg[k][op][kind];
+  return BFP_OK;
+}
+
+bfp_status bfp_int_launch_set(int op, int k, int kind, const bfp_launch* cfg) {
+  if (op != BFP_ADD && op != BFP_SUB && op != BFP_MUL) return BFP_E_OP;
+  if (!int_bits_ok(k) || kind < BFP_INT_WRAP || kind > BFP_INT_SAT_S) return BFP_E_FORMAT;
+  if (!cfg) return BFP_E_NULL;
+  if (!cfg_valid(*cfg) || cfg->words_per_lane != int_registry().words[k][op] || cfg->unroll > 1) return BFP_E_ARG;
+  std::lock_guard<std::mutex> lk(g_cfg_mu);
+  aux_init_locked();
+  g_int_cfg[k][op][kind] = *cfg;
+  return BFP_OK;
+}
+
 bfp_status bfp_launch_load(const char* path) {
   if (!path) return BFP_E_NULL;
   FILE* fp = fopen(path, "r");
@@ -386,6 +460,27 @@ bfp_status bfp_launch_load(const char* path) {
   bfp_status st = BFP_OK;
   while (fgets(line, sizeof line, fp)) {
     if (line[0] == '#' || line[0] == '\n') continue;
+    if (line[0] == 'c' || line[0] == 'i') {  // "chain op1 op2 e m round block bpc" / "int op k kind block bpc"
+      int v[6] = {0};
+      bfp_launch c{1, 256, 0, 1};
+      bfp_status s2 = BFP_E_ARG;
+      if (line[0] == 'c' && sscanf(line, "chain %d %d %d %d %d %d %d", &v[0], &v[1], &v[2], &v[3], &v[4], &c.block,
+                                   &c.blocks_per_cu) == 7) {
+        bfp_format f{(uint8_t)v[2], (uint8_t)v[3], (uint8_t)v[4], 0};
+        if (!format_ok(f) || !registry().chain[f.e][f.m][0][0][0]) continue;
+        s2 = bfp_chain_launch_set(v[0], v[1], f, &c);
+      } else if (line[0] == 'i' && sscanf(line, "int %d %d %d %d %d", &v[0], &v[1], &v[2], &c.block,
+                                          &c.blocks_per_cu) == 5) {
+        if (!int_bits_ok(v[1]) || v[0] < 0 || v[0] > 2) continue;
+        c.words_per_lane = int_registry().words[v[1]][v[0]];
+        s2 = bfp_int_launch_set(v[0], v[1], v[2], &c);
+      }
+      if (s2 != BFP_OK) {
+        st = s2;
+        break;
+      }
+      continue;
+    }
     int op, e, m, r, wpl, block, bpc, unroll = 1;
     const int got = sscanf(line, "%d %d %d %d %d %d %d %d", &op, &e, &m, &r, &wpl, &block, &bpc, &unroll);
     if (got != 7 && got != 8) {  // the unroll column may be absent (one unit per step)
@@ -431,6 +526,27 @@ bfp_status bfp_launch_save(const char* path) {
             fprintf(fp, "%d %d %d %d %d %d %d %d\n", op, e, m, r, c.words_per_lane, c.block,
                     c.blocks_per_cu, c.unroll > 1 ? 2 : 1);
           }
+    aux_init_locked();
+    fprintf(fp, "# chain op1 op2 e m round block blocks_per_cu (op classes: 0 add/sub, 2 mul)\n");
+    for (int e = 0; e <= kMaxE; ++e)
+      for (int m = 0; m <= kMaxM; ++m) {
+        if (!registry().chain[e][m][0][0][0]) continue;
+        for (int o1 = 0; o1 < 2; ++o1)
+          for (int o2 = 0; o2 < 2; ++o2)
+            for (int r = 0; r < 2; ++r) {
+              const bfp_launch& c = g_chain_cfg[e][m][o1][o2][r];
+              fprintf(fp, "chain %d %d %d %d %d %d %d\n", o1 ? BFP_MUL : BFP_ADD, o2 ? BFP_MUL : BFP_ADD, e, m, r,
+                      c.block, c.blocks_per_cu);
+            }
+      }
+    fprintf(fp, "# int op k kind block blocks_per_cu\n");
+    for (int k = 1; k <= kMaxIntBits; ++k)
+      for (int o = 0; o < 3; ++o)
+        for (int kd = 0; kd < 3; ++kd) {
+          if (!int_registry().op[k][o][kd]) continue;
+          const bfp_launch& c = g_int_cfg[k][o][kd];
+          fprintf(fp, "int %d %d %d %d %d\n", o, k, kd, c.block, c.blocks_per_cu);
+        }
   }
   fclose(fp);
   return BFP_OK;

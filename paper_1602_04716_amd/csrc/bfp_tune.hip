@@ -103,6 +103,57 @@ struct DevBuf {
   }
 };
 
+// Time `run` under every block x grid depth (words per lane fixed at wpl),
+// each configuration installed by `set` first: median of `reps` runs, each
+// after a read sweep of the 512 MiB `sweep` buffer; the fastest is left in
+// *best_cfg and *best_us (microseconds).
+template <class Set, class Run>
+bfp_status tune_block_grid(Set set, Run run, int wpl, int reps, hipStream_t s, const DevBuf& sweep,
+                           const DevBuf& sink, bfp_launch* best_cfg, double* best_us) {
+  hipEvent_t e0, e1;
+  if (hipEventCreate(&e0) != hipSuccess) return BFP_E_HIP;
+  if (hipEventCreate(&e1) != hipSuccess) {
+    (void)hipEventDestroy(e0);
+    return BFP_E_HIP;
+  }
+  const int blocks[] = {64, 128, 256, 512};
+  const int bpcs[] = {0, 4, 8};
+  const uint64_t sweep_bytes = 512ull << 20;
+  bfp_status st = BFP_OK;
+  *best_us = 1e30;
+  std::vector<float> ts;
+  for (int blk : blocks) {
+    for (int bpc : bpcs) {
+      const bfp_launch cfg{wpl, blk, bpc, 1};
+      st = set(cfg);
+      if (st != BFP_OK) break;
+      ts.clear();
+      for (int r = 0; r <= reps && st == BFP_OK; ++r) {
+        hipLaunchKernelGGL(k_sweep_read, dim3(4096), dim3(256), 0, s, (const u32x4*)sweep.p, sweep_bytes / 16,
+                           (uint32_t*)sink.p);
+        if (hipEventRecord(e0, s) != hipSuccess) st = BFP_E_HIP;
+        if (st == BFP_OK) st = run();
+        if (st == BFP_OK && hipEventRecord(e1, s) != hipSuccess) st = BFP_E_HIP;
+        if (st == BFP_OK && hipEventSynchronize(e1) != hipSuccess) st = BFP_E_HIP;
+        float ms = 0.f;
+        if (st == BFP_OK && hipEventElapsedTime(&ms, e0, e1) != hipSuccess) st = BFP_E_HIP;
+        if (r > 0) ts.push_back(ms);
+      }
+      if (st != BFP_OK) break;
+      std::nth_element(ts.begin(), ts.begin() + ts.size() / 2, ts.end());
+      const double med = ts[ts.size() / 2] * 1e3;
+      if (med < *best_us) {
+        *best_us = med;
+        *best_cfg = cfg;
+      }
+    }
+    if (st != BFP_OK) break;
+  }
+  (void)hipEventDestroy(e0);
+  (void)hipEventDestroy(e1);
+  return st;
+}
+
 }  // namespace
 }  // namespace bfp
 
@@ -280,5 +331,70 @@ extern "C" bfp_status bfp_autotune(int op, bfp_format f, uint64_t n_probe, int w
   st = bfp_launch_set(op, f, &best_cfg);
   if (best_out) *best_out = best_cfg;
   if (best_us_out) *best_us_out = best;
+  return st;
+}
+
+extern "C" bfp_status bfp_autotune_chain(int op1, int op2, bfp_format f, uint64_t n_probe, int reps, void* stream,
+                                         bfp_launch* best_out, double* best_us_out) {
+  bfp_launch saved;
+  bfp_status st = bfp_chain_launch_get(op1, op2, f, &saved);
+  if (st != BFP_OK) return st;
+  if (n_probe == 0 || n_probe > (1ull << 30) || reps < 1 || reps > 1000) return BFP_E_ARG;
+  hipStream_t s = (hipStream_t)stream;
+  const size_t vec_bytes = bfp_bitslice_bytes(f, n_probe);
+  DevBuf a, b, c, d, sweep, sink;
+  if (hipMalloc(&a.p, vec_bytes) != hipSuccess || hipMalloc(&b.p, vec_bytes) != hipSuccess ||
+      hipMalloc(&c.p, vec_bytes) != hipSuccess || hipMalloc(&d.p, vec_bytes) != hipSuccess ||
+      hipMalloc(&sweep.p, 512ull << 20) != hipSuccess || hipMalloc(&sink.p, 256) != hipSuccess)
+    return BFP_E_NOMEM;
+  hipLaunchKernelGGL(k_fill_random, dim3(2048), dim3(256), 0, s, (uint32_t*)a.p, vec_bytes / 4, 0x1234u);
+  hipLaunchKernelGGL(k_fill_random, dim3(2048), dim3(256), 0, s, (uint32_t*)b.p, vec_bytes / 4, 0x9876u);
+  hipLaunchKernelGGL(k_fill_random, dim3(2048), dim3(256), 0, s, (uint32_t*)c.p, vec_bytes / 4, 0x4321u);
+  hipLaunchKernelGGL(k_fill_random, dim3(2048), dim3(256), 0, s, (uint32_t*)sweep.p, (512ull << 20) / 4, 0x5555u);
+  if (hipGetLastError() != hipSuccess) return BFP_E_HIP;
+  bfp_launch best = saved;
+  double us = 0;
+  st = tune_block_grid([&](const bfp_launch& cfg) { return bfp_chain_launch_set(op1, op2, f, &cfg); },
+                       [&]() { return bfp_chain2(op1, op2, f, a.p, b.p, c.p, d.p, n_probe, stream); }, 1, reps, s,
+                       sweep, sink, &best, &us);
+  if (st != BFP_OK) {
+    (void)bfp_chain_launch_set(op1, op2, f, &saved);
+    return st;
+  }
+  st = bfp_chain_launch_set(op1, op2, f, &best);
+  if (best_out) *best_out = best;
+  if (best_us_out) *best_us_out = us;
+  return st;
+}
+
+extern "C" bfp_status bfp_autotune_int(int op, int k, int kind, uint64_t n_probe, int reps, void* stream,
+                                       bfp_launch* best_out, double* best_us_out) {
+  bfp_launch saved;
+  bfp_status st = bfp_int_launch_get(op, k, kind, &saved);
+  if (st != BFP_OK) return st;
+  if (n_probe == 0 || n_probe > (1ull << 30) || reps < 1 || reps > 1000) return BFP_E_ARG;
+  hipStream_t s = (hipStream_t)stream;
+  const size_t vec_bytes = bfp_int_bitslice_bytes(k, n_probe);
+  DevBuf a, b, c, sweep, sink;
+  if (hipMalloc(&a.p, vec_bytes) != hipSuccess || hipMalloc(&b.p, vec_bytes) != hipSuccess ||
+      hipMalloc(&c.p, vec_bytes) != hipSuccess || hipMalloc(&sweep.p, 512ull << 20) != hipSuccess ||
+      hipMalloc(&sink.p, 256) != hipSuccess)
+    return BFP_E_NOMEM;
+  hipLaunchKernelGGL(k_fill_random, dim3(2048), dim3(256), 0, s, (uint32_t*)a.p, vec_bytes / 4, 0x1234u);
+  hipLaunchKernelGGL(k_fill_random, dim3(2048), dim3(256), 0, s, (uint32_t*)b.p, vec_bytes / 4, 0x9876u);
+  hipLaunchKernelGGL(k_fill_random, dim3(2048), dim3(256), 0, s, (uint32_t*)sweep.p, (512ull << 20) / 4, 0x5555u);
+  if (hipGetLastError() != hipSuccess) return BFP_E_HIP;
+  bfp_launch best = saved;
+  double us = 0;
+  st = tune_block_grid([&](const bfp_launch& cfg) { return bfp_int_launch_set(op, k, kind, &cfg); },
+                       [&]() { return bfp_int_binop(op, k, kind, a.p, b.p, c.p, n_probe, stream); },
+                       saved.words_per_lane, reps, s, sweep, sink, &best, &us);
+  if (st != BFP_OK) {
+    (void)bfp_int_launch_set(op, k, kind, &saved);
+    return st;
+  }
+  st = bfp_int_launch_set(op, k, kind, &best);
+  if (best_out) *best_out = best;
+  if (best_us_out) *best_us_out = us;
   return st;
 }

@@ -189,3 +189,34 @@ def test_one_hip_runtime_per_process():
     import ast
     runtimes = ast.literal_eval(out.stdout.strip().splitlines()[-1])
     assert len(runtimes) == 1, runtimes
+
+
+def test_chain_and_int_launch_tables_round_trip(tmp_path):
+    """Chain and integer launch entries: validation, and save/load of the
+    table with their lines (host only)."""
+    f = bfp.fmt(5, 10)
+    old_c = bfp.bfp_chain_launch_get("mul", "sub", f)
+    old_i = bfp.bfp_int_launch_get("add", 9, "wrap")
+    bfp.bfp_chain_launch_set("mul", "sub", f, 128, 4)
+    bfp.bfp_int_launch_set("add", 9, "wrap", 512, 8)
+    c = bfp.bfp_chain_launch_get("mul", "add", f)          # sub shares add's entry
+    assert (c.block, c.blocks_per_cu, c.words_per_lane) == (128, 4, 1)
+    i = bfp.bfp_int_launch_get("add", 9, "wrap")
+    assert (i.block, i.blocks_per_cu) == (512, 8) and i.words_per_lane == old_i.words_per_lane
+    with pytest.raises(bfp.BfpError):
+        bfp.bfp_chain_launch_set("div", "add", f, 128, 0)  # division is not chained
+    with pytest.raises(bfp.BfpError):
+        bfp.bfp_chain_launch_set("mul", "add", f, 100, 0)
+    with pytest.raises(bfp.BfpError):
+        bfp.bfp_int_launch_set("add", 33, "wrap", 256, 0)
+    path = str(tmp_path / "table.txt")
+    bfp.bfp_launch_save(path)
+    text = open(path).read()
+    assert "chain 2 0 5 10 0 128 4" in text and "int 0 9 0 512 8" in text
+    bfp.bfp_chain_launch_set("mul", "sub", f, old_c.block, old_c.blocks_per_cu)
+    bfp.bfp_int_launch_set("add", 9, "wrap", old_i.block, old_i.blocks_per_cu)
+    bfp.bfp_launch_load(path)
+    assert bfp.bfp_chain_launch_get("mul", "add", f).block == 128
+    assert bfp.bfp_int_launch_get("add", 9, "wrap").blocks_per_cu == 8
+    bfp.bfp_chain_launch_set("mul", "sub", f, old_c.block, old_c.blocks_per_cu)
+    bfp.bfp_int_launch_set("add", 9, "wrap", old_i.block, old_i.blocks_per_cu)

@@ -98,3 +98,38 @@ def test_flush_llc_runs():
     torch.cuda.synchronize()
     with pytest.raises(bfp.BfpError):
         bfp.bfp_flush_llc(100)
+
+
+def test_chain_and_int_autotune_install_and_stay_exact():
+    f = bfp.fmt(5, 10)
+    old = bfp.bfp_chain_launch_get("mul", "add", f)
+    best, us = bfp.bfp_autotune_chain("mul", "add", f, 1 << 20, 2)
+    cur = bfp.bfp_chain_launch_get("mul", "add", f)
+    assert us > 0 and (cur.block, cur.blocks_per_cu) == (best.block, best.blocks_per_cu)
+    n = 100003
+    a, b, c = (inputs.sweep_operands(5, 10, n, s) for s in (1, 2, 3))
+    pa, pb, pc = (bfp.pack(f, torch.from_numpy(x).cuda()) for x in (a, b, c))
+    want = oracle.binop("add", 5, 10, 0, oracle.binop("mul", 5, 10, 0, a, b), c)
+    for blk in (64, 512):
+        for bpc in (0, 8):
+            bfp.bfp_chain_launch_set("mul", "add", f, blk, bpc)
+            pd = bfp.empty_bitslice(f, n)
+            bfp.bfp_chain2("mul", "add", f, pa, pb, pc, pd, n)
+            assert np.array_equal(bfp.unpack(f, pd, n).cpu().numpy().astype(np.uint32), want), (blk, bpc)
+    bfp.bfp_chain_launch_set("mul", "add", f, old.block, old.blocks_per_cu)
+    k = 13
+    oi = bfp.bfp_int_launch_get("mul", k, "sats")
+    best, us = bfp.bfp_autotune_int("mul", k, "sats", 1 << 20, 2)
+    assert us > 0 and best.words_per_lane == oi.words_per_lane
+    rng = np.random.default_rng(5)
+    x = rng.integers(0, 1 << k, n).astype(np.uint16)
+    y = rng.integers(0, 1 << k, n).astype(np.uint16)
+    px, py = bfp.int_pack(k, torch.from_numpy(x).cuda()), bfp.int_pack(k, torch.from_numpy(y).cuda())
+    want = oracle.int_binop("mul", k, "sats", x, y)
+    for blk in (64, 512):
+        for bpc in (0, 8):
+            bfp.bfp_int_launch_set("mul", k, "sats", blk, bpc)
+            pz = bfp.int_empty_bitslice(k, n)
+            bfp.bfp_int_binop("mul", k, "sats", px, py, pz, n)
+            assert np.array_equal(bfp.int_unpack(k, pz, n).cpu().numpy().astype(np.uint32), want), (blk, bpc)
+    bfp.bfp_int_launch_set("mul", k, "sats", oi.block, oi.blocks_per_cu)
