@@ -26,6 +26,8 @@ Also printed in the same JSON line:
                 what the previous one left in the 256 MB last-level cache);
   sweep         the 40-format sweep: add and mul on 2^24 elements per format,
                 tuned launches, each launch timed cold (median of 5);
+  layout_methods pack and unpack with each transpose method (per lane,
+                across lanes) for 1-, 2- and 4-byte containers, cold;
   batched       4096 mixed vectors: one persistent launch vs one launch per
                 vector, the per-vector launches also replayed from a captured
                 graph (skipped with --no-batched);
@@ -86,6 +88,7 @@ def parse():
     ap.add_argument("--no-wide", action="store_true")
     ap.add_argument("--no-small", action="store_true")
     ap.add_argument("--no-sweep", action="store_true")
+    ap.add_argument("--no-layout-methods", action="store_true")
     ap.add_argument("--sweep-n-log2", type=int, default=24)
     ap.add_argument("--div-reps", type=int, default=10)
     ap.add_argument("--serving-requests", type=int, default=20000)
@@ -430,6 +433,45 @@ def bench_sweep(torch, bfp, dev, n_log2, reps=5):
     return out
 
 
+def bench_layout_methods(torch, bfp, dev, n, reps=5):
+    """Pack and unpack with each transpose method (per lane, across lanes)
+    for 1-, 2- and 4-byte containers ((4,3), (5,10), (8,23)) on n elements,
+    each launch timed cold (1 GiB read sweep first), median of `reps`."""
+    import numpy as np
+    s = torch.cuda.current_stream()
+    out = {}
+    for (e, m) in ((4, 3), (5, 10), (8, 23)):
+        f = bfp.fmt(e, m)
+        cb = bfp.bfp_container_bytes(f)
+        B = 1 + e + m
+        x = torch.randint(0, 1 << min(B, 31), (n,), dtype=torch.int64, device=dev).to(bfp.container_dtype(f))
+        bs = bfp.empty_bitslice(f, n, dev)
+        y = torch.empty_like(x)
+        row = {}
+        for meth, name in ((bfp.BFP_TRANSPOSE_LANE, "lane"), (bfp.BFP_TRANSPOSE_XLANE, "xlane")):
+            for d, fn in (("pack", lambda: bfp.bfp_pack(f, x, bs, n, s)), ("unpack", lambda: bfp.bfp_unpack(f, bs, y, n, s))):
+                bfp.bfp_layout_method_set(d, cb, meth)
+                fn()
+                ts = []
+                for _ in range(reps):
+                    bfp.bfp_flush_llc(1 << 30, s)
+                    ev0, ev1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+                    ev0.record(s)
+                    fn()
+                    ev1.record(s)
+                    torch.cuda.synchronize()
+                    ts.append(ev0.elapsed_time(ev1) * 1e3)
+                us = float(np.median(ts))
+                nbytes = n * (cb + B / 8)
+                row["%s_%s_us" % (d, name)] = us
+                row["%s_%s_hbm_frac" % (d, name)] = nbytes / (us * 1e-6) / HBM_PEAK
+        for d in ("pack", "unpack"):
+            bfp.bfp_layout_method_set(d, cb, bfp.BFP_TRANSPOSE_LANE)
+        out["(%d,%d)" % (e, m)] = row
+        del x, y, bs
+    return out
+
+
 def device_kernel(label):
     """Device kernel that a bench label ("unpack(8,7)", "mul(5,10)") launches
     with the bench's configuration (64-element lane words, nearest-even)."""
@@ -708,6 +750,8 @@ def main():
     }
     if not args.no_sweep:
         res["sweep"] = bench_sweep(torch, bfp, dev, args.sweep_n_log2)
+    if not args.no_layout_methods:
+        res["layout_methods"] = bench_layout_methods(torch, bfp, dev, n)
     if not args.no_batched:
         res["batched"] = bench_batched(torch, bfp, dev, args.batched_reps, graphs=not args.batched_no_graph)
     if not args.no_serving:

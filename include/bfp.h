@@ -291,6 +291,27 @@ bfp_status bfp_autotune_chain(int op1, int op2, bfp_format f, uint64_t n_probe, 
 bfp_status bfp_autotune_int(int op, int k, int kind, uint64_t n_probe, int reps, void* stream, bfp_launch* best,
                             double* best_us);
 
+/* Transpose method of bfp_pack / bfp_unpack (direction 0 / 1) for one
+ * container size (1, 2 or 4 bytes; 8-byte containers have the per-lane
+ * method only), both computing the layout of Figure 1:
+ *   BFP_TRANSPOSE_LANE   each lane transposes one 32-element group in its
+ *                        registers (the default);
+ *   BFP_TRANSPOSE_XLANE  each lane holds one element and the 32 lanes of a
+ *                        half-wave transpose their words together (ds_swizzle
+ *                        exchanges), plane rows gathered in LDS.
+ * The get call returns the method or BFP_E_ARG. */
+#define BFP_TRANSPOSE_LANE 0
+#define BFP_TRANSPOSE_XLANE 1
+bfp_status bfp_layout_method_set(int direction, int cbytes, int method);
+int bfp_layout_method_get(int direction, int cbytes);
+
+/* Time pack (direction 0) or unpack (1) of n_probe elements of format f with
+ * each method (median of `reps` cold runs), install the faster for f's
+ * container size and return it in *best_method (and its microseconds in
+ * *best_us; either may be NULL). */
+bfp_status bfp_autotune_layout(int direction, bfp_format f, uint64_t n_probe, int reps, void* stream,
+                               int* best_method, double* best_us);
+
 /* ---- batched persistent launch --------------------------------------------- */
 /* Many vectors of uneven length and mixed formats in one persistent kernel,
  * captured once in a HIP graph.  (Not in the paper, whose operations act on

@@ -117,6 +117,10 @@ _SIGS = {
     "bfp_measure_copy": (ctypes.c_int, [ctypes.c_uint64, ctypes.c_int, ctypes.c_void_p,
                                         ctypes.POINTER(ctypes.c_double)]),
     "bfp_launch_save": (ctypes.c_int, [ctypes.c_char_p]),
+    "bfp_layout_method_set": (ctypes.c_int, [ctypes.c_int, ctypes.c_int, ctypes.c_int]),
+    "bfp_layout_method_get": (ctypes.c_int, [ctypes.c_int, ctypes.c_int]),
+    "bfp_autotune_layout": (ctypes.c_int, [ctypes.c_int, bfp_format, ctypes.c_uint64, ctypes.c_int, ctypes.c_void_p,
+                                           ctypes.POINTER(ctypes.c_int), ctypes.POINTER(ctypes.c_double)]),
     "bfp_chain_launch_get": (ctypes.c_int, [ctypes.c_int, ctypes.c_int, bfp_format, ctypes.POINTER(bfp_launch)]),
     "bfp_chain_launch_set": (ctypes.c_int, [ctypes.c_int, ctypes.c_int, bfp_format, ctypes.POINTER(bfp_launch)]),
     "bfp_int_launch_get": (ctypes.c_int, [ctypes.c_int, ctypes.c_int, ctypes.c_int, ctypes.POINTER(bfp_launch)]),
@@ -361,6 +365,32 @@ def bfp_launch_get(op, f) -> bfp_launch:
 def bfp_launch_set(op, f, words_per_lane: int, block: int, blocks_per_cu: int, unroll: int = 1):
     cfg = bfp_launch(words_per_lane, block, blocks_per_cu, unroll)
     _check(lib().bfp_launch_set(_op(op), f, ctypes.byref(cfg)), "bfp_launch_set")
+
+
+BFP_TRANSPOSE_LANE, BFP_TRANSPOSE_XLANE = 0, 1
+_DIRECTIONS = {"pack": 0, "unpack": 1}
+
+
+def _dir(d) -> int:
+    return _DIRECTIONS[d] if isinstance(d, str) else int(d)
+
+
+def bfp_layout_method_set(direction, cbytes: int, method: int):
+    _check(lib().bfp_layout_method_set(_dir(direction), cbytes, method), "bfp_layout_method_set")
+
+
+def bfp_layout_method_get(direction, cbytes: int) -> int:
+    r = lib().bfp_layout_method_get(_dir(direction), cbytes)
+    _check(r if r < 0 else BFP_OK, "bfp_layout_method_get")
+    return r
+
+
+def bfp_autotune_layout(direction, f, n_probe: int = 1 << 24, reps: int = 5, stream=None):
+    """Returns (best method, median microseconds); installs the best."""
+    m, us = ctypes.c_int(), ctypes.c_double()
+    _check(lib().bfp_autotune_layout(_dir(direction), f, n_probe, reps, _stream(stream), ctypes.byref(m),
+                                     ctypes.byref(us)), "bfp_autotune_layout")
+    return m.value, us.value
 
 
 def bfp_chain_launch_get(op1, op2, f) -> bfp_launch:

@@ -11,6 +11,7 @@
 #include "bfp_int_kernels.hpp"
 #include "bfp_kernels.hpp"
 #include "bfp_layout.hpp"
+#include "bfp_xlane.hpp"
 
 namespace bfp {
 
@@ -147,6 +148,35 @@ hipError_t launch_unpack(const void* src, void* dst, uint64_t n, uint64_t gpad, 
   return hipGetLastError();
 }
 
+template <int C>
+hipError_t launch_pack_x(const void* src, void* dst, uint64_t n, uint64_t gpad, int B, unsigned grid, unsigned block,
+                         hipStream_t s) {
+  const size_t lds = (size_t)(block / 64) * 32 * kXlaneRow * 4;
+  hipLaunchKernelGGL((k_pack_x<C>), dim3(grid), dim3(block), lds, s, static_cast<const uint8_t*>(src),
+                     static_cast<uint32_t*>(dst), n, gpad, B);
+  return hipGetLastError();
+}
+template <int C>
+hipError_t launch_unpack_x(const void* src, void* dst, uint64_t n, uint64_t gpad, int B, unsigned grid,
+                           unsigned block, hipStream_t s) {
+  const size_t lds = (size_t)(block / 64) * 32 * kXlaneRow * 4;
+  hipLaunchKernelGGL((k_unpack_x<C>), dim3(grid), dim3(block), lds, s, static_cast<const uint32_t*>(src),
+                     static_cast<uint8_t*>(dst), n, gpad, B);
+  return hipGetLastError();
+}
+
+// Transpose method of pack [0] and unpack [1] per container size (1, 2, 4
+// bytes): BFP_TRANSPOSE_LANE or BFP_TRANSPOSE_XLANE; 8-byte containers have
+// the per-lane method only.
+int g_layout_method[2][3] = {};
+int cidx(int C) { return C == 1 ? 0 : (C == 2 ? 1 : (C == 4 ? 2 : -1)); }
+int layout_method(int dir, int C) {
+  const int ci = cidx(C);
+  if (ci < 0) return BFP_TRANSPOSE_LANE;
+  std::lock_guard<std::mutex> lk(g_cfg_mu);
+  return g_layout_method[dir][ci];
+}
+
 bfp_status check_op(int op) { return op_valid(op) ? BFP_OK : BFP_E_OP; }
 
 // Ops a two-op chain accepts: add, sub, mul (division is not chained).
@@ -237,6 +267,8 @@ bfp_status pack_impl(int B, const void* std_in, void* bs_out, uint64_t n, void* 
   const int block = 256;
   const unsigned grid = grid_for(gpad, block, 0);
   PackLauncher L = C == 1 ? launch_pack<1> : (C == 2 ? launch_pack<2> : (C == 4 ? launch_pack<4> : launch_pack<8>));
+  if (layout_method(0, C) == BFP_TRANSPOSE_XLANE)
+    L = C == 1 ? launch_pack_x<1> : (C == 2 ? launch_pack_x<2> : launch_pack_x<4>);
   return hip_status(L(std_in, bs_out, n, gpad, B, grid, block, (hipStream_t)stream));
 }
 
@@ -253,6 +285,8 @@ bfp_status unpack_impl(int B, const void* bs_in, void* std_out, uint64_t n, void
   const unsigned grid = grid_for(tiles * 64, block, 0);
   PackLauncher L =
       C == 1 ? launch_unpack<1> : (C == 2 ? launch_unpack<2> : (C == 4 ? launch_unpack<4> : launch_unpack<8>));
+  if (layout_method(1, C) == BFP_TRANSPOSE_XLANE)
+    L = C == 1 ? launch_unpack_x<1> : (C == 2 ? launch_unpack_x<2> : launch_unpack_x<4>);
   return hip_status(L(bs_in, std_out, n, gpad, B, grid, block, (hipStream_t)stream));
 }
 
@@ -452,6 +486,21 @@ bfp_status bfp_int_launch_set(int op, int k, int kind, const bfp_launch* cfg) {
   return BFP_OK;
 }
 
+bfp_status bfp_layout_method_set(int direction, int cbytes, int method) {
+  if (direction != 0 && direction != 1) return BFP_E_ARG;
+  if (method != BFP_TRANSPOSE_LANE && method != BFP_TRANSPOSE_XLANE) return BFP_E_ARG;
+  const int ci = cidx(cbytes);
+  if (ci < 0) return cbytes == 8 && method == BFP_TRANSPOSE_LANE ? BFP_OK : BFP_E_ARG;
+  std::lock_guard<std::mutex> lk(g_cfg_mu);
+  g_layout_method[direction][ci] = method;
+  return BFP_OK;
+}
+
+int bfp_layout_method_get(int direction, int cbytes) {
+  if ((direction != 0 && direction != 1) || (cidx(cbytes) < 0 && cbytes != 8)) return BFP_E_ARG;
+  return layout_method(direction, cbytes);
+}
+
 bfp_status bfp_launch_load(const char* path) {
   if (!path) return BFP_E_NULL;
   FILE* fp = fopen(path, "r");
@@ -460,6 +509,14 @@ bfp_status bfp_launch_load(const char* path) {
   bfp_status st = BFP_OK;
   while (fgets(line, sizeof line, fp)) {
     if (line[0] == '#' || line[0] == '\n') continue;
+    if (line[0] == 'l') {  // "layout direction cbytes method"
+      int dir, cb, meth;
+      if (sscanf(line, "layout %d %d %d", &dir, &cb, &meth) != 3 || bfp_layout_method_set(dir, cb, meth) != BFP_OK) {
+        st = BFP_E_ARG;
+        break;
+      }
+      continue;
+    }
     if (line[0] == 'c' || line[0] == 'i') {  // "chain op1 op2 e m round block bpc" / "int op k kind block bpc"
       int v[6] = {0};
       bfp_launch c{1, 256, 0, 1};
@@ -539,6 +596,9 @@ bfp_status bfp_launch_save(const char* path) {
                       c.block, c.blocks_per_cu);
             }
       }
+    fprintf(fp, "# layout direction(0 pack, 1 unpack) cbytes method(0 per lane, 1 across lanes)\n");
+    for (int dir = 0; dir < 2; ++dir)
+      for (int cb : {1, 2, 4}) fprintf(fp, "layout %d %d %d\n", dir, cb, g_layout_method[dir][cidx(cb)]);
     fprintf(fp, "# int op k kind block blocks_per_cu\n");
     for (int k = 1; k <= kMaxIntBits; ++k)
       for (int o = 0; o < 3; ++o)

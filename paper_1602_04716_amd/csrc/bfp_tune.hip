@@ -103,55 +103,60 @@ struct DevBuf {
   }
 };
 
-// Time `run` under every block x grid depth (words per lane fixed at wpl),
-// each configuration installed by `set` first: median of `reps` runs, each
-// after a read sweep of the 512 MiB `sweep` buffer; the fastest is left in
-// *best_cfg and *best_us (microseconds).
-template <class Set, class Run>
-bfp_status tune_block_grid(Set set, Run run, int wpl, int reps, hipStream_t s, const DevBuf& sweep,
-                           const DevBuf& sink, bfp_launch* best_cfg, double* best_us) {
+// Median microseconds of `reps` runs of `run`, each after a read sweep of
+// the 512 MiB `sweep` buffer (plus one untimed warm-up run).
+template <class Run>
+bfp_status median_cold_us(Run run, int reps, hipStream_t s, const DevBuf& sweep, const DevBuf& sink, double* us) {
   hipEvent_t e0, e1;
   if (hipEventCreate(&e0) != hipSuccess) return BFP_E_HIP;
   if (hipEventCreate(&e1) != hipSuccess) {
     (void)hipEventDestroy(e0);
     return BFP_E_HIP;
   }
-  const int blocks[] = {64, 128, 256, 512};
-  const int bpcs[] = {0, 4, 8};
   const uint64_t sweep_bytes = 512ull << 20;
   bfp_status st = BFP_OK;
-  *best_us = 1e30;
   std::vector<float> ts;
-  for (int blk : blocks) {
-    for (int bpc : bpcs) {
-      const bfp_launch cfg{wpl, blk, bpc, 1};
-      st = set(cfg);
-      if (st != BFP_OK) break;
-      ts.clear();
-      for (int r = 0; r <= reps && st == BFP_OK; ++r) {
-        hipLaunchKernelGGL(k_sweep_read, dim3(4096), dim3(256), 0, s, (const u32x4*)sweep.p, sweep_bytes / 16,
-                           (uint32_t*)sink.p);
-        if (hipEventRecord(e0, s) != hipSuccess) st = BFP_E_HIP;
-        if (st == BFP_OK) st = run();
-        if (st == BFP_OK && hipEventRecord(e1, s) != hipSuccess) st = BFP_E_HIP;
-        if (st == BFP_OK && hipEventSynchronize(e1) != hipSuccess) st = BFP_E_HIP;
-        float ms = 0.f;
-        if (st == BFP_OK && hipEventElapsedTime(&ms, e0, e1) != hipSuccess) st = BFP_E_HIP;
-        if (r > 0) ts.push_back(ms);
-      }
-      if (st != BFP_OK) break;
-      std::nth_element(ts.begin(), ts.begin() + ts.size() / 2, ts.end());
-      const double med = ts[ts.size() / 2] * 1e3;
-      if (med < *best_us) {
-        *best_us = med;
-        *best_cfg = cfg;
-      }
-    }
-    if (st != BFP_OK) break;
+  for (int r = 0; r <= reps && st == BFP_OK; ++r) {
+    hipLaunchKernelGGL(k_sweep_read, dim3(4096), dim3(256), 0, s, (const u32x4*)sweep.p, sweep_bytes / 16,
+                       (uint32_t*)sink.p);
+    if (hipEventRecord(e0, s) != hipSuccess) st = BFP_E_HIP;
+    if (st == BFP_OK) st = run();
+    if (st == BFP_OK && hipEventRecord(e1, s) != hipSuccess) st = BFP_E_HIP;
+    if (st == BFP_OK && hipEventSynchronize(e1) != hipSuccess) st = BFP_E_HIP;
+    float ms = 0.f;
+    if (st == BFP_OK && hipEventElapsedTime(&ms, e0, e1) != hipSuccess) st = BFP_E_HIP;
+    if (r > 0) ts.push_back(ms);  // the first run warms the code path
   }
   (void)hipEventDestroy(e0);
   (void)hipEventDestroy(e1);
-  return st;
+  if (st != BFP_OK) return st;
+  std::nth_element(ts.begin(), ts.begin() + ts.size() / 2, ts.end());
+  *us = ts[ts.size() / 2] * 1e3;
+  return BFP_OK;
+}
+
+// Time `run` under every block x grid depth (words per lane fixed at wpl),
+// each configuration installed by `set` first; the fastest is left in
+// *best_cfg and *best_us.
+template <class Set, class Run>
+bfp_status tune_block_grid(Set set, Run run, int wpl, int reps, hipStream_t s, const DevBuf& sweep,
+                           const DevBuf& sink, bfp_launch* best_cfg, double* best_us) {
+  const int blocks[] = {64, 128, 256, 512};
+  const int bpcs[] = {0, 4, 8};
+  *best_us = 1e30;
+  for (int blk : blocks)
+    for (int bpc : bpcs) {
+      const bfp_launch cfg{wpl, blk, bpc, 1};
+      bfp_status st = set(cfg);
+      double us = 0;
+      if (st == BFP_OK) st = median_cold_us(run, reps, s, sweep, sink, &us);
+      if (st != BFP_OK) return st;
+      if (us < *best_us) {
+        *best_us = us;
+        *best_cfg = cfg;
+      }
+    }
+  return BFP_OK;
 }
 
 }  // namespace
@@ -396,5 +401,50 @@ extern "C" bfp_status bfp_autotune_int(int op, int k, int kind, uint64_t n_probe
   st = bfp_int_launch_set(op, k, kind, &best);
   if (best_out) *best_out = best;
   if (best_us_out) *best_us_out = us;
+  return st;
+}
+
+extern "C" bfp_status bfp_autotune_layout(int direction, bfp_format f, uint64_t n_probe, int reps, void* stream,
+                                          int* best_method, double* best_us_out) {
+  if (direction != 0 && direction != 1) return BFP_E_ARG;
+  if (!bfp_format_supported(f)) return BFP_E_FORMAT;
+  const int cb = (int)bfp_container_bytes(f);
+  const int saved = bfp_layout_method_get(direction, cb);
+  if (saved < 0) return saved;
+  if (n_probe == 0 || n_probe > (1ull << 30) || reps < 1 || reps > 1000) return BFP_E_ARG;
+  hipStream_t s = (hipStream_t)stream;
+  const size_t bs_bytes = bfp_bitslice_bytes(f, n_probe), std_bytes = (size_t)n_probe * cb;
+  DevBuf bs, sd, sweep, sink;
+  if (hipMalloc(&bs.p, bs_bytes) != hipSuccess || hipMalloc(&sd.p, std_bytes + 16) != hipSuccess ||
+      hipMalloc(&sweep.p, 512ull << 20) != hipSuccess || hipMalloc(&sink.p, 256) != hipSuccess)
+    return BFP_E_NOMEM;
+  hipLaunchKernelGGL(k_fill_random, dim3(2048), dim3(256), 0, s, (uint32_t*)sd.p, (std_bytes + 3) / 4, 0x1234u);
+  hipLaunchKernelGGL(k_fill_random, dim3(2048), dim3(256), 0, s, (uint32_t*)sweep.p, (512ull << 20) / 4, 0x5555u);
+  if (hipGetLastError() != hipSuccess) return BFP_E_HIP;
+  bfp_status st = direction == 0 ? BFP_OK : bfp_pack(f, sd.p, bs.p, n_probe, stream);  // valid planes to unpack
+  int best = saved;
+  double best_us = 1e30;
+  const int methods[2] = {BFP_TRANSPOSE_LANE, BFP_TRANSPOSE_XLANE};
+  for (int meth : methods) {
+    if (st != BFP_OK) break;
+    if (cb == 8 && meth != BFP_TRANSPOSE_LANE) continue;
+    st = bfp_layout_method_set(direction, cb, meth);
+    double us = 0;
+    if (st == BFP_OK)
+      st = median_cold_us([&]() { return direction == 0 ? bfp_pack(f, sd.p, bs.p, n_probe, stream)
+                                                        : bfp_unpack(f, bs.p, sd.p, n_probe, stream); },
+                          reps, s, sweep, sink, &us);
+    if (st == BFP_OK && us < best_us) {
+      best_us = us;
+      best = meth;
+    }
+  }
+  if (st != BFP_OK) {
+    (void)bfp_layout_method_set(direction, cb, saved);
+    return st;
+  }
+  st = bfp_layout_method_set(direction, cb, best);
+  if (best_method) *best_method = best;
+  if (best_us_out) *best_us_out = best_us;
   return st;
 }

@@ -220,3 +220,24 @@ def test_chain_and_int_launch_tables_round_trip(tmp_path):
     assert bfp.bfp_int_launch_get("add", 9, "wrap").blocks_per_cu == 8
     bfp.bfp_chain_launch_set("mul", "sub", f, old_c.block, old_c.blocks_per_cu)
     bfp.bfp_int_launch_set("add", 9, "wrap", old_i.block, old_i.blocks_per_cu)
+
+
+def test_layout_method_table(tmp_path):
+    for d in ("pack", "unpack"):
+        for cb in (1, 2, 4, 8):
+            assert bfp.bfp_layout_method_get(d, cb) == bfp.BFP_TRANSPOSE_LANE
+    bfp.bfp_layout_method_set("unpack", 2, bfp.BFP_TRANSPOSE_XLANE)
+    assert bfp.bfp_layout_method_get("unpack", 2) == bfp.BFP_TRANSPOSE_XLANE
+    path = str(tmp_path / "t.txt")
+    bfp.bfp_launch_save(path)
+    assert "layout 1 2 1" in open(path).read()
+    bfp.bfp_layout_method_set("unpack", 2, bfp.BFP_TRANSPOSE_LANE)
+    bfp.bfp_launch_load(path)
+    assert bfp.bfp_layout_method_get("unpack", 2) == bfp.BFP_TRANSPOSE_XLANE
+    bfp.bfp_layout_method_set("unpack", 2, bfp.BFP_TRANSPOSE_LANE)
+    with pytest.raises(bfp.BfpError):
+        bfp.bfp_layout_method_set("pack", 8, bfp.BFP_TRANSPOSE_XLANE)  # 8-byte containers: per lane only
+    with pytest.raises(bfp.BfpError):
+        bfp.bfp_layout_method_set("pack", 3, 0)
+    with pytest.raises(bfp.BfpError):
+        bfp.bfp_layout_method_set(2, 1, 0)

@@ -80,6 +80,34 @@ def test_pack_unpack(e, m):
         assert np.array_equal(_host(back), (x.astype(np.uint64) & mask).astype(dt)), ("unpack", n)
 
 
+@pytest.mark.parametrize("e,m", FORMATS + [(8, 31)])
+def test_pack_unpack_across_lanes(e, m):
+    """The cross-lane transposes (BFP_TRANSPOSE_XLANE) against the oracle's
+    layout, on ragged lengths, tails and padding tiles included; 8-byte
+    containers keep the per-lane method."""
+    f = bfp.fmt(e, m)
+    dt = inputs.container_dtype(e, m) if 1 + e + m <= 32 else np.uint64
+    cb = bfp.bfp_container_bytes(f)
+    rng = np.random.default_rng(e * 1000 + m)
+    if cb == 8:
+        with pytest.raises(bfp.BfpError):
+            bfp.bfp_layout_method_set("pack", cb, bfp.BFP_TRANSPOSE_XLANE)
+        return
+    try:
+        bfp.bfp_layout_method_set("pack", cb, bfp.BFP_TRANSPOSE_XLANE)
+        bfp.bfp_layout_method_set("unpack", cb, bfp.BFP_TRANSPOSE_XLANE)
+        for n in (1, 31, 33, 2047, 2049, 64 * 32 * 5 + 17, NPAR):
+            x = rng.integers(0, np.iinfo(dt).max, n, dtype=np.uint64, endpoint=True).astype(dt)
+            bs = bfp.pack(f, _dev(x))
+            assert np.array_equal(_host(bs), oracle.pack(e, m, x)), ("pack", n)
+            back = bfp.unpack(f, bs, n)
+            mask = (1 << (1 + e + m)) - 1
+            assert np.array_equal(_host(back), (x.astype(np.uint64) & mask).astype(dt)), ("unpack", n)
+    finally:
+        bfp.bfp_layout_method_set("pack", cb, bfp.BFP_TRANSPOSE_LANE)
+        bfp.bfp_layout_method_set("unpack", cb, bfp.BFP_TRANSPOSE_LANE)
+
+
 @pytest.mark.parametrize("e,m", FORMATS)
 def test_binop_bitslice(e, m):
     a, b = _operands(e, m, NPAR, 7 * e + m)
