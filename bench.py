@@ -229,7 +229,7 @@ def bench_div(torch, bfp, dev, n, reps):
         out["(%d,%d)" % (e, m)] = {
             "us": us, "elements_per_s": n / (us * 1e-6), "gates": G, "Tops/s": ops_s / 1e12,
             "valu_frac": ops_s / VALU_PEAK, "GB/s": bytes_s / 1e9, "hbm_frac": bytes_s / HBM_PEAK,
-            "device_kernel": "bfp::k_binop<%d, %d, false, 2, %d>" % (e, m, cfg.words_per_lane),
+            "device_kernel": "bfp::k_binop<%d, %d, false, 2, %d, %d>" % (e, m, cfg.words_per_lane, max(1, cfg.unroll)),
             "block": cfg.block, "blocks_per_cu": cfg.blocks_per_cu}
         del pa, pb, pc
     return out
@@ -483,7 +483,7 @@ def device_kernel(label):
         return "bfp::k_pack<%d>" % C
     if kind == "unpack":
         return "bfp::k_unpack<%d>" % C
-    return "bfp::k_binop<%d, %d, false, %d, 2>" % (e, m, {"add": 0, "sub": 0, "mul": 1, "div": 2}[kind])
+    return "bfp::k_binop<%d, %d, false, %d, 2, 1>" % (e, m, {"add": 0, "sub": 0, "mul": 1, "div": 2}[kind])
 
 
 def committed_traffic(kernel):

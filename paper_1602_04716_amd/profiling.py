@@ -181,13 +181,45 @@ def read_traffic(path: str):
 VALU_PEAK = 256 * 4 * 16 * 2.4e9  # 32-bit lane-ops/s: 256 CU x 4 SIMD x 16 lanes x 2.4 GHz
 
 
-def counter_by_name(db: str, counter: str):
-    """(kernel short name) -> list of per-dispatch values of one counter."""
+def main_grid_durations(db: str):
+    """(kernel short name) -> average duration (us) of its dispatches at its
+    largest grid."""
+    by = collections.defaultdict(list)
+    for name, us, grid in dispatches(db):
+        by[name].append((grid, us))
+    out = {}
+    for name, v in by.items():
+        g = max(x for x, _u in v)
+        sel = [u for x, u in v if x == g]
+        out[name] = sum(sel) / len(sel)
+    return out
+
+
+def _main_grid_rows(db: str):
+    """(kernel short name, counter name, value) of every counter record of
+    each kernel's dispatches at that kernel's largest grid (the bench's main
+    workload; the batch's per-vector launches and the sweep run the same
+    kernels on smaller grids)."""
     c = sqlite3.connect(db).cursor()
+    cols = [r[1] for r in c.execute("pragma table_info(counters_collection)")]
+    if "grid_size" in cols:
+        rows = list(c.execute("select kernel_name, counter_name, value, grid_size from counters_collection"))
+    else:
+        rows = [(a, b, v, 0) for (a, b, v) in c.execute("select kernel_name, counter_name, value "
+                                                          "from counters_collection")]
+    top = collections.defaultdict(int)
+    for name, _cn, _v, g in rows:
+        top[short_name(name)] = max(top[short_name(name)], g or 0)
+    return [(short_name(n), cn, v) for (n, cn, v, g) in rows if (g or 0) == top[short_name(n)]]
+
+
+def counter_by_name(db: str, counter: str):
+    """(kernel short name) -> list of per-dispatch values of one counter, at
+    each kernel's largest grid."""
     d = collections.defaultdict(list)
-    for name, cname, val in c.execute("select kernel_name, counter_name, value from counters_collection"):
+    for name, cname, val in _main_grid_rows(db):
         if cname == counter:
-            d[short_name(name)].append(val)
+            d[name].append(val)
     return d
 
 
@@ -212,7 +244,7 @@ def valu_summary(trace_db, pmc_db, n, out, commands):
     to their gate counts: instructions issued per 32 elements against gates
     per 32 elements, and the VALU utilisation the instruction count implies
     at the kernel-trace duration."""
-    stats = {k: avg for (k, calls, avg, tot, pct) in trace_stats(trace_db)}
+    stats = main_grid_durations(trace_db)
     insts = counter_by_name(pmc_db, "SQ_INSTS_VALU")
     lines = ["# rocprofv3 VALU summary: %s" % os.path.basename(out), "",
              "Kernel sources hash: `%s`" % source_hash(), "",
@@ -246,18 +278,17 @@ def sq_summary(trace_db, pmc_db, kernels, out, commands):
     fraction of wave lifetime spent waiting on issued instructions
     (SQ_WAIT_INST_ANY / SQ_WAVE_CYCLES) and the mean number of resident waves
     (SQ_WAVE_CYCLES / SQ_BUSY_CYCLES)."""
-    stats = {k: avg for (k, calls, avg, tot, pct) in trace_stats(trace_db)}
-    c = sqlite3.connect(pmc_db).cursor()
+    stats = main_grid_durations(trace_db)
     vals = collections.defaultdict(lambda: collections.defaultdict(list))
-    for name, cname, val in c.execute("select kernel_name, counter_name, value from counters_collection"):
-        vals[short_name(name)][cname].append(val)
+    for name, cname, val in _main_grid_rows(pmc_db):
+        vals[name][cname].append(val)
     lines = ["# rocprofv3 SQ counters: %s" % os.path.basename(out), "",
              "Kernel sources hash: `%s`" % source_hash(), "",
              "Commands (run from the repository root on one MI355X):", ""]
     for k, v in commands.items():
         lines.append("- %s: `%s`" % (k, v))
     names = sorted({cn for k in kernels for cn in vals.get(k, {})})
-    lines += ["", "Per-dispatch averages (counters summed over the device):", "",
+    lines += ["", "Per-dispatch averages at each kernel's largest grid (counters summed over the device):", "",
               "| kernel | dispatches | " + " | ".join(names) + " | wait / wave cycles | waves resident | trace avg us |",
               "|---|---|" + "---|" * len(names) + "---|---|---|"]
     for k in kernels:
