@@ -1,12 +1,14 @@
 """Autotune bfp_binop for every compiled format and record the format sweep.
 
-    python -m paper_1602_04716_amd.autotune [--n-log2 24] [--reps 7] [--out tuning/gfx950.txt]
+    python -m paper_1602_04716_amd.autotune [--n-log2 26] [--reps 7] [--out tuning/gfx950.txt]
 
 For each format of the sweep (e in {3,4,5,6,8} x m in {1,2,3,5,7,10,15,23})
 and the four wide formats (one-word kernels only),
 each op class (add, mul, div) and each rounding mode, ``bfp_autotune`` times the
 launch variants (words per lane, units per step, block, grid depth) on a
-2^24-element probe with the last-level cache swept clean
+2^26-element probe with the last-level cache swept clean (at 2^24 elements a
+single launch of a light format is a few microseconds, close to the dispatch
+time, and the candidates differ by less than the noise)
 before every run and installs the fastest; the table is saved for
 ``bfp.lib()`` to load.  The printed JSON lines are the format-sweep
 measurement: elements/s, achieved HBM GB/s (3B/8 bytes per element) and
@@ -28,7 +30,7 @@ HBM_PEAK = 8.0e12
 VALU_PEAK = 256 * 4 * 16 * 2.4e9
 
 
-def tune(formats, ops=("add", "mul", "div"), modes=(0, 1), n=1 << 24, reps=7, mask=7, log=print):
+def tune(formats, ops=("add", "mul", "div"), modes=(0, 1), n=1 << 26, reps=7, mask=7, log=print):
     out = []
     for (e, m) in formats:
         for op in ops:
@@ -75,7 +77,7 @@ def tune_ints(ks=range(1, 33), n=1 << 24, reps=5, log=print):
 
 def main(argv=None):
     ap = argparse.ArgumentParser()
-    ap.add_argument("--n-log2", type=int, default=24)
+    ap.add_argument("--n-log2", type=int, default=26)
     ap.add_argument("--reps", type=int, default=7)
     ap.add_argument("--out", default=bfp.TUNE_TABLE)
     ap.add_argument("--formats", default="", help="comma list like 5:10,8:7; default all 44")

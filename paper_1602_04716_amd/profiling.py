@@ -100,8 +100,14 @@ def cold_average(db: str, kernel: str):
             "other_dispatches": len(other), "other_avg_us": avg(other)}
 
 
-def counter_per_dispatch(db: str):
-    """(kernel short name) -> list of per-dispatch values (KiB)."""
+def counter_per_dispatch(db: str, main_grid_only: bool = False):
+    """(kernel name) -> list of per-dispatch values (KiB); with
+    `main_grid_only`, only each kernel's dispatches at its largest grid."""
+    if main_grid_only:
+        d = collections.defaultdict(list)
+        for name, _cn, val in _main_grid_rows(db, short=False):
+            d[name].append(val)
+        return d
     c = sqlite3.connect(db).cursor()
     d = collections.defaultdict(list)
     for name, val in c.execute("select kernel_name, value from counters_collection"):
@@ -118,10 +124,12 @@ def _calib(d):
 
 def summarize(trace_db, fetch_db, write_db, kernel, out, commands):
     stats = trace_stats(trace_db)
-    fetch = counter_per_dispatch(fetch_db)
-    write = counter_per_dispatch(write_db)
-    f_fac = (CALIB_BYTES / 1024) / _calib(fetch)
-    w_fac = (CALIB_BYTES / 1024) / _calib(write)
+    # The calibration copy is the first dispatch of its kernel, whatever its
+    # grid; every other kernel counts its dispatches at its largest grid.
+    f_fac = (CALIB_BYTES / 1024) / _calib(counter_per_dispatch(fetch_db))
+    w_fac = (CALIB_BYTES / 1024) / _calib(counter_per_dispatch(write_db))
+    fetch = counter_per_dispatch(fetch_db, main_grid_only=True)
+    write = counter_per_dispatch(write_db, main_grid_only=True)
     lines = ["# rocprofv3 summary: %s" % os.path.basename(out), "",
              "Kernel sources hash: `%s`" % source_hash(), "",
              "Commands (run from the repository root on one MI355X):", ""]
@@ -142,7 +150,7 @@ def summarize(trace_db, fetch_db, write_db, kernel, out, commands):
     lines += ["", "## HBM bytes per dispatch (FETCH_SIZE, WRITE_SIZE)", "",
               "Calibration: the int32->float32 copy of 2^26 elements reads and writes 262144 KiB; its "
               "FETCH_SIZE reads %.1f KiB and WRITE_SIZE %.1f KiB, so the factors are %.4f (fetch) and "
-              "%.4f (write)." % (_calib(fetch), _calib(write), f_fac, w_fac), "",
+              "%.4f (write)." % ((CALIB_BYTES / 1024) / f_fac, (CALIB_BYTES / 1024) / w_fac, f_fac, w_fac), "",
               "| kernel | dispatches | FETCH KiB (raw) | WRITE KiB (raw) | HBM MB (scaled) |",
               "|---|---|---|---|---|"]
     chosen = None
@@ -181,6 +189,14 @@ def read_traffic(path: str):
 VALU_PEAK = 256 * 4 * 16 * 2.4e9  # 32-bit lane-ops/s: 256 CU x 4 SIMD x 16 lanes x 2.4 GHz
 
 
+def main_grids(db: str):
+    """(kernel short name) -> its largest grid size in a kernel trace."""
+    top = {}
+    for name, _us, grid in dispatches(db):
+        top[name] = max(top.get(name, 0), grid or 0)
+    return top
+
+
 def main_grid_durations(db: str):
     """(kernel short name) -> average duration (us) of its dispatches at its
     largest grid."""
@@ -195,11 +211,25 @@ def main_grid_durations(db: str):
     return out
 
 
-def _main_grid_rows(db: str):
+def counter_grids(db: str):
+    """(kernel short name) -> its largest grid size among counter records
+    (empty if this rocprofv3 version does not record grid sizes)."""
+    c = sqlite3.connect(db).cursor()
+    cols = [r[1] for r in c.execute("pragma table_info(counters_collection)")]
+    if "grid_size" not in cols:
+        return {}
+    top = {}
+    for name, g in c.execute("select kernel_name, grid_size from counters_collection"):
+        k = short_name(name)
+        top[k] = max(top.get(k, 0), g or 0)
+    return top
+
+
+def _main_grid_rows(db: str, short: bool = True):
     """(kernel short name, counter name, value) of every counter record of
     each kernel's dispatches at that kernel's largest grid (the bench's main
     workload; the batch's per-vector launches and the sweep run the same
-    kernels on smaller grids)."""
+    kernels on smaller grids).  `short=False` keeps the full kernel names."""
     c = sqlite3.connect(db).cursor()
     cols = [r[1] for r in c.execute("pragma table_info(counters_collection)")]
     if "grid_size" in cols:
@@ -210,7 +240,8 @@ def _main_grid_rows(db: str):
     top = collections.defaultdict(int)
     for name, _cn, _v, g in rows:
         top[short_name(name)] = max(top[short_name(name)], g or 0)
-    return [(short_name(n), cn, v) for (n, cn, v, g) in rows if (g or 0) == top[short_name(n)]]
+    return [(short_name(n) if short else n, cn, v) for (n, cn, v, g) in rows
+            if (g or 0) == top[short_name(n)]]
 
 
 def counter_by_name(db: str, counter: str):
@@ -246,6 +277,10 @@ def valu_summary(trace_db, pmc_db, n, out, commands):
     at the kernel-trace duration."""
     stats = main_grid_durations(trace_db)
     insts = counter_by_name(pmc_db, "SQ_INSTS_VALU")
+    # Only kernels whose counted launches ran the n-element workload: a
+    # kernel that the counter pass launched on a smaller grid than the trace
+    # (the format sweep is skipped there) would be divided by the wrong n.
+    tgrid, cgrid = main_grids(trace_db), counter_grids(pmc_db)
     lines = ["# rocprofv3 VALU summary: %s" % os.path.basename(out), "",
              "Kernel sources hash: `%s`" % source_hash(), "",
              "Commands (run from the repository root on one MI355X):", ""]
@@ -260,6 +295,8 @@ def valu_summary(trace_db, pmc_db, n, out, commands):
     for name in sorted(insts):
         g = _gates(name)
         if g is None or name not in stats:
+            continue
+        if cgrid and cgrid.get(name) != tgrid.get(name):
             continue
         vi = sum(insts[name]) / len(insts[name])
         per32 = vi * 64 / groups
