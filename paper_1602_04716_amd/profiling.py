@@ -309,12 +309,13 @@ def valu_summary(trace_db, pmc_db, n, out, commands):
         fp.write("\n".join(lines) + "\n")
 
 
-def sq_summary(trace_db, pmc_db, kernels, out, commands):
+def sq_summary(trace_db, pmc_db, kernels, out, commands, cycle_unit=None, clock_hz=2.4e9):
     """Per-dispatch averages of the SQ counters of one --pmc pass for the
-    chosen kernels, with derived figures: VMEM instructions issued, the
-    fraction of wave lifetime spent waiting on issued instructions
-    (SQ_WAIT_INST_ANY / SQ_WAVE_CYCLES) and the mean number of resident waves
-    (SQ_WAVE_CYCLES / SQ_BUSY_CYCLES)."""
+    chosen kernels, with derived figures: each wait counter (SQ_WAIT_ANY,
+    SQ_WAIT_INST_ANY) and SQ_ACTIVE_INST_ANY as a fraction of SQ_WAVE_CYCLES,
+    the mean number of resident waves (SQ_WAVE_CYCLES / SQ_BUSY_CYCLES), and,
+    when `cycle_unit` (shader cycles per SQ_WAVE_CYCLES count) is given, the
+    mean lifetime of one wave in microseconds at `clock_hz`."""
     stats = main_grid_durations(trace_db)
     vals = collections.defaultdict(lambda: collections.defaultdict(list))
     for name, cname, val in _main_grid_rows(pmc_db):
@@ -325,19 +326,30 @@ def sq_summary(trace_db, pmc_db, kernels, out, commands):
     for k, v in commands.items():
         lines.append("- %s: `%s`" % (k, v))
     names = sorted({cn for k in kernels for cn in vals.get(k, {})})
-    lines += ["", "Per-dispatch averages at each kernel's largest grid (counters summed over the device):", "",
-              "| kernel | dispatches | " + " | ".join(names) + " | wait / wave cycles | waves resident | trace avg us |",
-              "|---|---|" + "---|" * len(names) + "---|---|---|"]
+    fracs = [c for c in ("SQ_WAIT_ANY", "SQ_WAIT_INST_ANY", "SQ_ACTIVE_INST_ANY") if c in names]
+    derived = ["%s / WAVE_CYCLES" % c[3:] for c in fracs] + ["waves resident"]
+    if cycle_unit:
+        derived.append("wave life us")
+    lines += ["", "Per-dispatch averages at each kernel's largest grid (counters summed over the device):", ""]
+    if cycle_unit:
+        lines += ["Wave life = SQ_WAVE_CYCLES / SQ_WAVES x %g shader cycles per count / %.2f GHz." %
+                  (cycle_unit, clock_hz / 1e9), ""]
+    lines += ["| kernel | dispatches | " + " | ".join(names) + " | " + " | ".join(derived) + " | trace avg us |",
+              "|---|---|" + "---|" * len(names) + "---|" * len(derived) + "---|"]
     for k in kernels:
         if k not in vals:
             continue
         d = vals[k]
         avg = {cn: sum(v) / len(v) for cn, v in d.items()}
         nd = max(len(v) for v in d.values())
-        wait = avg.get("SQ_WAIT_INST_ANY", 0) / avg["SQ_WAVE_CYCLES"] if avg.get("SQ_WAVE_CYCLES") else float("nan")
-        res = avg["SQ_WAVE_CYCLES"] / avg["SQ_BUSY_CYCLES"] if avg.get("SQ_BUSY_CYCLES") else float("nan")
+        wc = avg.get("SQ_WAVE_CYCLES")
+        row = ["%.2f" % (avg[c] / wc) if wc else "nan" for c in fracs]
+        row.append("%.1f" % (wc / avg["SQ_BUSY_CYCLES"]) if wc and avg.get("SQ_BUSY_CYCLES") else "nan")
+        if cycle_unit:
+            row.append("%.2f" % (wc / avg["SQ_WAVES"] * cycle_unit / clock_hz * 1e6)
+                       if wc and avg.get("SQ_WAVES") else "nan")
         lines.append("| `%s` | %d | " % (k, nd) + " | ".join("%.4g" % avg.get(cn, float("nan")) for cn in names)
-                     + " | %.2f | %.1f | %.2f |" % (wait, res, stats.get(k, float("nan"))))
+                     + " | " + " | ".join(row) + " | %.2f |" % stats.get(k, float("nan")))
     with open(out + ".md", "w") as fp:
         fp.write("\n".join(lines) + "\n")
 
@@ -354,8 +366,11 @@ def main(argv=None):
         ap.add_argument("--out", required=True)
         ap.add_argument("--command-trace", default="")
         ap.add_argument("--command-pmc", default="")
+        ap.add_argument("--cycle-unit", type=float, default=None,
+                        help="shader cycles per SQ_WAVE_CYCLES count (measured, e.g. with a one-wave spin kernel)")
         a = ap.parse_args(argv[1:])
-        sq_summary(a.trace, a.pmc, a.kernel, a.out, {"trace": a.command_trace, "SQ counters": a.command_pmc})
+        sq_summary(a.trace, a.pmc, a.kernel, a.out, {"trace": a.command_trace, "SQ counters": a.command_pmc},
+                   cycle_unit=a.cycle_unit)
         return
     if argv and argv[0] == "valu":
         ap = argparse.ArgumentParser()

@@ -58,6 +58,21 @@ def test_sizing():
     assert bfp.bfp_bitslice_bytes(bfp.fmt(7, 3), 10) == 0  # not compiled
 
 
+def test_oracle_layout_follows_the_library_stride():
+    """The oracle lays planes out at the library's documented stride, so the
+    two sides are compared word for word: every n up to 2^17 + 2048, the
+    non-monotonic window around a skewed stride (65,000 elements take 2,304
+    words, 66,000 take 2,112), and large powers of two with their
+    neighbours."""
+    import oracle
+    ns = list(range(0, (1 << 17) + 2048, 7)) + [65000, 66000, 65536, 65535, 65537]
+    ns += [(1 << k) + d for k in range(17, 34) for d in (-1, 0, 1, 4096)]
+    for n in ns:
+        n = max(n, 1)
+        assert oracle.plane_stride_words(n) == bfp.bfp_plane_stride_words(n), n
+    assert oracle.plane_stride_words(65000) == 2304 and oracle.plane_stride_words(66000) == 2112
+
+
 def test_wide_formats_sizing_and_table():
     for (e, m), C in (((8, 31), 8), ((11, 20), 4), ((11, 40), 8), ((11, 52), 8)):
         f = bfp.fmt(e, m)

@@ -134,3 +134,25 @@ def test_valu_rows_only_for_kernels_counted_at_the_traced_grid(tmp_path, monkeyp
     # 1e7 wave instructions x 64 lanes over n/32 groups = 305 lane-instr per 32 elements.
     row = [l for l in text.splitlines() if "k_binop<5, 10" in l][0]
     assert "| 305 | 404 |" in row
+
+
+def test_sq_summary_fractions_and_wave_life(tmp_path, monkeypatch):
+    tdb, pdb = str(tmp_path / "t.db"), str(tmp_path / "p.db")
+    k = "void bfp::k_binop_std<5, 2, false, 0>(Args)"
+    _trace_db(tdb, [(k, 3400, 2048), (k, 3300, 2048)])
+    rows = []
+    for _ in range(2):
+        rows += [(k, "SQ_WAVES", 32.0, 2048), (k, "SQ_WAVE_CYCLES", 57600.0, 2048),
+                 (k, "SQ_BUSY_CYCLES", 57600.0, 2048), (k, "SQ_WAIT_ANY", 28800.0, 2048),
+                 (k, "SQ_WAIT_INST_ANY", 576.0, 2048), (k, "SQ_ACTIVE_INST_ANY", 14400.0, 2048)]
+    rows.append((k, "SQ_WAVES", 1.0, 64))  # a smaller launch: not averaged in
+    _counter_db(pdb, rows)
+    monkeypatch.setattr(P, "source_hash", lambda: "abc123")
+    out = str(tmp_path / "sq")
+    P.sq_summary(tdb, pdb, ["bfp::k_binop_std<5, 2, false, 0>"], out, {"pmc": "cmd"}, cycle_unit=4)
+    text = open(out + ".md").read()
+    row = [l for l in text.splitlines() if "k_binop_std" in l][0].split("|")
+    cells = [c.strip() for c in row[1:-1]]
+    # columns: kernel, dispatches, 6 counters (sorted), 3 fractions, resident, life, trace us
+    assert cells[1] == "2"
+    assert cells[8:] == ["0.50", "0.01", "0.25", "1.0", "3.00", "3.35"]
