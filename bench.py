@@ -78,6 +78,9 @@ def parse():
     ap.add_argument("--calibrate-copy", action="store_true",
                     help="also run one int32->float32 conversion of 2^26 elements (256 MiB read, 256 MiB "
                          "written) so hardware byte counters can be scaled against a kernel of known traffic")
+    ap.add_argument("--calibrate-cycles", action="store_true",
+                    help="also run the one-wave bfp_wave_clock kernel (400,000 dependent FMAs) so per-wave "
+                         "cycle counters can be set against its traced duration")
     ap.add_argument("--batched-reps", type=int, default=10)
     ap.add_argument("--batched-no-graph", action="store_true",
                     help="time the batch's kernels launched directly only (no graph replays), e.g. under counters")
@@ -583,6 +586,9 @@ def main():
         dst.copy_(src)
         torch.cuda.synchronize()
         del src, dst
+    if args.calibrate_cycles:
+        bfp.bfp_wave_clock(400000, stream)
+        torch.cuda.synchronize()
 
     # one step = for each format: pack a, pack b, add, sub, mul, unpack x3.
     # Launches of one kernel that follow each other form a group bracketed by

@@ -263,6 +263,15 @@ bfp_status bfp_measure_copy(uint64_t bytes, int reps, void* stream, double* gbps
  * cache: the "cold" measurements use it between timed launches. */
 bfp_status bfp_flush_llc(uint64_t bytes, void* stream);
 
+/* Enqueue one kernel of a single wave (64 threads) that runs a dependent
+ * chain of `iters` fused multiply-adds (1 <= iters <= 2^26) into a 256-byte
+ * buffer the library keeps per device.  The kernel lasts as long as its one
+ * wave, so its traced duration times the shader clock, set against the
+ * profiler's per-wave cycle counter for the same dispatch, gives the
+ * counter's unit; the profile summaries use it to turn wave-cycle counts
+ * into time.  Returns BFP_E_ARG for `iters` out of range. */
+bfp_status bfp_wave_clock(int iters, void* stream);
+
 
 /* Gate count of one circuit instance (one group of 32 elements per word),
  * constants folded: the cost model of Table 1.  Returns -1 if the format

@@ -135,6 +135,7 @@ _SIGS = {
                                        ctypes.POINTER(ctypes.c_double), ctypes.POINTER(ctypes.c_int),
                                        ctypes.POINTER(ctypes.c_int)]),
     "bfp_flush_llc": (ctypes.c_int, [ctypes.c_uint64, ctypes.c_void_p]),
+    "bfp_wave_clock": (ctypes.c_int, [ctypes.c_int, ctypes.c_void_p]),
     "bfp_gate_count": (ctypes.c_long, [ctypes.c_int, bfp_format]),
     "bfp_autotune": (ctypes.c_int, [ctypes.c_int, bfp_format, ctypes.c_uint64, ctypes.c_int, ctypes.c_int,
                                     ctypes.c_void_p, ctypes.POINTER(bfp_launch), ctypes.POINTER(ctypes.c_double)]),
@@ -449,6 +450,12 @@ def bfp_measure_hbm(nbytes: int, mode: str, reps: int = 10, stream=None) -> dict
 
 def bfp_flush_llc(nbytes: int = 1 << 30, stream=None):
     _check(lib().bfp_flush_llc(nbytes, _stream(stream)), "bfp_flush_llc")
+
+
+def bfp_wave_clock(iters: int = 400000, stream=None):
+    """Enqueue the one-wave calibration kernel (a dependent chain of `iters`
+    fused multiply-adds) on `stream`."""
+    _check(lib().bfp_wave_clock(iters, _stream(stream)), "bfp_wave_clock")
 
 
 def bfp_launch_load(path: str):

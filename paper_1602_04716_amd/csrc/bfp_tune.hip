@@ -251,6 +251,29 @@ extern "C" bfp_status bfp_flush_llc(uint64_t bytes, void* stream) {
   return hipGetLastError() == hipSuccess ? BFP_OK : BFP_E_HIP;
 }
 
+// One wave running a dependent chain of fused multiply-adds: the kernel's
+// duration is that wave's lifetime.
+__global__ void __launch_bounds__(64) k_wave_clock(float* out, int iters) {
+  float x = (float)threadIdx.x;
+  for (int i = 0; i < iters; ++i) x = __builtin_fmaf(x, 0.999f, 0.001f);
+  out[threadIdx.x] = x;
+}
+
+extern "C" bfp_status bfp_wave_clock(int iters, void* stream) {
+  static std::mutex mu;
+  static void* buf[64] = {};
+  if (iters < 1 || iters > (1 << 26)) return BFP_E_ARG;
+  int dev = 0;
+  if (hipGetDevice(&dev) != hipSuccess || dev < 0 || dev >= 64) return BFP_E_NODEV;
+  std::lock_guard<std::mutex> lk(mu);
+  if (!buf[dev] && hipMalloc(&buf[dev], 256) != hipSuccess) {
+    buf[dev] = nullptr;
+    return BFP_E_NOMEM;
+  }
+  hipLaunchKernelGGL(k_wave_clock, dim3(1), dim3(64), 0, (hipStream_t)stream, static_cast<float*>(buf[dev]), iters);
+  return hipGetLastError() == hipSuccess ? BFP_OK : BFP_E_HIP;
+}
+
 extern "C" bfp_status bfp_autotune(int op, bfp_format f, uint64_t n_probe, int words_per_lane_mask, int reps,
                                    void* stream, bfp_launch* best_out, double* best_us_out) {
   if (!op_valid(op)) return BFP_E_OP;

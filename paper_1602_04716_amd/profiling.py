@@ -309,17 +309,44 @@ def valu_summary(trace_db, pmc_db, n, out, commands):
         fp.write("\n".join(lines) + "\n")
 
 
-def sq_summary(trace_db, pmc_db, kernels, out, commands, cycle_unit=None, clock_hz=2.4e9):
+CLOCK_KERNEL = "k_wave_clock"  # one-wave calibration kernel (bfp_wave_clock)
+
+
+def wave_cycle_unit(trace_db, pmc_db, clock_hz=2.4e9):
+    """Shader cycles per count of SQ_WAVE_CYCLES, from the one-wave
+    calibration kernel: its traced duration at `clock_hz` over its counter
+    value.  Returns (unit, measured ratio, dispatches) or None when either
+    database lacks the kernel.  The unit is the ratio rounded to the nearest
+    power of two when within 5% of it (the counter counts whole cycles or
+    groups of cycles), else the ratio itself."""
+    us = [u for name, u, _g in dispatches(trace_db) if CLOCK_KERNEL in name]
+    wc = [v for name, cn, v in _main_grid_rows(pmc_db) if CLOCK_KERNEL in name and cn == "SQ_WAVE_CYCLES"]
+    if not us or not wc:
+        return None
+    ratio = (sum(us) / len(us)) * 1e-6 * clock_hz / (sum(wc) / len(wc))
+    unit = ratio
+    for p2 in (1, 2, 4, 8, 16):
+        if abs(ratio / p2 - 1) < 0.05:
+            unit = float(p2)
+    return unit, ratio, len(wc)
+
+
+def sq_summary(trace_db, pmc_db, kernels, out, commands, cycle_unit=None, clock_hz=2.4e9, cus=256):
     """Per-dispatch averages of the SQ counters of one --pmc pass for the
-    chosen kernels, with derived figures: each wait counter (SQ_WAIT_ANY,
-    SQ_WAIT_INST_ANY) and SQ_ACTIVE_INST_ANY as a fraction of SQ_WAVE_CYCLES,
-    the mean number of resident waves (SQ_WAVE_CYCLES / SQ_BUSY_CYCLES), and,
-    when `cycle_unit` (shader cycles per SQ_WAVE_CYCLES count) is given, the
-    mean lifetime of one wave in microseconds at `clock_hz`."""
+    chosen kernels, with derived figures: each wave-state counter
+    (SQ_WAIT_ANY, SQ_WAIT_INST_ANY, SQ_ACTIVE_INST_ANY) as a fraction of
+    SQ_WAVE_CYCLES, and, when `cycle_unit` (shader cycles per count of those
+    counters) is given, the mean lifetime of one wave and the mean number of
+    waves resident per CU over the kernel's traced duration at `clock_hz`."""
     stats = main_grid_durations(trace_db)
     vals = collections.defaultdict(lambda: collections.defaultdict(list))
     for name, cname, val in _main_grid_rows(pmc_db):
         vals[name][cname].append(val)
+    calib = None
+    if cycle_unit is None:
+        calib = wave_cycle_unit(trace_db, pmc_db, clock_hz)
+        if calib:
+            cycle_unit = calib[0]
     lines = ["# rocprofv3 SQ counters: %s" % os.path.basename(out), "",
              "Kernel sources hash: `%s`" % source_hash(), "",
              "Commands (run from the repository root on one MI355X):", ""]
@@ -327,13 +354,19 @@ def sq_summary(trace_db, pmc_db, kernels, out, commands, cycle_unit=None, clock_
         lines.append("- %s: `%s`" % (k, v))
     names = sorted({cn for k in kernels for cn in vals.get(k, {})})
     fracs = [c for c in ("SQ_WAIT_ANY", "SQ_WAIT_INST_ANY", "SQ_ACTIVE_INST_ANY") if c in names]
-    derived = ["%s / WAVE_CYCLES" % c[3:] for c in fracs] + ["waves resident"]
+    derived = ["%s / WAVE_CYCLES" % c[3:] for c in fracs]
     if cycle_unit:
-        derived.append("wave life us")
+        derived += ["wave life us", "waves per CU"]
     lines += ["", "Per-dispatch averages at each kernel's largest grid (counters summed over the device):", ""]
+    if calib:
+        lines += ["Counter unit: the one-wave `%s` kernel (%d counted dispatches) lasts %.3f x its "
+                  "SQ_WAVE_CYCLES count in %.2f GHz cycles, so one count is %g shader cycles."
+                  % (CLOCK_KERNEL, calib[2], calib[1], clock_hz / 1e9, calib[0]), ""]
     if cycle_unit:
-        lines += ["Wave life = SQ_WAVE_CYCLES / SQ_WAVES x %g shader cycles per count / %.2f GHz." %
-                  (cycle_unit, clock_hz / 1e9), ""]
+        lines += ["SQ_WAVE_CYCLES and the wave-state counters count units of %g shader cycles. Wave life = "
+                  "SQ_WAVE_CYCLES / SQ_WAVES x %g / %.2f GHz; waves per CU = SQ_WAVE_CYCLES x %g / (trace avg "
+                  "x %.2f GHz) / %d CUs." % (cycle_unit, cycle_unit, clock_hz / 1e9, cycle_unit, clock_hz / 1e9,
+                                             cus), ""]
     lines += ["| kernel | dispatches | " + " | ".join(names) + " | " + " | ".join(derived) + " | trace avg us |",
               "|---|---|" + "---|" * len(names) + "---|" * len(derived) + "---|"]
     for k in kernels:
@@ -343,13 +376,14 @@ def sq_summary(trace_db, pmc_db, kernels, out, commands, cycle_unit=None, clock_
         avg = {cn: sum(v) / len(v) for cn, v in d.items()}
         nd = max(len(v) for v in d.values())
         wc = avg.get("SQ_WAVE_CYCLES")
+        us = stats.get(k, float("nan"))
         row = ["%.2f" % (avg[c] / wc) if wc else "nan" for c in fracs]
-        row.append("%.1f" % (wc / avg["SQ_BUSY_CYCLES"]) if wc and avg.get("SQ_BUSY_CYCLES") else "nan")
         if cycle_unit:
             row.append("%.2f" % (wc / avg["SQ_WAVES"] * cycle_unit / clock_hz * 1e6)
                        if wc and avg.get("SQ_WAVES") else "nan")
+            row.append("%.1f" % (wc * cycle_unit / (us * 1e-6 * clock_hz) / cus) if wc and us == us else "nan")
         lines.append("| `%s` | %d | " % (k, nd) + " | ".join("%.4g" % avg.get(cn, float("nan")) for cn in names)
-                     + " | " + " | ".join(row) + " | %.2f |" % stats.get(k, float("nan")))
+                     + " | " + " | ".join(row) + " | %.2f |" % us)
     with open(out + ".md", "w") as fp:
         fp.write("\n".join(lines) + "\n")
 
@@ -367,7 +401,8 @@ def main(argv=None):
         ap.add_argument("--command-trace", default="")
         ap.add_argument("--command-pmc", default="")
         ap.add_argument("--cycle-unit", type=float, default=None,
-                        help="shader cycles per SQ_WAVE_CYCLES count (measured, e.g. with a one-wave spin kernel)")
+                        help="shader cycles per SQ_WAVE_CYCLES count; by default measured from the one-wave "
+                             "k_wave_clock kernel when both databases hold it (bench.py --calibrate-cycles)")
         a = ap.parse_args(argv[1:])
         sq_summary(a.trace, a.pmc, a.kernel, a.out, {"trace": a.command_trace, "SQ counters": a.command_pmc},
                    cycle_unit=a.cycle_unit)

@@ -100,6 +100,23 @@ def test_flush_llc_runs():
         bfp.bfp_flush_llc(100)
 
 
+def test_wave_clock_lasts_longer_with_more_iterations():
+    s = torch.cuda.current_stream()
+    times = {}
+    for iters in (20000, 80000):
+        bfp.bfp_wave_clock(iters, s)  # warm
+        e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+        e0.record(s)
+        bfp.bfp_wave_clock(iters, s)
+        e1.record(s)
+        torch.cuda.synchronize()
+        times[iters] = e0.elapsed_time(e1)
+    # a dependent chain: four times the iterations takes clearly longer
+    assert times[80000] > 2.5 * times[20000], times
+    with pytest.raises(bfp.BfpError):
+        bfp.bfp_wave_clock(0)
+
+
 def test_chain_and_int_autotune_install_and_stay_exact():
     f = bfp.fmt(5, 10)
     old = bfp.bfp_chain_launch_get("mul", "add", f)

@@ -153,6 +153,31 @@ def test_sq_summary_fractions_and_wave_life(tmp_path, monkeypatch):
     text = open(out + ".md").read()
     row = [l for l in text.splitlines() if "k_binop_std" in l][0].split("|")
     cells = [c.strip() for c in row[1:-1]]
-    # columns: kernel, dispatches, 6 counters (sorted), 3 fractions, resident, life, trace us
+    # columns: kernel, dispatches, 6 counters (sorted), 3 fractions, wave life, waves per CU, trace us.
+    # 57600 counts x 4 cycles / 32 waves at 2.4 GHz = 3.00 us per wave; over the 3.35 us
+    # trace average that is 57600 x 4 / 8040 cycles = 28.66 waves, 0.11 per CU.
     assert cells[1] == "2"
-    assert cells[8:] == ["0.50", "0.01", "0.25", "1.0", "3.00", "3.35"]
+    assert cells[8:] == ["0.50", "0.01", "0.25", "3.00", "0.1", "3.35"]
+
+
+def test_wave_cycle_unit_from_the_one_wave_kernel(tmp_path, monkeypatch):
+    tdb, pdb = str(tmp_path / "t.db"), str(tmp_path / "p.db")
+    clock = "void bfp::k_wave_clock(float*, int)"
+    k = "void bfp::k_binop_std<5, 2, false, 0>(Args)"
+    # 7.36 ms at 2.4 GHz = 17.664e6 cycles; a count of 4.40e6 is 4.01 cycles per count.
+    _trace_db(tdb, [(clock, 7360000, 64), (k, 3400, 2048)])
+    _counter_db(pdb, [(clock, "SQ_WAVE_CYCLES", 4.40e6, 64), (clock, "SQ_WAVES", 1.0, 64),
+                      (k, "SQ_WAVES", 32.0, 2048), (k, "SQ_WAVE_CYCLES", 1700.0 * 32, 2048)])
+    unit, ratio, nd = P.wave_cycle_unit(tdb, pdb)
+    assert unit == 4.0 and ratio == pytest.approx(4.0145, rel=1e-3) and nd == 1
+    monkeypatch.setattr(P, "source_hash", lambda: "abc123")
+    out = str(tmp_path / "sq")
+    P.sq_summary(tdb, pdb, ["bfp::k_binop_std<5, 2, false, 0>"], out, {"pmc": "cmd"})
+    text = open(out + ".md").read()
+    assert "one count is 4 shader cycles" in text
+    row = [l for l in text.splitlines() if "k_binop_std" in l][0]
+    # 1700 counts x 4 cycles / 2.4 GHz = 2.83 us per wave
+    assert "| 2.83 |" in row
+    # without the calibration kernel no unit is assumed
+    _counter_db(str(tmp_path / "q.db"), [(k, "SQ_WAVES", 32.0, 2048), (k, "SQ_WAVE_CYCLES", 54400.0, 2048)])
+    assert P.wave_cycle_unit(tdb, str(tmp_path / "q.db")) is None
