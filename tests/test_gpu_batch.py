@@ -78,6 +78,16 @@ def test_batch_mixed_all_variants():
     out = _outputs(bt)
     for i in range(len(bt.tasks)):
         assert torch.equal(out[i], ref[i]), ("eager", i)
+    # launches that follow each other on one stream with no host step between
+    # them: each starts from the counters the previous one left at zero
+    _scrub(bt)
+    plan.run()
+    plan.run_eager()
+    plan.run()
+    plan.run_eager()
+    out = _outputs(bt)
+    for i in range(len(bt.tasks)):
+        assert torch.equal(out[i], ref[i]), ("back to back", i)
     # the per-vector launches replayed from their captured graph
     for rep in range(2):
         _scrub(bt)
