@@ -695,8 +695,11 @@ def main():
         roof = {"kernel": dom, "bound": "hbm", "achieved": dk["GB/s"], "peak": HBM_PEAK / 1e9, "unit": "GB/s",
                 "frac": dk["hbm_frac"], "traffic": None}
     # practical ceilings on this machine: best read, write and copy sweeps over
-    # 1 GiB (several 16-byte accesses in flight per lane), events on the same stream
-    ceil = {mode: bfp.bfp_measure_hbm(1 << 30, mode, 5, stream) for mode in ("read", "write", "copy")}
+    # 1 GiB, and a sweep that reads two 1 GiB streams and writes a third (an
+    # elementwise binary op's traffic), several 16-byte accesses in flight
+    # per lane, events on the same stream
+    ceil = {mode: bfp.bfp_measure_hbm(1 << 30, mode, 5, stream)
+            for mode in ("read", "write", "copy", "read2_write1")}
     roof["ceiling_GBps"] = {mode: c["GB/s"] for mode, c in ceil.items()}
     roof["copy_GBps"] = ceil["copy"]["GB/s"]
     if roof["unit"] == "GB/s":
@@ -712,6 +715,11 @@ def main():
         rd, wr = k["read_bytes"], k["bytes"] - k["read_bytes"]
         k["mix_ceiling_GBps"] = k["bytes"] / (rd / (ceil["read"]["GB/s"] * 1e9) + wr / (ceil["write"]["GB/s"] * 1e9)) / 1e9
         k["frac_of_mix_ceiling"] = k["GB/s"] / k["mix_ceiling_GBps"]
+        # kernels with the same traffic shape as a probe, against that probe
+        if abs(rd - 2 * wr) <= 1e-9 * rd:
+            k["frac_of_probe"] = k["GB/s"] / ceil["read2_write1"]["GB/s"]
+        elif abs(rd - wr) <= 1e-9 * rd:
+            k["frac_of_probe"] = k["GB/s"] / ceil["copy"]["GB/s"]
     # the dominant kernel alone: after one 1 GiB sweep, its launches of every
     # format back to back, twice over (each launch's input was last touched
     # several launches, and more than the cache holds, earlier), so the event
@@ -763,7 +771,8 @@ def main():
         "roofline": roof,
         "kernels": {k: {x: v[x] for x in ("us", "launches", "GB/s", "hbm_frac", "Tops/s", "valu_frac",
                                           "us_cache_assisted", "hbm_frac_cache_assisted",
-                                          "valu_frac_cache_assisted", "frac_of_mix_ceiling") if x in v}
+                                          "valu_frac_cache_assisted", "frac_of_mix_ceiling", "frac_of_probe")
+                                 if x in v}
                     for k, v in kernels.items()},
     }
     if not args.no_sweep:

@@ -243,12 +243,14 @@ bfp_status bfp_autotune(int op, bfp_format f, uint64_t n_probe, int words_per_la
                         bfp_launch* best, double* best_us);
 
 /* Practical HBM ceiling of this device: `mode` 0 reads, 1 writes, 2 copies
- * `bytes` (>= 1 GiB recommended, so the 256 MB last-level cache cannot hold
- * the buffer) with several 16-byte accesses in flight per lane; every
+ * `bytes`, 3 reads two streams of `bytes` and writes their XOR to a third
+ * (an elementwise binary op's traffic) (>= 1 GiB recommended, so the 256 MB
+ * last-level cache cannot hold the buffers) with several 16-byte accesses
+ * per stream in flight per lane; every
  * launch shape of a small sweep (grids of 4..32 blocks per CU, 2, 4 or 8
  * accesses in flight, ordinary or non-temporal accesses) is timed over `reps` launches between events on
  * `stream`, and the best rate is returned in *gbps (bytes moved per second,
- * read + written for a copy, 1e9 units); the winning grid and accesses in
+ * everything read + written, 1e9 units); the winning grid and accesses in
  * flight go to *best_grid and *best_unroll when not NULL.  Allocates its
  * buffers.  2^20 <= bytes <= 2^36, bytes a multiple of 16, 1 <= reps <= 1000. */
 bfp_status bfp_measure_hbm(uint64_t bytes, int mode, int reps, void* stream, double* gbps, int* best_grid,

@@ -439,10 +439,11 @@ def bfp_measure_copy(nbytes: int, reps: int = 10, stream=None) -> float:
 
 
 def bfp_measure_hbm(nbytes: int, mode: str, reps: int = 10, stream=None) -> dict:
-    """Best read / write / copy rate (GB/s) over the probe's launch shapes."""
+    """Best read / write / copy / two-reads-one-write rate (GB/s, all bytes
+    moved) over the probe's launch shapes."""
     g = ctypes.c_double()
     grid, unroll = ctypes.c_int(), ctypes.c_int()
-    m = {"read": 0, "write": 1, "copy": 2}[mode]
+    m = {"read": 0, "write": 1, "copy": 2, "read2_write1": 3}[mode]
     _check(lib().bfp_measure_hbm(nbytes, m, reps, _stream(stream), ctypes.byref(g), ctypes.byref(grid),
                                  ctypes.byref(unroll)), "bfp_measure_hbm")
     return {"GB/s": g.value, "grid": grid.value, "in_flight": unroll.value}

@@ -46,12 +46,15 @@ __global__ void k_sweep_read(const u32x4* p, uint64_t n4, uint32_t* sink) {
   if (acc == 0x9E3779B9u) sink[threadIdx.x & 63] = acc;  // keeps the loads live; practically never taken
 }
 
-// Ceiling probes: plain read, write and copy sweeps with U independent
-// 16-byte accesses in flight per lane (each wave instruction covers 1 KiB
-// contiguous; the U accesses of a lane are a grid stride apart), with
-// ordinary or non-temporal accesses.  The best launch shape over a small
-// sweep is the practical HBM ceiling the kernels' fractions are read against.
-template <int MODE, int U, bool NT>  // MODE 0 read, 1 write, 2 copy; NT: non-temporal accesses
+// Ceiling probes: plain read, write and copy sweeps, and a sweep that reads
+// two streams and writes their XOR to a third (the traffic of an elementwise
+// binary op), with U independent 16-byte accesses per stream in flight per
+// lane (each wave instruction covers 1 KiB contiguous; the U accesses of a
+// lane are a grid stride apart), with ordinary or non-temporal accesses.
+// The best launch shape over a small sweep is the practical HBM ceiling the
+// kernels' fractions are read against.  In mode 3 `src` holds the two read
+// streams back to back, n4 16-byte words each.
+template <int MODE, int U, bool NT>  // MODE 0 read, 1 write, 2 copy, 3 two reads + one write; NT: non-temporal
 __global__ void __launch_bounds__(256) k_bw(const u32x4* __restrict__ src, u32x4* __restrict__ dst, uint64_t n4,
                                             uint32_t* sink) {
   const uint64_t stride = (uint64_t)gridDim.x * blockDim.x;
@@ -59,7 +62,16 @@ __global__ void __launch_bounds__(256) k_bw(const u32x4* __restrict__ src, u32x4
   uint32_t acc = 0;
   for (; i + (U - 1) * stride < n4; i += U * stride) {
     u32x4 v[U];
-    if constexpr (MODE != 1) {
+    if constexpr (MODE == 3) {
+      u32x4 w[U];
+#pragma unroll
+      for (int u = 0; u < U; ++u) {
+        v[u] = NT ? __builtin_nontemporal_load(src + i + u * stride) : src[i + u * stride];
+        w[u] = NT ? __builtin_nontemporal_load(src + n4 + i + u * stride) : src[n4 + i + u * stride];
+      }
+#pragma unroll
+      for (int u = 0; u < U; ++u) v[u] = u32x4{v[u].x ^ w[u].x, v[u].y ^ w[u].y, v[u].z ^ w[u].z, v[u].w ^ w[u].w};
+    } else if constexpr (MODE != 1) {
 #pragma unroll
       for (int u = 0; u < U; ++u) v[u] = NT ? __builtin_nontemporal_load(src + i + u * stride) : src[i + u * stride];
     } else {
@@ -83,8 +95,11 @@ __global__ void __launch_bounds__(256) k_bw(const u32x4* __restrict__ src, u32x4
       acc ^= v.x ^ v.y ^ v.z ^ v.w;
     } else if constexpr (MODE == 1) {
       dst[i] = u32x4{(uint32_t)i, 0u, 0u, 0u};
-    } else {
+    } else if constexpr (MODE == 2) {
       dst[i] = src[i];
+    } else {
+      const u32x4 v = src[i], w = src[n4 + i];
+      dst[i] = u32x4{v.x ^ w.x, v.y ^ w.y, v.z ^ w.z, v.w ^ w.w};
     }
   }
   if (MODE == 0 && acc == 0x9E3779B9u) sink[threadIdx.x & 63] = acc;  // keeps the loads live
@@ -168,22 +183,25 @@ extern "C" bfp_status bfp_measure_hbm(uint64_t bytes, int mode, int reps, void* 
                                      int* best_grid, int* best_unroll) {
   if (!gbps) return BFP_E_NULL;
   if (bytes < (1u << 20) || bytes > (1ull << 36) || (bytes & 15u) || reps < 1 || reps > 1000) return BFP_E_ARG;
-  if (mode < 0 || mode > 2) return BFP_E_ARG;
+  if (mode < 0 || mode > 3) return BFP_E_ARG;
   hipStream_t s = (hipStream_t)stream;
   DevBuf src, dst, sink;
-  if (hipMalloc(&src.p, bytes) != hipSuccess || hipMalloc(&dst.p, bytes) != hipSuccess ||
+  const uint64_t src_bytes = mode == 3 ? 2 * bytes : bytes;  // mode 3: two read streams of `bytes` each
+  if (hipMalloc(&src.p, src_bytes) != hipSuccess || hipMalloc(&dst.p, bytes) != hipSuccess ||
       hipMalloc(&sink.p, 256) != hipSuccess)
     return BFP_E_NOMEM;
   const uint64_t n4 = bytes / 16;
-  hipLaunchKernelGGL(k_fill_random, dim3(2048), dim3(256), 0, s, (uint32_t*)src.p, bytes / 4, 0x4242u);
+  hipLaunchKernelGGL(k_fill_random, dim3(2048), dim3(256), 0, s, (uint32_t*)src.p, src_bytes / 4, 0x4242u);
   if (hipGetLastError() != hipSuccess) return BFP_E_HIP;
-  static const BwLauncher table[3][6] = {
+  static const BwLauncher table[4][6] = {
       {launch_bw<0, 2, false>, launch_bw<0, 4, false>, launch_bw<0, 8, false>, launch_bw<0, 2, true>,
        launch_bw<0, 4, true>, launch_bw<0, 8, true>},
       {launch_bw<1, 2, false>, launch_bw<1, 4, false>, launch_bw<1, 8, false>, launch_bw<1, 2, true>,
        launch_bw<1, 4, true>, launch_bw<1, 8, true>},
       {launch_bw<2, 2, false>, launch_bw<2, 4, false>, launch_bw<2, 8, false>, launch_bw<2, 2, true>,
-       launch_bw<2, 4, true>, launch_bw<2, 8, true>}};
+       launch_bw<2, 4, true>, launch_bw<2, 8, true>},
+      {launch_bw<3, 2, false>, launch_bw<3, 4, false>, launch_bw<3, 8, false>, launch_bw<3, 2, true>,
+       launch_bw<3, 4, true>, launch_bw<3, 8, true>}};
   const int unrolls[6] = {2, 4, 8, 2, 4, 8};
   const unsigned grids[4] = {1024, 2048, 4096, 8192};  // 4 to 32 blocks of 256 threads per CU
   hipEvent_t e0, e1;
@@ -206,7 +224,7 @@ extern "C" bfp_status bfp_measure_hbm(uint64_t bytes, int mode, int reps, void* 
       if (st == BFP_OK && hipEventSynchronize(e1) != hipSuccess) st = BFP_E_HIP;
       if (st == BFP_OK && hipEventElapsedTime(&ms, e0, e1) != hipSuccess) st = BFP_E_HIP;
       if (st != BFP_OK) break;
-      const double moved = (mode == 2 ? 2.0 : 1.0) * (double)bytes;
+      const double moved = (mode == 2 ? 2.0 : (mode == 3 ? 3.0 : 1.0)) * (double)bytes;
       const double g = moved / ((double)ms / reps * 1e-3) / 1e9;
       if (g > best) {
         best = g;

@@ -82,9 +82,10 @@ def test_measure_copy_is_plausible():
 
 
 def test_measure_hbm_modes_are_plausible():
-    """Read, write and copy ceilings over 1 GiB: between 1 TB/s and the
-    8 TB/s peak (bytes moved per second, both directions counted)."""
-    for mode in ("read", "write", "copy"):
+    """Read, write, copy and two-reads-one-write ceilings over 1 GiB streams:
+    between 1 TB/s and the 8 TB/s peak (bytes moved per second, every
+    stream counted)."""
+    for mode in ("read", "write", "copy", "read2_write1"):
         r = bfp.bfp_measure_hbm(1 << 30, mode, 3)
         assert 1000.0 < r["GB/s"] < 8000.0, (mode, r)
         assert r["grid"] in (1024, 2048, 4096, 8192) and r["in_flight"] in (2, 4, 8)
