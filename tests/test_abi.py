@@ -87,7 +87,7 @@ def test_wide_formats_sizing_and_table():
     with pytest.raises(bfp.BfpError):
         bfp.bfp_launch_set("mul", w, 2, 256, 0)  # one-word kernels only
     bfp.bfp_launch_set("mul", w, 1, 128, 4)
-    bfp.bfp_launch_set("mul", w, old.words_per_lane, old.block, old.blocks_per_cu)
+    bfp.bfp_launch_set("mul", w, old.words_per_lane, old.block, old.blocks_per_cu, max(1, old.unroll))
     assert not bfp.bfp_format_supported(bfp.fmt(11, 53))
     assert not bfp.bfp_format_supported(bfp.fmt(12, 40))
 
@@ -161,22 +161,22 @@ def test_launch_table_roundtrip(tmp_path):
     assert bfp.bfp_launch_get("mul", f).block == 128
     p = str(tmp_path / "t.txt")
     bfp.bfp_launch_save(p)
-    bfp.bfp_launch_set("mul", f, old.words_per_lane, old.block, old.blocks_per_cu)
+    bfp.bfp_launch_set("mul", f, old.words_per_lane, old.block, old.blocks_per_cu, max(1, old.unroll))
     bfp.bfp_launch_load(p)
     assert bfp.bfp_launch_get("mul", f).block == 128
-    bfp.bfp_launch_set("mul", f, old.words_per_lane, old.block, old.blocks_per_cu)
+    bfp.bfp_launch_set("mul", f, old.words_per_lane, old.block, old.blocks_per_cu, max(1, old.unroll))
     # division has a table entry of its own
     old_d = bfp.bfp_launch_get("div", f)
     bfp.bfp_launch_set("div", f, 1, 512, 8)
     bfp.bfp_launch_save(p)
-    bfp.bfp_launch_set("div", f, old_d.words_per_lane, old_d.block, old_d.blocks_per_cu)
+    bfp.bfp_launch_set("div", f, old_d.words_per_lane, old_d.block, old_d.blocks_per_cu, max(1, old_d.unroll))
     cm = bfp.bfp_launch_get("mul", f)
     assert (cm.words_per_lane, cm.block, cm.blocks_per_cu) == (old.words_per_lane, old.block, old.blocks_per_cu)
     bfp.bfp_launch_load(p)
     c = bfp.bfp_launch_get("div", f)
     assert (c.words_per_lane, c.block, c.blocks_per_cu) == (1, 512, 8)
-    bfp.bfp_launch_set("div", f, old_d.words_per_lane, old_d.block, old_d.blocks_per_cu)
-    bfp.bfp_launch_set("mul", f, old.words_per_lane, old.block, old.blocks_per_cu)
+    bfp.bfp_launch_set("div", f, old_d.words_per_lane, old_d.block, old_d.blocks_per_cu, max(1, old_d.unroll))
+    bfp.bfp_launch_set("mul", f, old.words_per_lane, old.block, old.blocks_per_cu, max(1, old.unroll))
     with pytest.raises(bfp.BfpError):
         bfp.bfp_launch_set("add", f, 3, 256, 0)
     with pytest.raises(bfp.BfpError):

@@ -32,7 +32,7 @@ def test_autotune_installs_measured_best(e, m, op):
     assert best.unroll in (1, 2)
     best1, _ = bfp.bfp_autotune(op, f, 1 << 18, 1, 1)
     assert best1.words_per_lane == 1
-    bfp.bfp_launch_set(op, f, old.words_per_lane, old.block, old.blocks_per_cu)
+    bfp.bfp_launch_set(op, f, old.words_per_lane, old.block, old.blocks_per_cu, max(1, old.unroll))
 
 
 @pytest.mark.parametrize("e,m", [(6, 7), (4, 3)])
