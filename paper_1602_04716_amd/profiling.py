@@ -388,10 +388,71 @@ def sq_summary(trace_db, pmc_db, kernels, out, commands, cycle_unit=None, clock_
         fp.write("\n".join(lines) + "\n")
 
 
+def tick_bursts(trace_db, kernel="k_batch", gap_ns=20e6):
+    """Dispatches of `kernel` in a kernel trace, split into bursts wherever
+    no such dispatch runs for `gap_ns` (the serving bench's separate runs).
+    Per burst: dispatches, window (first start to last end), the share of
+    the window in which at least one dispatch ran, and dispatch durations."""
+    rows = []
+    c = sqlite3.connect(trace_db).cursor()
+    for name, start, end in c.execute("select name, start, end from kernels order by start"):
+        if kernel in name:
+            rows.append((start, end))
+    bursts, cur = [], []
+    for s_, e_ in rows:
+        if cur and s_ - max(e for _s, e in cur) > gap_ns:
+            bursts.append(cur)
+            cur = []
+        cur.append((s_, e_))
+    if cur:
+        bursts.append(cur)
+    out = []
+    for bu in bursts:
+        t0, t1 = bu[0][0], max(e for _s, e in bu)
+        busy, last = 0, t0
+        for s_, e_ in sorted(bu):
+            if e_ <= last:
+                continue
+            busy += e_ - max(s_, last)
+            last = e_
+        durs = sorted((e_ - s_) / 1e3 for s_, e_ in bu)
+        out.append({"dispatches": len(bu), "window_ms": (t1 - t0) / 1e6,
+                    "busy_frac": busy / (t1 - t0) if t1 > t0 else float("nan"),
+                    "median_us": durs[len(durs) // 2], "p90_us": durs[int(len(durs) * 0.9)]})
+    return out
+
+
+def ticks_summary(trace_db, out, commands, labels=()):
+    lines = ["# rocprofv3 serving ticks: %s" % os.path.basename(out), "",
+             "Kernel sources hash: `%s`" % source_hash(), "",
+             "Commands (run from the repository root on one MI355X):", ""]
+    for k, v in commands.items():
+        lines.append("- %s: `%s`" % (k, v))
+    lines += ["", "Persistent batch kernels of the serving bench, one burst per run (runs are separated by more "
+              "than 20 ms without a batch kernel); busy = share of the burst's window in which a batch kernel "
+              "ran on the device.", "",
+              "| run | ticks | window ms | device busy | tick median us | tick p90 us |", "|---|---|---|---|---|---|"]
+    for i, b in enumerate(tick_bursts(trace_db)):
+        name = labels[i] if i < len(labels) else "run %d" % i
+        lines.append("| %s | %d | %.2f | %.1f%% | %.1f | %.1f |" % (name, b["dispatches"], b["window_ms"],
+                                                                 100 * b["busy_frac"], b["median_us"], b["p90_us"]))
+    with open(out + ".md", "w") as fp:
+        fp.write("\n".join(lines) + "\n")
+
+
 def main(argv=None):
     import sys
     if argv is None:
         argv = sys.argv[1:]
+    if argv and argv[0] == "ticks":
+        ap = argparse.ArgumentParser()
+        ap.add_argument("--trace", required=True)
+        ap.add_argument("--out", required=True)
+        ap.add_argument("--command-trace", default="")
+        ap.add_argument("--label", action="append", default=[])
+        a = ap.parse_args(argv[1:])
+        ticks_summary(a.trace, a.out, {"trace": a.command_trace}, a.label)
+        return 0
     if argv and argv[0] == "sq":
         ap = argparse.ArgumentParser()
         ap.add_argument("--trace", required=True)

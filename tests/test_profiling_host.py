@@ -181,3 +181,29 @@ def test_wave_cycle_unit_from_the_one_wave_kernel(tmp_path, monkeypatch):
     # without the calibration kernel no unit is assumed
     _counter_db(str(tmp_path / "q.db"), [(k, "SQ_WAVES", 32.0, 2048), (k, "SQ_WAVE_CYCLES", 54400.0, 2048)])
     assert P.wave_cycle_unit(tdb, str(tmp_path / "q.db")) is None
+
+
+def test_tick_bursts_split_runs_and_measure_busy_share(tmp_path):
+    db = str(tmp_path / "t.db")
+    c = sqlite3.connect(db)
+    c.execute("create table kernels (name text, start integer, end integer, grid_x integer)")
+    c.execute("create table top_kernels (name text, total_calls integer, total_duration real, "
+              "average real, percentage real)")
+    k0, k1 = "void bfp::k_batch<0>(Args)", "void bfp::k_batch<1>(Args)"
+    us = 1000
+    # run 1: two overlapping ticks then one after a 10 us gap: busy 30 of 40 us
+    rows = [(k0, 0, 20 * us), (k0, 10 * us, 20 * us), (k1, 30 * us, 40 * us)]
+    # run 2, 50 ms later: back-to-back ticks, fully busy
+    t = 50_000 * us
+    rows += [(k0, t, t + 5 * us), (k0, t + 5 * us, t + 10 * us), ("void other(Args)", t + 10 * us, t + 90 * us)]
+    c.executemany("insert into kernels values (?,?,?,0)", rows)
+    c.commit()
+    c.close()
+    b = P.tick_bursts(db)
+    assert [x["dispatches"] for x in b] == [3, 2]
+    assert b[0]["window_ms"] == pytest.approx(0.04) and b[0]["busy_frac"] == pytest.approx(0.75)
+    assert b[1]["busy_frac"] == pytest.approx(1.0) and b[1]["median_us"] == pytest.approx(5.0)
+    out = str(tmp_path / "ticks")
+    P.ticks_summary(db, out, {"trace": "cmd"}, ["first", "second"])
+    text = open(out + ".md").read()
+    assert "| first | 3 | 0.04 | 75.0% |" in text and "| second | 2 |" in text
