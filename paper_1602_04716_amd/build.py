@@ -1,5 +1,6 @@
-"""Build libbfp.so (HIP kernels for gfx950 + C ABI) and the host-side
-circuit simulator used by the CPU tests.
+"""Build libbfp.so (HIP kernels for gfx950 + C ABI), the host-side circuit
+simulator used by the CPU tests, and the plain C program the tests use to
+call the library from C.
 
     python -m paper_1602_04716_amd.build [--force] [-j N]
 
@@ -7,7 +8,9 @@ Every ``csrc/*.hip`` file is compiled with hipcc for gfx950 and every
 ``csrc/*.cpp`` that belongs to the library with the host compiler; the objects
 are linked into ``paper_1602_04716_amd/libbfp.so``.  ``bfp_host_sim.cpp`` is
 built separately into ``paper_1602_04716_amd/libbfp_hostsim.so`` (test-only:
-the GPU library never loads it).
+the GPU library never loads it), and ``tests/abi_consumer.c``, a C99 program
+that includes only ``include/bfp.h`` and the HIP runtime's C API, into
+``tests/abi_consumer`` (linked against libbfp.so).
 """
 from __future__ import annotations
 
@@ -24,6 +27,9 @@ INCLUDE = os.path.join(ROOT, "include")
 OBJDIR = os.path.join(ROOT, "_build")
 LIB = os.path.join(PKG, "libbfp.so")
 HOSTSIM = os.path.join(PKG, "libbfp_hostsim.so")
+CONSUMER_SRC = os.path.join(ROOT, "tests", "abi_consumer.c")
+CONSUMER = os.path.join(ROOT, "tests", "abi_consumer")
+ROCM = os.environ.get("ROCM_PATH", "/opt/rocm")
 
 ARCH = "gfx950"
 HIPCC = os.environ.get("HIPCC", "/opt/rocm/bin/hipcc")
@@ -81,6 +87,13 @@ def build(force: bool = False, jobs: int | None = None, verbose: bool = False) -
         tmp = LIB + ".tmp%d" % os.getpid()
         _run([HIPCC, "--offload-arch=" + ARCH, "-shared", "-fPIC", "-o", tmp] + objs)
         os.replace(tmp, LIB)
+    if force or _stale(CONSUMER, [CONSUMER_SRC, LIB, os.path.join(INCLUDE, "bfp.h")]):
+        tmp = CONSUMER + ".tmp%d" % os.getpid()
+        _run(["gcc", "-std=c99", "-O1", "-Wall", "-Wextra", "-pedantic", "-D__HIP_PLATFORM_AMD__",
+              "-I" + INCLUDE, "-I" + os.path.join(ROCM, "include"), CONSUMER_SRC, "-o", tmp,
+              "-L" + PKG, "-lbfp", "-Wl,-rpath,$ORIGIN/../paper_1602_04716_amd",
+              "-L" + os.path.join(ROCM, "lib"), "-lamdhip64", "-Wl,-rpath," + os.path.join(ROCM, "lib")])
+        os.replace(tmp, CONSUMER)
     return LIB
 
 

@@ -259,3 +259,33 @@ def test_layout_method_table(tmp_path):
         bfp.bfp_layout_method_set("pack", 3, 0)
     with pytest.raises(bfp.BfpError):
         bfp.bfp_layout_method_set(2, 1, 0)
+
+
+CONSUMER = os.path.join(ROOT, "tests", "abi_consumer")
+
+
+def test_c_consumer_host_mode():
+    """A C99 program that includes only include/bfp.h (and the HIP runtime's
+    C API) and links libbfp.so: its host-side calls agree with the binding's."""
+    assert os.path.exists(CONSUMER), "tests/abi_consumer is built by paper_1602_04716_amd.build"
+    out = subprocess.run([CONSUMER, "host"], check=True, capture_output=True, text=True, timeout=60).stdout
+    kv = dict(line.split(" ", 1) for line in out.strip().splitlines())
+    f = bfp.fmt(5, 10)
+    assert kv["version"] == bfp.bfp_version()
+    assert int(kv["container_bytes_5_10"]) == bfp.bfp_container_bytes(f)
+    for n in (1, 2048, 65000, 66000):
+        assert int(kv["stride_%d" % n]) == bfp.bfp_plane_stride_words(n)
+    assert int(kv["bitslice_bytes_5_10_65000"]) == bfp.bfp_bitslice_bytes(f, 65000)
+    assert int(kv["gates_add_5_10"]) == bfp.bfp_gate_count("add", f)
+    assert int(kv["gates_mul_5_10"]) == bfp.bfp_gate_count("mul", f)
+    assert kv["format_7_4_supported"] == "0" and kv["pack_bad_format"] == str(bfp.BFP_E_FORMAT)
+    assert kv["status_null"] == bfp.bfp_status_string(bfp.BFP_E_NULL)
+
+
+def test_header_compiles_as_c99_and_cxx():
+    src = '#include "bfp.h"\nint main(void) { bfp_format f = {5, 10, BFP_RNE, 0}; return (int)bfp_container_bytes(f); }\n'
+    inc = os.path.join(ROOT, "include")
+    for cc, std, ext in (("gcc", "-std=c99", "c"), ("g++", "-std=c++17", "cpp")):
+        r = subprocess.run([cc, std, "-Wall", "-Wextra", "-pedantic", "-Werror", "-fsyntax-only", "-I" + inc,
+                            "-x", "c" if ext == "c" else "c++", "-"], input=src, capture_output=True, text=True)
+        assert r.returncode == 0, (cc, r.stderr)
