@@ -710,11 +710,13 @@ def main():
                 "frac": dk["hbm_frac"], "traffic": None}
     # practical ceilings on this machine: best read, write and copy sweeps over
     # 1 GiB, and a sweep that reads two 1 GiB streams and writes a third (an
-    # elementwise binary op's traffic), several 16-byte accesses in flight
-    # per lane, events on the same stream
+    # elementwise binary op's traffic), over launch shapes from one block per
+    # CU to 32 and 1 to 8 accesses in flight per lane, events on the same stream
     ceil = {mode: bfp.bfp_measure_hbm(1 << 30, mode, 5, stream)
             for mode in ("read", "write", "copy", "read2_write1")}
     roof["ceiling_GBps"] = {mode: c["GB/s"] for mode, c in ceil.items()}
+    roof["ceiling_shapes"] = {mode: {"grid": c["grid"], "block": c["block"], "in_flight": c["in_flight"]}
+                              for mode, c in ceil.items()}
     roof["copy_GBps"] = ceil["copy"]["GB/s"]
     if roof["unit"] == "GB/s":
         roof["frac_of_copy"] = roof["achieved"] / roof["copy_GBps"]

@@ -245,16 +245,18 @@ bfp_status bfp_autotune(int op, bfp_format f, uint64_t n_probe, int words_per_la
 /* Practical HBM ceiling of this device: `mode` 0 reads, 1 writes, 2 copies
  * `bytes`, 3 reads two streams of `bytes` and writes their XOR to a third
  * (an elementwise binary op's traffic) (>= 1 GiB recommended, so the 256 MB
- * last-level cache cannot hold the buffers) with several 16-byte accesses
- * per stream in flight per lane; every
- * launch shape of a small sweep (grids of 4..32 blocks per CU, 2, 4 or 8
- * accesses in flight, ordinary or non-temporal accesses) is timed over `reps` launches between events on
- * `stream`, and the best rate is returned in *gbps (bytes moved per second,
- * everything read + written, 1e9 units); the winning grid and accesses in
- * flight go to *best_grid and *best_unroll when not NULL.  Allocates its
- * buffers.  2^20 <= bytes <= 2^36, bytes a multiple of 16, 1 <= reps <= 1000. */
+ * last-level cache cannot hold the buffers) with 16-byte accesses, every
+ * wave instruction covering 1 KiB contiguous.  Every launch shape of a sweep
+ * (1, 2, 4, 8, 16 or 32 blocks per CU of 256 threads, and 1 or 2 blocks per
+ * CU of 512 or 1024 threads; 1, 2, 4 or 8 accesses per stream in flight per
+ * lane; ordinary or non-temporal accesses) is timed over `reps` launches
+ * between events on `stream`, and the best rate is returned in *gbps (bytes
+ * moved per second, everything read + written, 1e9 units); the winning grid
+ * (blocks), block (threads) and accesses in flight go to *best_grid,
+ * *best_block and *best_unroll when not NULL.  Allocates its buffers.
+ * 2^20 <= bytes <= 2^36, bytes a multiple of 16, 1 <= reps <= 1000. */
 bfp_status bfp_measure_hbm(uint64_t bytes, int mode, int reps, void* stream, double* gbps, int* best_grid,
-                           int* best_unroll);
+                           int* best_block, int* best_unroll);
 
 /* bfp_measure_hbm in copy mode (read + write GB/s). */
 bfp_status bfp_measure_copy(uint64_t bytes, int reps, void* stream, double* gbps);

@@ -133,7 +133,7 @@ _SIGS = {
                                         ctypes.POINTER(ctypes.c_double)]),
     "bfp_measure_hbm": (ctypes.c_int, [ctypes.c_uint64, ctypes.c_int, ctypes.c_int, ctypes.c_void_p,
                                        ctypes.POINTER(ctypes.c_double), ctypes.POINTER(ctypes.c_int),
-                                       ctypes.POINTER(ctypes.c_int)]),
+                                       ctypes.POINTER(ctypes.c_int), ctypes.POINTER(ctypes.c_int)]),
     "bfp_flush_llc": (ctypes.c_int, [ctypes.c_uint64, ctypes.c_void_p]),
     "bfp_wave_clock": (ctypes.c_int, [ctypes.c_int, ctypes.c_void_p]),
     "bfp_gate_count": (ctypes.c_long, [ctypes.c_int, bfp_format]),
@@ -442,11 +442,11 @@ def bfp_measure_hbm(nbytes: int, mode: str, reps: int = 10, stream=None) -> dict
     """Best read / write / copy / two-reads-one-write rate (GB/s, all bytes
     moved) over the probe's launch shapes."""
     g = ctypes.c_double()
-    grid, unroll = ctypes.c_int(), ctypes.c_int()
+    grid, block, unroll = ctypes.c_int(), ctypes.c_int(), ctypes.c_int()
     m = {"read": 0, "write": 1, "copy": 2, "read2_write1": 3}[mode]
     _check(lib().bfp_measure_hbm(nbytes, m, reps, _stream(stream), ctypes.byref(g), ctypes.byref(grid),
-                                 ctypes.byref(unroll)), "bfp_measure_hbm")
-    return {"GB/s": g.value, "grid": grid.value, "in_flight": unroll.value}
+                                 ctypes.byref(block), ctypes.byref(unroll)), "bfp_measure_hbm")
+    return {"GB/s": g.value, "grid": grid.value, "block": block.value, "in_flight": unroll.value}
 
 
 def bfp_flush_llc(nbytes: int = 1 << 30, stream=None):

@@ -51,11 +51,14 @@ __global__ void k_sweep_read(const u32x4* p, uint64_t n4, uint32_t* sink) {
 // binary op), with U independent 16-byte accesses per stream in flight per
 // lane (each wave instruction covers 1 KiB contiguous; the U accesses of a
 // lane are a grid stride apart), with ordinary or non-temporal accesses.
-// The best launch shape over a small sweep is the practical HBM ceiling the
-// kernels' fractions are read against.  In mode 3 `src` holds the two read
-// streams back to back, n4 16-byte words each.
+// The best launch shape over a sweep of grids (1 to 32 blocks per CU) and
+// block sizes (256 to 1024 threads for 1 or 2 blocks per CU) is the
+// practical HBM ceiling the kernels' fractions are read against: writes in
+// particular go fastest from few waves (one 256-thread block per CU), not
+// from a full grid.  In mode 3 `src` holds the two read streams back to back,
+// n4 16-byte words each.
 template <int MODE, int U, bool NT>  // MODE 0 read, 1 write, 2 copy, 3 two reads + one write; NT: non-temporal
-__global__ void __launch_bounds__(256) k_bw(const u32x4* __restrict__ src, u32x4* __restrict__ dst, uint64_t n4,
+__global__ void __launch_bounds__(1024) k_bw(const u32x4* __restrict__ src, u32x4* __restrict__ dst, uint64_t n4,
                                             uint32_t* sink) {
   const uint64_t stride = (uint64_t)gridDim.x * blockDim.x;
   uint64_t i = blockIdx.x * (uint64_t)blockDim.x + threadIdx.x;
@@ -105,10 +108,12 @@ __global__ void __launch_bounds__(256) k_bw(const u32x4* __restrict__ src, u32x4
   if (MODE == 0 && acc == 0x9E3779B9u) sink[threadIdx.x & 63] = acc;  // keeps the loads live
 }
 
-using BwLauncher = void (*)(unsigned grid, hipStream_t s, const u32x4* src, u32x4* dst, uint64_t n4, uint32_t* sink);
+using BwLauncher = void (*)(unsigned grid, unsigned block, hipStream_t s, const u32x4* src, u32x4* dst, uint64_t n4,
+                           uint32_t* sink);
 template <int MODE, int U, bool NT>
-void launch_bw(unsigned grid, hipStream_t s, const u32x4* src, u32x4* dst, uint64_t n4, uint32_t* sink) {
-  hipLaunchKernelGGL((k_bw<MODE, U, NT>), dim3(grid), dim3(256), 0, s, src, dst, n4, sink);
+void launch_bw(unsigned grid, unsigned block, hipStream_t s, const u32x4* src, u32x4* dst, uint64_t n4,
+               uint32_t* sink) {
+  hipLaunchKernelGGL((k_bw<MODE, U, NT>), dim3(grid), dim3(block), 0, s, src, dst, n4, sink);
 }
 
 struct DevBuf {
@@ -180,7 +185,7 @@ bfp_status tune_block_grid(Set set, Run run, int wpl, int reps, hipStream_t s, c
 using namespace bfp;
 
 extern "C" bfp_status bfp_measure_hbm(uint64_t bytes, int mode, int reps, void* stream, double* gbps,
-                                     int* best_grid, int* best_unroll) {
+                                     int* best_grid, int* best_block, int* best_unroll) {
   if (!gbps) return BFP_E_NULL;
   if (bytes < (1u << 20) || bytes > (1ull << 36) || (bytes & 15u) || reps < 1 || reps > 1000) return BFP_E_ARG;
   if (mode < 0 || mode > 3) return BFP_E_ARG;
@@ -193,17 +198,22 @@ extern "C" bfp_status bfp_measure_hbm(uint64_t bytes, int mode, int reps, void* 
   const uint64_t n4 = bytes / 16;
   hipLaunchKernelGGL(k_fill_random, dim3(2048), dim3(256), 0, s, (uint32_t*)src.p, src_bytes / 4, 0x4242u);
   if (hipGetLastError() != hipSuccess) return BFP_E_HIP;
-  static const BwLauncher table[4][6] = {
-      {launch_bw<0, 2, false>, launch_bw<0, 4, false>, launch_bw<0, 8, false>, launch_bw<0, 2, true>,
-       launch_bw<0, 4, true>, launch_bw<0, 8, true>},
-      {launch_bw<1, 2, false>, launch_bw<1, 4, false>, launch_bw<1, 8, false>, launch_bw<1, 2, true>,
-       launch_bw<1, 4, true>, launch_bw<1, 8, true>},
-      {launch_bw<2, 2, false>, launch_bw<2, 4, false>, launch_bw<2, 8, false>, launch_bw<2, 2, true>,
-       launch_bw<2, 4, true>, launch_bw<2, 8, true>},
-      {launch_bw<3, 2, false>, launch_bw<3, 4, false>, launch_bw<3, 8, false>, launch_bw<3, 2, true>,
-       launch_bw<3, 4, true>, launch_bw<3, 8, true>}};
-  const int unrolls[6] = {2, 4, 8, 2, 4, 8};
-  const unsigned grids[4] = {1024, 2048, 4096, 8192};  // 4 to 32 blocks of 256 threads per CU
+  static const BwLauncher table[4][8] = {
+#define BFP_BW_ROW(MODE)                                                                                      \
+  {launch_bw<MODE, 1, false>, launch_bw<MODE, 2, false>, launch_bw<MODE, 4, false>, launch_bw<MODE, 8, false>, \
+   launch_bw<MODE, 1, true>, launch_bw<MODE, 2, true>, launch_bw<MODE, 4, true>, launch_bw<MODE, 8, true>}
+      BFP_BW_ROW(0), BFP_BW_ROW(1), BFP_BW_ROW(2), BFP_BW_ROW(3)};
+#undef BFP_BW_ROW
+  const int unrolls[8] = {1, 2, 4, 8, 1, 2, 4, 8};
+  struct Shape {
+    int blocks_per_cu, block;
+  };
+  static const Shape shapes[] = {{1, 256}, {1, 512}, {1, 1024}, {2, 256}, {2, 512}, {4, 256},
+                                 {8, 256}, {16, 256}, {32, 256}};
+  int dev = 0, cus = 0;
+  if (hipGetDevice(&dev) != hipSuccess ||
+      hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev) != hipSuccess || cus < 1)
+    return BFP_E_NODEV;
   hipEvent_t e0, e1;
   if (hipEventCreate(&e0) != hipSuccess) return BFP_E_HIP;
   if (hipEventCreate(&e1) != hipSuccess) {
@@ -212,13 +222,15 @@ extern "C" bfp_status bfp_measure_hbm(uint64_t bytes, int mode, int reps, void* 
   }
   bfp_status st = BFP_OK;
   double best = 0.0;
-  for (int ui = 0; ui < 6 && st == BFP_OK; ++ui) {
-    for (unsigned grid : grids) {
+  for (int ui = 0; ui < 8 && st == BFP_OK; ++ui) {
+    for (const Shape& sh : shapes) {
       const BwLauncher L = table[mode][ui];
-      L(grid, s, (const u32x4*)src.p, (u32x4*)dst.p, n4, (uint32_t*)sink.p);  // warm-up
+      const unsigned grid = (unsigned)(cus * sh.blocks_per_cu), block = (unsigned)sh.block;
+      L(grid, block, s, (const u32x4*)src.p, (u32x4*)dst.p, n4, (uint32_t*)sink.p);  // warm-up
       float ms = 0.f;
       if (hipEventRecord(e0, s) != hipSuccess) st = BFP_E_HIP;
-      for (int r = 0; r < reps && st == BFP_OK; ++r) L(grid, s, (const u32x4*)src.p, (u32x4*)dst.p, n4, (uint32_t*)sink.p);
+      for (int r = 0; r < reps && st == BFP_OK; ++r)
+        L(grid, block, s, (const u32x4*)src.p, (u32x4*)dst.p, n4, (uint32_t*)sink.p);
       if (st == BFP_OK && hipGetLastError() != hipSuccess) st = BFP_E_HIP;
       if (st == BFP_OK && hipEventRecord(e1, s) != hipSuccess) st = BFP_E_HIP;
       if (st == BFP_OK && hipEventSynchronize(e1) != hipSuccess) st = BFP_E_HIP;
@@ -229,6 +241,7 @@ extern "C" bfp_status bfp_measure_hbm(uint64_t bytes, int mode, int reps, void* 
       if (g > best) {
         best = g;
         if (best_grid) *best_grid = (int)grid;
+        if (best_block) *best_block = (int)block;
         if (best_unroll) *best_unroll = unrolls[ui];
       }
     }
@@ -240,7 +253,7 @@ extern "C" bfp_status bfp_measure_hbm(uint64_t bytes, int mode, int reps, void* 
 }
 
 extern "C" bfp_status bfp_measure_copy(uint64_t bytes, int reps, void* stream, double* gbps) {
-  return bfp_measure_hbm(bytes, 2, reps, stream, gbps, nullptr, nullptr);
+  return bfp_measure_hbm(bytes, 2, reps, stream, gbps, nullptr, nullptr, nullptr);
 }
 
 // Read sweep over `bytes` of a library buffer, so that what a following

@@ -148,8 +148,8 @@ def test_argument_errors_before_any_device_work():
     assert L.bfp_measure_copy(1 << 20, 0, None, ctypes.byref(g)) == -6
     assert L.bfp_measure_copy(1 << 20, 10, None, None) == -2
     assert L.bfp_wave_clock(0, None) == -6 and L.bfp_wave_clock((1 << 26) + 1, None) == -6
-    assert L.bfp_measure_hbm(1 << 20, 4, 1, None, ctypes.byref(g), None, None) == -6    # no mode 4
-    assert L.bfp_measure_hbm(1 << 20, -1, 1, None, ctypes.byref(g), None, None) == -6
+    assert L.bfp_measure_hbm(1 << 20, 4, 1, None, ctypes.byref(g), None, None, None) == -6    # no mode 4
+    assert L.bfp_measure_hbm(1 << 20, -1, 1, None, ctypes.byref(g), None, None, None) == -6
 
 
 def test_launch_table_roundtrip(tmp_path):

@@ -88,7 +88,10 @@ def test_measure_hbm_modes_are_plausible():
     for mode in ("read", "write", "copy", "read2_write1"):
         r = bfp.bfp_measure_hbm(1 << 30, mode, 3)
         assert 1000.0 < r["GB/s"] < 8000.0, (mode, r)
-        assert r["grid"] in (1024, 2048, 4096, 8192) and r["in_flight"] in (2, 4, 8)
+        cus = torch.cuda.get_device_properties(0).multi_processor_count
+        assert r["grid"] // cus in (1, 2, 4, 8, 16, 32) and r["grid"] % cus == 0, r
+        assert r["block"] in (256, 512, 1024) and r["in_flight"] in (1, 2, 4, 8), r
+        assert r["block"] == 256 or r["grid"] // cus <= 2, r
     with pytest.raises(bfp.BfpError):
         bfp.bfp_measure_hbm(1 << 30, "copy", 0)
 
