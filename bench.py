@@ -46,9 +46,7 @@ Also printed in the same JSON line:
                 the two separate launches (6 vectors);
   small         the 65,536-element (5,2) workload (launch-latency bound): the
                 fused standard-in/standard-out add, and pack + add + unpack
-                as four launches, microseconds per call, beside the launch
-                floor (back-to-back launches of a kernel that does almost
-                nothing);
+                as four launches, microseconds per call;
   cpu_baseline  the oracle timed on this host on a bounded sample (threads
                 and one thread), with the CPU model.
 """
@@ -296,10 +294,8 @@ def bench_chain(torch, bfp, dev, n, reps):
 def bench_small(torch, bfp, dev, reps=200):
     """65,536 uniform (5,2) patterns without NaN/Inf, add to nearest even:
     the fused kernel and the three-kernel path, `reps` back-to-back calls
-    between two events; beside them the launch floor, the same number of
-    back-to-back launches of the library's one-wave clock kernel with a
-    single iteration (a launch that does almost nothing).  The three are
-    measured in turn, twice, and each reports its lower time."""
+    between two events, each path measured twice in turn and reported by its
+    lower time."""
     from paper_1602_04716_amd import inputs
     s = torch.cuda.current_stream()
     n = 65536
@@ -318,13 +314,10 @@ def bench_small(torch, bfp, dev, reps=200):
         bfp.bfp_add(f, pa, pb, pc, n, s)
         bfp.bfp_unpack(f, pc, c, n, s)
 
-    def floor():
-        bfp.bfp_wave_clock(1, s)
-
     out = {"n": n, "format": "(5,2)"}
     best = {}
     for _round in range(2):
-        for name, fn in (("fused", fused), ("pack_add_unpack", three), ("launch_floor", floor)):
+        for name, fn in (("fused", fused), ("pack_add_unpack", three)):
             for _ in range(10):
                 fn()
             ev0, ev1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
@@ -338,8 +331,6 @@ def bench_small(torch, bfp, dev, reps=200):
     for name in ("fused", "pack_add_unpack"):
         out[name + "_us"] = best[name]
         out[name + "_elements_per_s"] = n / (best[name] * 1e-6)
-    out["launch_floor_us"] = best["launch_floor"]
-    out["fused_above_floor_us"] = best["fused"] - best["launch_floor"]
     return out
 
 
