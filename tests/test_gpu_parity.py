@@ -251,6 +251,29 @@ def test_full_size_2_26(e, m):
     torch.cuda.synchronize()
 
 
+@pytest.mark.parametrize("e,m", [(5, 10), (8, 7)])
+def test_full_size_2_26_toward_zero(e, m):
+    """The benchmark's size and launch configuration (64-element lane words)
+    in round-toward-zero: every op, the first and last 4096 outputs and
+    200,000 sampled ones against the oracle."""
+    n = 1 << 26
+    a = inputs.scaled_normal(e, m, n, 4)
+    b = inputs.scaled_normal(e, m, n, 5)
+    f = bfp.fmt(e, m, bfp.BFP_RZ)
+    pa, pb = bfp.pack(f, _dev(a)), bfp.pack(f, _dev(b))
+    rng = np.random.default_rng(6)
+    idx = np.concatenate([np.arange(4096), np.arange(n - 4096, n), rng.integers(0, n, 200000)])
+    for op in OPS:
+        bfp.bfp_launch_set(op, f, 2, 256, 0)
+        pc = bfp.empty_bitslice(f, n)
+        bfp.bfp_binop(op, f, pa, pb, pc, n)
+        got = _host(bfp.unpack(f, pc, n)).astype(np.uint32)
+        want = oracle.binop(op, e, m, 1, a[idx], b[idx], nthreads=8)
+        assert np.array_equal(got[idx], want), op
+        del pc
+    torch.cuda.synchronize()
+
+
 def test_beyond_32_bit_offsets():
     """n = 2^33 + 77 elements of (5,2) (8 GiB per operand): plane word offsets
     and element offsets exceed 2^32, through pack, add, mul, unpack and the
