@@ -295,7 +295,10 @@ def bench_small(torch, bfp, dev, reps=200):
     """65,536 uniform (5,2) patterns without NaN/Inf, add to nearest even:
     the fused kernel and the three-kernel path, `reps` back-to-back calls
     between two events, each path measured twice in turn and reported by its
-    lower time."""
+    lower time.  The calls are made from Python (each pays the binding's
+    argument marshalling on the host) and, separately, captured once in a
+    graph of `reps` calls and replayed, which leaves only the device's own
+    time per call; every replay's result is compared with the eager one."""
     from paper_1602_04716_amd import inputs
     s = torch.cuda.current_stream()
     n = 65536
@@ -305,32 +308,56 @@ def bench_small(torch, bfp, dev, reps=200):
     c = torch.empty_like(a)
     pa, pb, pc = (bfp.empty_bitslice(f, n, dev) for _ in range(3))
 
-    def fused():
-        bfp.bfp_binop_std("add", f, a, b, c, n, s)
+    def fused(st):
+        bfp.bfp_binop_std("add", f, a, b, c, n, st)
 
-    def three():
-        bfp.bfp_pack(f, a, pa, n, s)
-        bfp.bfp_pack(f, b, pb, n, s)
-        bfp.bfp_add(f, pa, pb, pc, n, s)
-        bfp.bfp_unpack(f, pc, c, n, s)
+    def three(st):
+        bfp.bfp_pack(f, a, pa, n, st)
+        bfp.bfp_pack(f, b, pb, n, st)
+        bfp.bfp_add(f, pa, pb, pc, n, st)
+        bfp.bfp_unpack(f, pc, c, n, st)
+
+    paths = (("fused", fused), ("pack_add_unpack", three))
+    graphs, want = {}, {}
+    for name, fn in paths:
+        fn(s)
+        torch.cuda.synchronize()
+        want[name] = c.clone()
+        cs = torch.cuda.Stream()
+        cs.wait_stream(s)
+        g = torch.cuda.CUDAGraph()
+        with torch.cuda.graph(g, stream=cs):
+            for _ in range(reps):
+                fn(cs)
+        torch.cuda.synchronize()
+        graphs[name] = g
+
+    def timed(run):
+        ev0, ev1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+        ev0.record(s)
+        run()
+        ev1.record(s)
+        torch.cuda.synchronize()
+        return ev0.elapsed_time(ev1) * 1e3 / reps
 
     out = {"n": n, "format": "(5,2)"}
     best = {}
     for _round in range(2):
-        for name, fn in (("fused", fused), ("pack_add_unpack", three)):
+        for name, fn in paths:
             for _ in range(10):
-                fn()
-            ev0, ev1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
-            ev0.record(s)
-            for _ in range(reps):
-                fn()
-            ev1.record(s)
-            torch.cuda.synchronize()
-            us = ev0.elapsed_time(ev1) * 1e3 / reps
+                fn(s)
+            us = timed(lambda: [fn(s) for _ in range(reps)])
             best[name] = min(best.get(name, us), us)
+            c.zero_()
+            us = timed(graphs[name].replay)
+            if not torch.equal(c, want[name]):
+                raise RuntimeError("graph replay of the %s path differs from its eager result" % name)
+            best[name + "_graph"] = min(best.get(name + "_graph", us), us)
     for name in ("fused", "pack_add_unpack"):
         out[name + "_us"] = best[name]
         out[name + "_elements_per_s"] = n / (best[name] * 1e-6)
+        out[name + "_graph_us"] = best[name + "_graph"]
+        out[name + "_graph_elements_per_s"] = n / (best[name + "_graph"] * 1e-6)
     return out
 
 

@@ -113,14 +113,16 @@ __device__ __forceinline__ void mask_padding(WordR<R>* z, uint64_t off, uint64_t
 // load (4, 8 or 16 bytes per lane), U puts independent loads and circuit
 // instances side by side; both trade registers for bytes in flight.  A unit
 // past the end reads the step's first unit again and is not stored.
+// `nb` and `ng` are the block and grid sizes, read by the kernel itself (see
+// k_binop).
 template <int E, int M, bool RZ, int OPC, int R, int U>
 __device__ __forceinline__ void binop_body(const uint32_t* a, const uint32_t* b, uint32_t* c, uint64_t gpad,
-                                           uint64_t n, uint32_t negb) {
+                                           uint64_t n, uint32_t negb, unsigned nb, unsigned ng) {
   constexpr int B = 1 + E + M;
   constexpr int RU = R * U;
   const uint64_t nt = gpad / R;
-  const uint64_t stride = (uint64_t)gridDim.x * blockDim.x;
-  for (uint64_t t = (uint64_t)blockIdx.x * blockDim.x + threadIdx.x; t < nt; t += stride * U) {
+  const uint64_t stride = (uint64_t)ng * nb;
+  for (uint64_t t = (uint64_t)blockIdx.x * nb + threadIdx.x; t < nt; t += stride * U) {
     uint64_t off[U];
     bool ok[U];
 #pragma unroll
@@ -159,10 +161,15 @@ __device__ __forceinline__ void binop_body(const uint32_t* a, const uint32_t* b,
   }
 }
 
+// The launch dimensions are read here, in the kernel, and passed down: read
+// inside the inlined body, the compiler fetched the block size with a vector
+// load from the dispatch's hidden arguments and waited for it before the
+// first operand load; read here they come from a scalar load with the other
+// kernel arguments.
 template <int E, int M, bool RZ, int OPC, int R, int U>
 __global__ void __launch_bounds__(512) k_binop(const uint32_t* a, const uint32_t* b, uint32_t* c,
                                                uint64_t gpad, uint64_t n, uint32_t negb) {
-  binop_body<E, M, RZ, OPC, R, U>(a, b, c, gpad, n, negb);
+  binop_body<E, M, RZ, OPC, R, U>(a, b, c, gpad, n, negb, blockDim.x, gridDim.x);
 }
 
 // Load the 32 R standard elements starting at element e0 (C bytes each) as
@@ -353,14 +360,15 @@ __global__ void __launch_bounds__(512) k_unpack(const uint32_t* planes, uint8_t*
 }
 
 // Fused standard-in / standard-out op: transposes and circuit in registers.
+// `nb` and `ng`: block and grid sizes, read by the kernel (as in k_binop).
 template <int E, int M, bool RZ, int OPC>
 __device__ __forceinline__ void binop_std_body(const uint8_t* a, const uint8_t* b, uint8_t* c, uint64_t n,
-                                               uint32_t negb) {
+                                               uint32_t negb, unsigned nb, unsigned ng) {
   constexpr int B = 1 + E + M;
   constexpr int C = B <= 8 ? 1 : (B <= 16 ? 2 : (B <= 32 ? 4 : 8));
   const uint64_t groups = (n + 31) / 32;
-  const uint64_t stride = (uint64_t)gridDim.x * blockDim.x;
-  for (uint64_t t = (uint64_t)blockIdx.x * blockDim.x + threadIdx.x; t < groups; t += stride) {
+  const uint64_t stride = (uint64_t)ng * nb;
+  for (uint64_t t = (uint64_t)blockIdx.x * nb + threadIdx.x; t < groups; t += stride) {
     uint32_t ia[1][8 * C], ib[1][8 * C];
     load_std<C, 1>(a, t * 32, n, ia);
     load_std<C, 1>(b, t * 32, n, ib);
@@ -386,7 +394,7 @@ __device__ __forceinline__ void binop_std_body(const uint8_t* a, const uint8_t* 
 template <int E, int M, bool RZ, int OPC>
 __global__ void __launch_bounds__(512) k_binop_std(const uint8_t* a, const uint8_t* b, uint8_t* c, uint64_t n,
                                                    uint32_t negb) {
-  binop_std_body<E, M, RZ, OPC>(a, b, c, n, negb);
+  binop_std_body<E, M, RZ, OPC>(a, b, c, n, negb, blockDim.x, gridDim.x);
 }
 
 // The wide formats' fused kernels hold two 64-word operands and their
@@ -399,7 +407,7 @@ __global__ void __launch_bounds__(512) k_binop_std(const uint8_t* a, const uint8
 template <int E, int M, bool RZ, int OPC>
 __global__ void __launch_bounds__(256) k_binop_std_w(const uint8_t* a, const uint8_t* b, uint8_t* c, uint64_t n,
                                                      uint32_t negb) {
-  binop_std_body<E, M, RZ, OPC>(a, b, c, n, negb);
+  binop_std_body<E, M, RZ, OPC>(a, b, c, n, negb, blockDim.x, gridDim.x);
 }
 
 // ---------------------------------------------------------------------------

@@ -194,6 +194,45 @@ def test_plain_add_5_2_workload():
     assert np.array_equal(_host(bfp.unpack(f, pc, n)).astype(np.uint32), want)
 
 
+def test_5_2_workload_captured_in_a_graph():
+    """The fused call and the pack + add + unpack calls captured in one
+    graph (two of each) and replayed three times, with other eager work on
+    the operands' buffers between replays: every replay gives the oracle's
+    result."""
+    e, m = 5, 2
+    n = 65536
+    a = inputs.plain_8bit(n, seed=1)
+    b = inputs.plain_8bit(n, seed=101)
+    want = oracle.binop("add", e, m, 0, a, b)
+    f = bfp.fmt(e, m)
+    _set_wpl("add", f, 1)
+    da, db = _dev(a), _dev(b)
+    dc, dd = torch.empty_like(da), torch.empty_like(da)
+    pa, pb, pc = (bfp.empty_bitslice(f, n) for _ in range(3))
+    bfp.bfp_binop_std("add", f, da, db, dc, n)  # eager once, before the capture
+    bfp.bfp_add(f, pa, pb, pc, n)
+    torch.cuda.synchronize()
+    cs = torch.cuda.Stream()
+    cs.wait_stream(torch.cuda.current_stream())
+    g = torch.cuda.CUDAGraph()
+    with torch.cuda.graph(g, stream=cs):
+        for _ in range(2):
+            bfp.bfp_binop_std("add", f, da, db, dc, n, cs)
+            bfp.bfp_pack(f, da, pa, n, cs)
+            bfp.bfp_pack(f, db, pb, n, cs)
+            bfp.bfp_add(f, pa, pb, pc, n, cs)
+            bfp.bfp_unpack(f, pc, dd, n, cs)
+    for rep in range(3):
+        dc.zero_()
+        dd.fill_(0xFF)
+        pc.zero_()
+        g.replay()
+        assert np.array_equal(_host(dc).astype(np.uint32), want), rep
+        assert np.array_equal(_host(dd).astype(np.uint32), want), rep
+        assert np.array_equal(_host(pc), oracle.pack(e, m, want)), rep
+        bfp.bfp_mul(f, pa, pb, pc, n)  # eager work between replays
+
+
 def test_in_place_and_zero_length():
     e, m = 5, 10
     f = bfp.fmt(e, m)
