@@ -24,7 +24,8 @@ def gpu():
 def _mixed_specs(count, seed):
     rng = np.random.default_rng(seed)
     fmts = inputs.sweep_formats()
-    edge_n = [1, 2, 31, 32, 33, 63, 64, 65, 2047, 2048, 2049, 64 * 32, 64 * 32 + 1, 2048 * 32 + 7, 100000]
+    edge_n = [1, 2, 31, 32, 33, 63, 64, 65, 2047, 2048, 2049, 64 * 32, 64 * 32 + 1, 1024 * 32, 1024 * 32 + 1,
+              2048 * 32 + 7, 100000]
     specs = []
     for i in range(count):
         n = edge_n[i] if i < len(edge_n) else int(np.exp(rng.uniform(0, np.log(120000))))
