@@ -73,6 +73,8 @@ def parse():
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--steps", type=int, default=10)
     ap.add_argument("--warmup", type=int, default=3)
+    ap.add_argument("--settle-ms", type=float, default=100.0,
+                    help="untimed device time of steps run before the warmup steps")
     ap.add_argument("--n-log2", type=int, default=26)
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-batched", action="store_true")
@@ -673,6 +675,21 @@ def main():
             if evs is not None:
                 evs[i][1].record(stream)
 
+    # Settle: the step runs untimed for at least --settle-ms of device time
+    # before the W warmup steps, so the timed steps see the GPU at the clocks
+    # it sustains under this load (after the host's input generation the
+    # device has idled; with 3 warmup steps and no settle period the timed
+    # steps measured 3% slower than after 50).
+    settle_ms = 0.0
+    while settle_ms < args.settle_ms:
+        sa = torch.cuda.Event(enable_timing=True)
+        sb = torch.cuda.Event(enable_timing=True)
+        sa.record(stream)
+        for _ in range(10):
+            step()
+        sb.record(stream)
+        torch.cuda.synchronize()
+        settle_ms += sa.elapsed_time(sb)
     for _ in range(args.warmup):
         step()
     torch.cuda.synchronize()
@@ -804,6 +821,7 @@ def main():
         "n_gpus": 1,
         "steps": args.steps,
         "warmup": args.warmup,
+        "settle_ms": settle_ms,
         "ms_per_step": ms_step,
         "ms_per_step_instrumented": ms_step_instrumented,
         "higher_is_better": True,
