@@ -101,6 +101,22 @@ def parse():
     return ap.parse_args()
 
 
+def settle(torch, fn, stream, ms=50.0):
+    """Run fn back to back, untimed, until `ms` of device time have passed:
+    the measurement that follows then sees the clocks the GPU sustains under
+    that work, not its ramp from the idle stretches in which the host
+    generates inputs."""
+    done = 0.0
+    while done < ms:
+        ea, eb = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+        ea.record(stream)
+        for _ in range(4):
+            fn()
+        eb.record(stream)
+        torch.cuda.synchronize()
+        done += ea.elapsed_time(eb)
+
+
 def bench_batched(torch, bfp, dev, reps, graphs=True):
     """4096 vectors, lengths log-uniform in [1024, 2^20], random format of the
     40-format sweep and random op: one graph launch of the persistent kernel
@@ -239,8 +255,7 @@ def bench_div(torch, bfp, dev, n, reps):
         pa, pb = bfp.pack(f, a), bfp.pack(f, b)
         pc = bfp.empty_bitslice(f, n, dev)
         del a, b
-        for _ in range(2):
-            bfp.bfp_div(f, pa, pb, pc, n, s)
+        settle(torch, lambda: bfp.bfp_div(f, pa, pb, pc, n, s), s)
         ev0, ev1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
         ev0.record(s)
         for _ in range(reps):
@@ -284,8 +299,7 @@ def bench_chain(torch, bfp, dev, n, reps):
 
         res = {}
         for name, fn in (("fused", fused), ("separate", separate)):
-            for _ in range(2):
-                fn()
+            settle(torch, fn, s)
             ev0, ev1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
             ev0.record(s)
             for _ in range(reps):
@@ -359,8 +373,7 @@ def bench_small(torch, bfp, dev, reps=200):
     best = {}
     for _round in range(2):
         for name, fn in paths:
-            for _ in range(10):
-                fn(s)
+            settle(torch, lambda: fn(s), s, ms=20.0)
             us = timed(lambda: [fn(s) for _ in range(reps)])
             best[name] = min(best.get(name, us), us)
             c.zero_()
@@ -388,8 +401,7 @@ def bench_wide(torch, bfp, dev, n, reps):
     pc = bfp.empty_bitslice(f, n, dev)
     out = {}
     for op in ("add", "mul", "div"):
-        for _ in range(2):
-            bfp.bfp_binop(op, f, pa, pb, pc, n, s)
+        settle(torch, lambda: bfp.bfp_binop(op, f, pa, pb, pc, n, s), s)
         ev0, ev1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
         ev0.record(s)
         for _ in range(reps):
@@ -422,8 +434,7 @@ def bench_int(torch, bfp, dev, n, reps):
                   for _ in range(2))
         pc = bfp.int_empty_bitslice(k, n, dev)
         for op, kind in (("add", "wrap"), ("mul", "wrap"), ("mul", "sats")):
-            for _ in range(2):
-                bfp.bfp_int_binop(op, k, kind, pa, pb, pc, n, s)
+            settle(torch, lambda: bfp.bfp_int_binop(op, k, kind, pa, pb, pc, n, s), s)
             ev0, ev1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
             ev0.record(s)
             for _ in range(reps):
