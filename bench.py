@@ -107,7 +107,9 @@ def settle(torch, fn, stream, ms=50.0):
     that work, not its ramp from the idle stretches in which the host
     generates inputs."""
     done = 0.0
-    while done < ms:
+    for _ in range(100000):  # bounded, in case fn does no device work
+        if done >= ms:
+            break
         ea, eb = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
         ea.record(stream)
         for _ in range(4):
@@ -692,7 +694,9 @@ def main():
     # device has idled; with 3 warmup steps and no settle period the timed
     # steps measured 3% slower than after 50).
     settle_ms = 0.0
-    while settle_ms < args.settle_ms:
+    for _ in range(100000):  # bounded: each pass is 10 steps of device work
+        if settle_ms >= args.settle_ms:
+            break
         sa = torch.cuda.Event(enable_timing=True)
         sb = torch.cuda.Event(enable_timing=True)
         sa.record(stream)
