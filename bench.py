@@ -349,19 +349,24 @@ def bench_small(torch, bfp, dev, reps=200):
         bfp.bfp_unpack(f, pc, c, n, st)
 
     paths = (("fused", fused), ("pack_add_unpack", three))
-    graphs, want = {}, {}
+    graphs, want, graph_error = {}, {}, None
     for name, fn in paths:
         fn(s)
         torch.cuda.synchronize()
         want[name] = c.clone()
-        cs = torch.cuda.Stream()
-        cs.wait_stream(s)
-        g = torch.cuda.CUDAGraph()
-        with torch.cuda.graph(g, stream=cs):
-            for _ in range(reps):
-                fn(cs)
-        torch.cuda.synchronize()
-        graphs[name] = g
+        try:
+            cs = torch.cuda.Stream()
+            cs.wait_stream(s)
+            g = torch.cuda.CUDAGraph()
+            with torch.cuda.graph(g, stream=cs):
+                for _ in range(reps):
+                    fn(cs)
+            torch.cuda.synchronize()
+            graphs[name] = g
+        except RuntimeError as exc:  # the eager figures stand without the graph ones
+            graph_error = "capture of the %s path failed: %s" % (name, exc)
+            graphs.clear()
+            break
 
     def timed(run):
         ev0, ev1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
@@ -378,16 +383,23 @@ def bench_small(torch, bfp, dev, reps=200):
             settle(torch, lambda: fn(s), s, ms=20.0)
             us = timed(lambda: [fn(s) for _ in range(reps)])
             best[name] = min(best.get(name, us), us)
+            if name not in graphs:
+                continue
             c.zero_()
             us = timed(graphs[name].replay)
             if not torch.equal(c, want[name]):
-                raise RuntimeError("graph replay of the %s path differs from its eager result" % name)
+                graph_error = "graph replay of the %s path differs from its eager result" % name
+                graphs.clear()
+                continue
             best[name + "_graph"] = min(best.get(name + "_graph", us), us)
     for name in ("fused", "pack_add_unpack"):
         out[name + "_us"] = best[name]
         out[name + "_elements_per_s"] = n / (best[name] * 1e-6)
-        out[name + "_graph_us"] = best[name + "_graph"]
-        out[name + "_graph_elements_per_s"] = n / (best[name + "_graph"] * 1e-6)
+        if graph_error is None:
+            out[name + "_graph_us"] = best[name + "_graph"]
+            out[name + "_graph_elements_per_s"] = n / (best[name + "_graph"] * 1e-6)
+    if graph_error is not None:
+        out["graph_error"] = graph_error
     return out
 
 
