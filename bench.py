@@ -868,26 +868,36 @@ def main():
                                  if x in v}
                     for k, v in kernels.items()},
     }
+    def section(name, fn, *a, **kw):
+        """A secondary section that raises is recorded with its error (and
+        its traceback on stderr) so the headline line is still printed."""
+        try:
+            res[name] = fn(*a, **kw)
+        except Exception as exc:  # noqa: BLE001
+            import traceback
+            traceback.print_exc()
+            res[name] = {"error": "%s: %s" % (type(exc).__name__, exc)}
+
     if not args.no_sweep:
-        res["sweep"] = bench_sweep(torch, bfp, dev, args.sweep_n_log2)
+        section("sweep", bench_sweep, torch, bfp, dev, args.sweep_n_log2)
     if not args.no_layout_methods:
-        res["layout_methods"] = bench_layout_methods(torch, bfp, dev, n)
+        section("layout_methods", bench_layout_methods, torch, bfp, dev, n)
     if not args.no_batched:
-        res["batched"] = bench_batched(torch, bfp, dev, args.batched_reps, graphs=not args.batched_no_graph)
+        section("batched", bench_batched, torch, bfp, dev, args.batched_reps, graphs=not args.batched_no_graph)
     if not args.no_serving:
-        res["serving"] = bench_serving(torch, bfp, dev, args.serving_requests)
+        section("serving", bench_serving, torch, bfp, dev, args.serving_requests)
     if not args.no_div:
-        res["div"] = bench_div(torch, bfp, dev, n, args.div_reps)
+        section("div", bench_div, torch, bfp, dev, n, args.div_reps)
     if not args.no_chain:
-        res["chain"] = bench_chain(torch, bfp, dev, n, args.div_reps)
+        section("chain", bench_chain, torch, bfp, dev, n, args.div_reps)
     if not args.no_int:
-        res["int"] = bench_int(torch, bfp, dev, n, args.div_reps)
+        section("int", bench_int, torch, bfp, dev, n, args.div_reps)
     if not args.no_wide:
-        res["wide"] = bench_wide(torch, bfp, dev, n, args.div_reps)
+        section("wide", bench_wide, torch, bfp, dev, n, args.div_reps)
     if not args.no_small:
-        res["small"] = bench_small(torch, bfp, dev)
+        section("small", bench_small, torch, bfp, dev)
     if not args.no_cpu_baseline:
-        res["cpu_baseline"] = cpu_baseline()
+        section("cpu_baseline", cpu_baseline)
     print(json.dumps(res), flush=True)
     return 0
 
